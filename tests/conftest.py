@@ -1,0 +1,25 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: long-running CPU test")
+
+
+def pytest_collection_modifyitems(config, items):
+    # GPU tests that find no GPU fail loudly instead of skipping; CPU runs select
+    # them out with -m "not gpu".
+    pass
+
+
+@pytest.fixture(scope="session")
+def oracle_lib():
+    from oracle import hamiltonian
+    return hamiltonian.lib()
