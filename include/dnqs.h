@@ -1,0 +1,188 @@
+/*
+ * dnqs.h -- C ABI of the MI355X (gfx950) hot path of the deterministic neural-network
+ * quantum-state method for quantum chemistry (arXiv 2601.21310):
+ *
+ *   Slater-Condon matrix elements between bit-string determinants -> H_SS (CSR)
+ *   neural backflow amplitude psi(x) = det A(x)                       (Eqs. 2-4)
+ *   variational energy E = psi^T H_SS psi / psi^T psi and its gradient (Eqs. 11-12)
+ *   Epstein-Nesbet PT2 correction over the connected set             (Eq. 13)
+ *
+ * Conventions
+ *   Determinant: two uint64 words {alpha, beta}; bit p = spatial orbital p; M <= 64.
+ *   Spin-orbital index: alpha p -> p, beta p -> M + p.  |x> = a+_{i1}...a+_{iN}|0>
+ *   with i1 < ... < iN; a_k and a+_k carry (-1)^(occupied spin-orbitals below k).
+ *   Determinant arrays are uint64[n][2], sorted ascending on (alpha, beta) as unsigned
+ *   integers ("canonical order") and free of duplicates.
+ *   Integrals: h[p*M+q] and eri[((p*M+q)*M+r)*M+s] = (pq|rs) (chemists' notation),
+ *   real, with 8-fold symmetry; FP64 host arrays.
+ *   Network: widths w[0] = 2M (occupation bits, spin-orbital order), w[1..L-1]
+ *   hidden (tanh), w[L] = 2M * N_e (linear).  DeltaPhi[p][k] = o[p*N_e + k].
+ *   theta (FP32, device) packs [W1 b1 W2 b2 ... WL bL Phi0]; W_l is row-major
+ *   w[l-1] x w[l]; Phi0 is row-major 2M x N_e.  Gradients use the same packing.
+ *
+ * Pointers
+ *   "dev" = device memory of the context's device, "host" = host memory.  The caller
+ *   owns every pointer it passes; the library never frees them and never keeps them
+ *   past the call, except where a call says otherwise.  The library owns the context
+ *   and connection objects and the device memory behind them.
+ *
+ * Streams and synchronisation
+ *   Work is enqueued on the context's stream (dnqs_create / dnqs_set_stream).
+ *   dnqs_amplitudes and dnqs_energy_and_grad enqueue and return without waiting;
+ *   results that feed later calls (E, norms) stay in device memory.
+ *   dnqs_set_integrals, dnqs_build_connections and dnqs_pt2 synchronise the stream
+ *   (they size buffers from results computed on the device).
+ *
+ * Errors
+ *   Every call returns a dnqs_status.  Arguments are validated on the host before
+ *   any launch; on a non-zero status nothing was enqueued by that call unless the
+ *   status is DNQS_EHIP.  dnqs_last_error() gives a message for the last failure on
+ *   a context.  No C++ exception crosses this boundary.
+ */
+#ifndef DNQS_H
+#define DNQS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dnqs_ctx dnqs_ctx;   /* device, stream, integral slots, workspaces */
+typedef struct dnqs_conn dnqs_conn; /* a variational set S with its H_SS */
+
+typedef enum {
+    DNQS_OK = 0,
+    DNQS_EINVAL = -1,    /* bad argument (size, pointer, sector, ordering) */
+    DNQS_ENOMEM = -2,    /* device allocation failed */
+    DNQS_EHIP = -3,      /* a HIP runtime call failed */
+    DNQS_ECAPACITY = -4, /* a fixed-capacity structure would overflow */
+    DNQS_ESTATE = -5,    /* call out of order (e.g. no integrals in the slot) */
+    DNQS_EDOMAIN = -6    /* numerical domain error (psi^T psi == 0) */
+} dnqs_status;
+
+typedef enum {
+    DNQS_FP32 = 0,  /* every network GEMM in FP32 on MFMA */
+    DNQS_MIXED = 1  /* hidden-layer GEMMs in BF16 on MFMA with FP32 accumulation;
+                       embedding, output layer and LU in FP32; reductions in FP64 */
+} dnqs_precision;
+
+#define DNQS_MAX_LAYERS 8
+#define DNQS_MAX_SLOTS 128
+
+/* Network shape: n_layers linear maps, width[0..n_layers]. */
+typedef struct {
+    int n_layers;
+    int width[DNQS_MAX_LAYERS + 1];
+} dnqs_net;
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device`, enqueuing on `stream` (a hipStream_t;
+ * NULL = the null stream).  *out receives the context. */
+dnqs_status dnqs_create(dnqs_ctx **out, int device, void *stream);
+void dnqs_destroy(dnqs_ctx *ctx);
+dnqs_status dnqs_set_stream(dnqs_ctx *ctx, void *stream);
+/* Message for the last failure on ctx (static storage owned by ctx); "" if none.
+ * With ctx == NULL, the message of the last dnqs_create failure. */
+const char *dnqs_last_error(const dnqs_ctx *ctx);
+
+/* Number of FP32 entries of theta (and of the gradient) for a network on a system
+ * with M spatial orbitals and n_alpha + n_beta electrons; -1 if the shape is invalid. */
+int64_t dnqs_param_count(const dnqs_net *net, int M, int n_alpha, int n_beta);
+
+/* ------------------------------------------------------------------ integrals
+ * Stage the Hamiltonian of one geometry into `slot` (0 <= slot < DNQS_MAX_SLOTS):
+ * the one- and two-electron integrals the paper reads from an FCIDUMP (Algorithm 1
+ * input; Sec. 3.3).  h: host FP64 [M*M]; eri: host FP64 [M^4]; e_core adds to every
+ * diagonal element.  1 <= M <= 64, 0 <= n_alpha, n_beta <= M, n_alpha+n_beta >= 1.
+ * The library keeps device copies (FP64 and FP32 tables); the host arrays may be
+ * freed after the call.  Synchronises the stream. */
+dnqs_status dnqs_set_integrals(dnqs_ctx *ctx, int slot, int M, int n_alpha, int n_beta, const double *h,
+                               const double *eri, double e_core);
+
+/* ------------------------------------------------------------------ connections
+ * Build H_SS for the variational set S = dets (dev uint64[n][2], canonical order,
+ * unique, every det in the slot's (n_alpha, n_beta) sector), using the integrals of
+ * `slot`.  H_SS[x][y] = <x|H|y> by the Slater-Condon rules; the off-diagonal pattern
+ * is every pair of S at excitation rank 1 or 2 (the connected set of Eq. 1 read as
+ * excitation rank <= 2, restricted to S).  The result keeps:
+ *   row_ptr int64[n+1], col int32[nnz] (ascending within each row), val FP32[nnz]
+ *   (off-diagonal only), diag FP64[n], a copy of S, and a device hash set of S.
+ * flags: DNQS_VALIDATE checks ordering, uniqueness and sector on the device first
+ * (DNQS_EINVAL on failure).  *out receives a new object owned by the caller through
+ * dnqs_conn_free.  1 <= n < 2^31.  Synchronises the stream. */
+#define DNQS_VALIDATE 1u
+dnqs_status dnqs_build_connections(dnqs_ctx *ctx, int slot, const uint64_t *dets, int64_t n, unsigned flags,
+                                   dnqs_conn **out);
+/* n_dets, nnz (off-diagonal) of a connection object (host outputs, either may be NULL). */
+dnqs_status dnqs_conn_info(const dnqs_conn *conn, int64_t *n_dets, int64_t *nnz);
+/* Copy H_SS into caller buffers (dev): row_ptr[n+1], col[nnz], val[nnz], diag[n];
+ * any pointer may be NULL to skip it.  Enqueued on the context's stream. */
+dnqs_status dnqs_conn_export(dnqs_ctx *ctx, const dnqs_conn *conn, int64_t *row_ptr, int32_t *col, float *val,
+                             double *diag);
+void dnqs_conn_free(dnqs_conn *conn);
+
+/* ------------------------------------------------------------------ amplitudes
+ * log|psi(x)| (dev FP64[n]) and sign(psi(x)) (dev int8[n], -1/0/+1) for each det of
+ * `dets` (dev uint64[n][2], any order, in the slot's sector), with
+ * psi(x) = det A(x), A(x)[j][k] = Phi0[i_j][k] + DeltaPhi(x)[i_j][k] (Eqs. 2-4).
+ * An exactly singular A(x) gives sign 0 and log|psi| = -inf.  n >= 1. */
+dnqs_status dnqs_amplitudes(dnqs_ctx *ctx, int slot, const dnqs_net *net, const float *theta, const uint64_t *dets,
+                            int64_t n, int precision, double *log_abs, int8_t *sign);
+
+/* ------------------------------------------------------------------ energy and gradient
+ * One variational step's worth of work on S = conn's determinants (Eqs. 11-12):
+ *   psi_x = sign_x exp(log|psi_x| - l_max)                (global scale removed)
+ *   v = H_SS psi,  E = psi^T v / psi^T psi                 (FP64 reductions)
+ *   grad = dE/dtheta = (2/psi^T psi) sum_x (v_x - E psi_x) d psi_x/d theta
+ * Outputs (dev): energy FP64[1]; stats FP64[3] = {psi^T psi, l_max, psi^T v};
+ * grad FP32[param_count] (NULL: no backward pass); v_out FP64[n] (NULL: not kept);
+ * log_abs FP64[n] and sign int8[n] (NULL: not kept).  E is NaN and the call still
+ * succeeds if psi^T psi underflows; grad is then zero.  Enqueued, does not wait. */
+dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, const float *theta,
+                                 const dnqs_conn *conn, int precision, unsigned flags, double *energy,
+                                 double *stats, float *grad, double *v_out, double *log_abs, int8_t *sign);
+
+/* ------------------------------------------------------------------ PT2
+ * Epstein-Nesbet correction of Eq. 13 for psi on S = conn's determinants, given
+ * as (log_abs, sign) (dev, any global scale) and E (dev FP64[1]):
+ *   dE = ( sum_{a in S} (v_a - E psi_a)^2 / (E - H_aa)
+ *        + sum_{a in P} w_a^2 / (E - H_aa) ) / psi^T psi,
+ *   v = H_SS psi, w_a = sum_{x in S} H_ax psi_x, P = C(S) \ S (unscreened).
+ * A term whose numerator is exactly 0 contributes 0.
+ * out (dev FP64[4]) = {dE, internal sum, external sum (both unnormalised), min|E-H_aa|}
+ * counts (dev int64[4]) = {(x,a) pairs generated, |P|, terms with |E-H_aa| < 1e-8,
+ *                          hash-table passes used}.
+ * opts may be NULL.  With opts->sample_mask != 0 only keys a whose
+ * SplitMix64-based key hash h(a) = mix(alpha ^ mix(beta)) has (h & sample_mask) == 0
+ * enter the external sum and |P| (the internal sum is always complete).  With
+ * opts->export_cap > 0 up to export_cap kept keys are written to export_keys
+ * (dev uint64[cap][2]) with export_w (w_a, for psi scaled so that max_x |psi_x| = 1)
+ * and export_haa (H_aa) (dev FP64[cap]), and the number of kept keys to export_count
+ * (dev int64[1]; may exceed export_cap).  Synchronises the stream. */
+typedef struct {
+    uint64_t sample_mask;
+    int64_t export_cap;
+    uint64_t *export_keys;
+    double *export_w;
+    double *export_haa;
+    int64_t *export_count;
+} dnqs_pt2_opts;
+dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const double *log_abs, const int8_t *sign,
+                     const double *energy, const dnqs_pt2_opts *opts, double *out, int64_t *counts);
+
+/* ------------------------------------------------------------------ timing
+ * Average device time (ms) of the most recent launches of the named kernel family
+ * recorded with HIP events on the context's stream since dnqs_timing_reset, and the
+ * number of launches; families: "hss", "amp", "egrad", "pt2_gen", "pt2".  Timing is
+ * recorded only after dnqs_timing_enable(ctx, 1). */
+dnqs_status dnqs_timing_enable(dnqs_ctx *ctx, int on);
+dnqs_status dnqs_timing_reset(dnqs_ctx *ctx);
+dnqs_status dnqs_timing_get(dnqs_ctx *ctx, const char *family, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DNQS_H */

@@ -13,3 +13,13 @@ def lowest(H) -> tuple:
     H = np.asarray(H.todense() if hasattr(H, "todense") else H, dtype=np.float64)
     w, V = np.linalg.eigh(H)
     return float(w[0]), V[:, 0].copy()
+
+
+def lowest_sparse(H, tol: float = 1e-13) -> tuple:
+    """(lowest eigenvalue, eigenvector) of a sparse symmetric matrix (scipy eigsh,
+    Lanczos); dense eigh below 2000 rows."""
+    import scipy.sparse.linalg as sla
+    if H.shape[0] < 2000:
+        return lowest(H)
+    w, V = sla.eigsh(H, k=1, which="SA", tol=tol)
+    return float(w[0]), V[:, 0].copy()

@@ -1,0 +1,297 @@
+"""ctypes binding of libdnqs.so (the C ABI in include/dnqs.h).
+
+Argument marshalling only: every step of the hot path runs in the library's HIP
+kernels.  PyTorch provides device memory and the stream.  There is no fallback: if
+the library is not built, or no gfx950 GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdnqs.so")
+
+MAX_LAYERS = 8
+FP32, MIXED = 0, 1
+VALIDATE = 1
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ECAPACITY", -5: "ESTATE", -6: "EDOMAIN"}
+
+
+class DnqsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"dnqs {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Net(C.Structure):
+    _fields_ = [("n_layers", C.c_int), ("width", C.c_int * (MAX_LAYERS + 1))]
+
+    @classmethod
+    def from_widths(cls, widths):
+        w = list(widths)
+        if not 3 <= len(w) <= MAX_LAYERS + 1:
+            raise ValueError("need between 3 and 9 widths (2 to 8 layers)")
+        net = cls()
+        net.n_layers = len(w) - 1
+        for i, v in enumerate(w):
+            net.width[i] = int(v)
+        return net
+
+
+class PT2Opts(C.Structure):
+    _fields_ = [("sample_mask", C.c_uint64), ("export_cap", C.c_int64), ("export_keys", C.c_void_p),
+                ("export_w", C.c_void_p), ("export_haa", C.c_void_p), ("export_count", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libdnqs.so; raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                              "python paper_2601_21310_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32, u64, dbl = C.c_void_p, C.c_int64, C.c_int, C.c_uint64, C.c_double
+        L.dnqs_create.argtypes = [C.POINTER(vp), i32, vp]
+        L.dnqs_destroy.argtypes = [vp]
+        L.dnqs_destroy.restype = None
+        L.dnqs_set_stream.argtypes = [vp, vp]
+        L.dnqs_last_error.argtypes = [vp]
+        L.dnqs_last_error.restype = C.c_char_p
+        L.dnqs_param_count.argtypes = [C.POINTER(Net), i32, i32, i32]
+        L.dnqs_param_count.restype = i64
+        L.dnqs_set_integrals.argtypes = [vp, i32, i32, i32, i32, vp, vp, dbl]
+        L.dnqs_build_connections.argtypes = [vp, i32, vp, i64, C.c_uint, C.POINTER(vp)]
+        L.dnqs_conn_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
+        L.dnqs_conn_export.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.dnqs_conn_free.argtypes = [vp]
+        L.dnqs_conn_free.restype = None
+        L.dnqs_amplitudes.argtypes = [vp, i32, C.POINTER(Net), vp, vp, i64, i32, vp, vp]
+        L.dnqs_energy_and_grad.argtypes = [vp, i32, C.POINTER(Net), vp, vp, i32, C.c_uint, vp, vp, vp, vp, vp, vp]
+        L.dnqs_pt2.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(PT2Opts), vp, vp]
+        L.dnqs_timing_enable.argtypes = [vp, i32]
+        L.dnqs_timing_reset.argtypes = [vp]
+        L.dnqs_timing_get.argtypes = [vp, C.c_char_p, C.POINTER(dbl), C.POINTER(i64)]
+        for fn in ("dnqs_create", "dnqs_set_stream", "dnqs_set_integrals", "dnqs_build_connections",
+                   "dnqs_conn_info", "dnqs_conn_export", "dnqs_amplitudes", "dnqs_energy_and_grad", "dnqs_pt2",
+                   "dnqs_timing_enable", "dnqs_timing_reset", "dnqs_timing_get"):
+            getattr(L, fn).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _dev_tensor(t, dtype, name, device):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda" or t.device.index != device:
+        raise ValueError(f"{name} must live on cuda:{device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+class Connections:
+    """H_SS of a variational set (library-owned device memory)."""
+
+    def __init__(self, ctx, handle, slot, dets):
+        self._ctx = ctx
+        self.handle = handle
+        self.slot = slot
+        self.dets = dets
+        n, nnz = C.c_int64(), C.c_int64()
+        lib().dnqs_conn_info(handle, C.byref(n), C.byref(nnz))
+        self.n, self.nnz = n.value, nnz.value
+
+    def export(self):
+        """(row_ptr int64, col int32, val float32, diag float64) as CUDA tensors."""
+        dev = self._ctx.device
+        row_ptr = torch.empty(self.n + 1, dtype=torch.int64, device=f"cuda:{dev}")
+        col = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=f"cuda:{dev}")
+        val = torch.empty(max(self.nnz, 1), dtype=torch.float32, device=f"cuda:{dev}")
+        diag = torch.empty(self.n, dtype=torch.float64, device=f"cuda:{dev}")
+        self._ctx._check(lib().dnqs_conn_export(self._ctx.handle, self.handle, _ptr(row_ptr), _ptr(col),
+                                                 _ptr(val), _ptr(diag)))
+        torch.cuda.current_stream(dev).synchronize()
+        return row_ptr, col[: self.nnz], val[: self.nnz], diag
+
+    def free(self):
+        if self.handle:
+            lib().dnqs_conn_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Context:
+    """One library context on one GPU, enqueuing on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the dnqs library runs only on gfx950 GPUs")
+        self.device = device
+        h = C.c_void_p()
+        stream = torch.cuda.current_stream(device).cuda_stream
+        st = lib().dnqs_create(C.byref(h), device, C.c_void_p(stream))
+        if st != 0:
+            raise DnqsError(st, lib().dnqs_last_error(None).decode())
+        self.handle = h
+        self._slots = {}
+
+    def _check(self, st):
+        if st != 0:
+            raise DnqsError(st, lib().dnqs_last_error(self.handle).decode())
+
+    def sync_stream(self):
+        """Point the context at torch's current stream."""
+        self._check(lib().dnqs_set_stream(self.handle, C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().dnqs_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- calls
+    def set_integrals(self, h, eri, e_core, n_alpha, n_beta, slot=0):
+        h = np.ascontiguousarray(h, dtype=np.float64)
+        eri = np.ascontiguousarray(eri, dtype=np.float64)
+        M = h.shape[0]
+        if h.shape != (M, M) or eri.shape != (M, M, M, M):
+            raise ValueError("h must be [M,M] and eri [M,M,M,M]")
+        self._check(lib().dnqs_set_integrals(self.handle, slot, M, n_alpha, n_beta, h.ctypes.data_as(C.c_void_p),
+                                              eri.ctypes.data_as(C.c_void_p), float(e_core)))
+        self._slots[slot] = (M, n_alpha, n_beta)
+
+    def shape(self, slot=0):
+        return self._slots[slot]
+
+    def build_connections(self, dets, slot=0, validate=True) -> Connections:
+        dets = _dev_tensor(dets, torch.int64, "dets", self.device)
+        n = dets.shape[0]
+        h = C.c_void_p()
+        self._check(lib().dnqs_build_connections(self.handle, slot, _ptr(dets), n, VALIDATE if validate else 0,
+                                                 C.byref(h)))
+        return Connections(self, h, slot, dets)
+
+    def param_count(self, widths, slot=0):
+        M, na, nb = self._slots[slot]
+        return int(lib().dnqs_param_count(C.byref(Net.from_widths(widths)), M, na, nb))
+
+    def amplitudes(self, widths, theta, dets, slot=0, precision=FP32):
+        theta = _dev_tensor(theta, torch.float32, "theta", self.device)
+        dets = _dev_tensor(dets, torch.int64, "dets", self.device)
+        if theta.numel() != self.param_count(widths, slot):
+            raise ValueError("theta has the wrong size for this network")
+        n = dets.shape[0]
+        la = torch.empty(n, dtype=torch.float64, device=dets.device)
+        sg = torch.empty(n, dtype=torch.int8, device=dets.device)
+        net = Net.from_widths(widths)
+        self._check(lib().dnqs_amplitudes(self.handle, slot, C.byref(net), _ptr(theta), _ptr(dets), n, precision,
+                                          _ptr(la), _ptr(sg)))
+        return la, sg
+
+    def energy_and_grad(self, widths, theta, conn: Connections, want_grad=True, precision=FP32, keep=True):
+        theta = _dev_tensor(theta, torch.float32, "theta", self.device)
+        if theta.numel() != self.param_count(widths, conn.slot):
+            raise ValueError("theta has the wrong size for this network")
+        dev = theta.device
+        n = conn.n
+        E = torch.empty(1, dtype=torch.float64, device=dev)
+        stats = torch.empty(3, dtype=torch.float64, device=dev)
+        grad = torch.empty_like(theta) if want_grad else None
+        v = torch.empty(n, dtype=torch.float64, device=dev) if keep else None
+        la = torch.empty(n, dtype=torch.float64, device=dev) if keep else None
+        sg = torch.empty(n, dtype=torch.int8, device=dev) if keep else None
+        net = Net.from_widths(widths)
+        self._check(lib().dnqs_energy_and_grad(self.handle, conn.slot, C.byref(net), _ptr(theta), conn.handle,
+                                               precision, 0, _ptr(E), _ptr(stats), _ptr(grad), _ptr(v), _ptr(la),
+                                               _ptr(sg)))
+        return {"E": E, "stats": stats, "grad": grad, "v": v, "logabs": la, "sign": sg}
+
+    def pt2(self, conn: Connections, logabs, sign, energy, sample_mask=0, export_cap=0):
+        dev = energy.device
+        logabs = _dev_tensor(logabs, torch.float64, "logabs", self.device)
+        sign = _dev_tensor(sign, torch.int8, "sign", self.device)
+        energy = _dev_tensor(energy, torch.float64, "energy", self.device)
+        out = torch.empty(4, dtype=torch.float64, device=dev)
+        counts = torch.empty(4, dtype=torch.int64, device=dev)
+        opts = PT2Opts()
+        opts.sample_mask = int(sample_mask)
+        ex = None
+        if export_cap > 0:
+            ex = {"keys": torch.empty((export_cap, 2), dtype=torch.int64, device=dev),
+                  "w": torch.empty(export_cap, dtype=torch.float64, device=dev),
+                  "haa": torch.empty(export_cap, dtype=torch.float64, device=dev),
+                  "count": torch.zeros(1, dtype=torch.int64, device=dev)}
+            opts.export_cap = export_cap
+            opts.export_keys = ex["keys"].data_ptr()
+            opts.export_w = ex["w"].data_ptr()
+            opts.export_haa = ex["haa"].data_ptr()
+            opts.export_count = ex["count"].data_ptr()
+        self._check(lib().dnqs_pt2(self.handle, conn.slot, conn.handle, _ptr(logabs), _ptr(sign), _ptr(energy),
+                                   C.byref(opts), _ptr(out), _ptr(counts)))
+        res = {"out": out, "counts": counts}
+        if ex is not None:
+            res["export"] = ex
+        return res
+
+    # -------------------------------------------------------------- timing
+    def timing(self, on=True):
+        self._check(lib().dnqs_timing_enable(self.handle, 1 if on else 0))
+
+    def timing_reset(self):
+        self._check(lib().dnqs_timing_reset(self.handle))
+
+    def timing_get(self, family):
+        ms, k = C.c_double(), C.c_int64()
+        self._check(lib().dnqs_timing_get(self.handle, family.encode(), C.byref(ms), C.byref(k)))
+        return ms.value, k.value
+
+
+def dets_to_device(dets_np, device=0):
+    """uint64[n,2] numpy -> int64 CUDA tensor with the same bits."""
+    a = np.ascontiguousarray(np.asarray(dets_np, dtype=np.uint64).reshape(-1, 2)).view(np.int64)
+    return torch.from_numpy(a.copy()).to(f"cuda:{device}")
+
+
+def dets_to_host(dets_t):
+    return dets_t.detach().cpu().numpy().view(np.uint64).reshape(-1, 2)
+
+
+class DetNQSEnergy(torch.autograd.Function):
+    """E(theta) of Eq. 11 with the library's adjoint (Eq. 12) as its backward."""
+
+    @staticmethod
+    def forward(ctx, theta, dctx: Context, widths, conn: Connections, precision=FP32):
+        res = dctx.energy_and_grad(widths, theta.detach().contiguous(), conn, want_grad=True, precision=precision,
+                                   keep=False)
+        ctx.save_for_backward(res["grad"])
+        return res["E"][0]
+
+    @staticmethod
+    def backward(ctx, gE):
+        (grad,) = ctx.saved_tensors
+        return (gE.to(grad.dtype) * grad, None, None, None, None)

@@ -1,0 +1,464 @@
+// Network kernels for the neural backflow amplitude (Eqs. 2-4) and its adjoint.
+//
+//   k_embed     h1 = tanh(b1 + sum_{p in occ(x)} W1[p,:])      (layer 1 on 0/1 input)
+//   k_gemm_f32  C = epi(A B) on MFMA v_mfma_f32_32x32x2f32, 128x128 tiles, fused
+//               epilogues: +bias, tanh(+bias), *(1 - h^2); split-K for weight grads
+//   k_orb_lu    A(x) = Phi0[occ] + O[x, occ] -> Gauss-Jordan with partial pivoting,
+//               row per lane, log|det| in FP64, sign, and A^-1 for the adjoint
+//   k_det_bwd   dL/dO[x, p*Ne+k] = c_x (A_x^-T)[j,k] for p = i_j, 0 elsewhere,
+//               c_x = 2 (v_x - E psi_x) psi_x / psi^T psi            (Eq. 12)
+#include "dnqs_device.h"
+#include "dnqs_kernels.h"
+
+namespace dnqs {
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ embedding
+constexpr int kEmbedCfg = 4;  // configurations per workgroup
+
+__global__ __launch_bounds__(256) void k_embed(const uint64_t *__restrict__ dets, int64_t n, int M, int d1,
+                                               const float *__restrict__ W1, const float *__restrict__ b1,
+                                               float *__restrict__ h1, float *__restrict__ U) {
+    const int No = 2 * M;
+    for (int i = 0; i < kEmbedCfg; ++i) {
+        const int64_t x = (int64_t)blockIdx.x * kEmbedCfg + i;
+        if (x >= n) return;
+        const uint64_t a = dets[2 * x], b = dets[2 * x + 1];
+        for (int c = threadIdx.x; c < d1; c += blockDim.x) {
+            float s = b1[c];
+            uint64_t t = a;
+            while (t) {
+                int p = ctz64(t);
+                t &= t - 1;
+                s += W1[(size_t)p * d1 + c];
+            }
+            t = b;
+            while (t) {
+                int p = ctz64(t);
+                t &= t - 1;
+                s += W1[(size_t)(M + p) * d1 + c];
+            }
+            h1[x * d1 + c] = tanhf(s);
+        }
+        if (U) {
+            for (int p = threadIdx.x; p < No; p += blockDim.x) {
+                uint64_t w = p < M ? a : b;
+                int q = p < M ? p : p - M;
+                U[x * No + p] = (float)((w >> q) & 1ull);
+            }
+        }
+    }
+}
+
+void launch_embed(hipStream_t st, const uint64_t *dets, int64_t n, int M, int d1, const float *W1, const float *b1,
+                  float *h1, float *U) {
+    hipLaunchKernelGGL(k_embed, dim3((unsigned)((n + kEmbedCfg - 1) / kEmbedCfg)), dim3(256), 0, st, dets, n, M,
+                       d1, W1, b1, h1, U);
+}
+
+// ------------------------------------------------------------------ FP32 MFMA GEMM
+constexpr int BM = 128, BN = 128, BK = 16;
+constexpr int LDS_A = BM + 4, LDS_B = BN + 4;
+
+// Workgroups are dispatched round-robin over the 8 XCDs.  Remap the linear id so that
+// consecutive logical tiles (which share an A row-tile) land on the same XCD and hit
+// its L2.
+__device__ __forceinline__ int xcd_remap(int L, int total) {
+    const int nx = 8;
+    int full = (total / nx) * nx;
+    if (L >= full) return L;
+    int per = total / nx;
+    return (L % nx) * per + (L / nx);
+}
+
+template <bool A_KCONTIG>
+__device__ __forceinline__ void load_a_tile(const GemmArgs &g, int m0, int k0, int kend, float (&r)[8]) {
+    const int t = threadIdx.x;
+    const int mload = g.ones_row >= 0 ? g.ones_row : g.M;
+    if (A_KCONTIG) {  // A[m*lda + k]; thread: one m, 8 consecutive k
+        const int m = m0 + (t >> 1), k = k0 + (t & 1) * 8;
+        const float *p = g.A + (int64_t)m * g.lda + k;
+        const bool full = m < mload && k + 8 <= kend && ((g.lda & 3) == 0) && ((((uintptr_t)p) & 15) == 0);
+        if (full) {
+            v4f u = *(const v4f *)p, w = *(const v4f *)(p + 4);
+            r[0] = u[0]; r[1] = u[1]; r[2] = u[2]; r[3] = u[3];
+            r[4] = w[0]; r[5] = w[1]; r[6] = w[2]; r[7] = w[3];
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) r[j] = (m < mload && k + j < kend) ? p[j] : 0.0f;
+        }
+        if (m == g.ones_row) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) r[j] = (k + j < kend) ? 1.0f : 0.0f;
+        }
+    } else {  // A[k*lda + m]; thread: one k, 8 consecutive m
+        const int k = k0 + (t >> 4), m = m0 + (t & 15) * 8;
+        const float *p = g.A + (int64_t)k * g.lda + m;
+        const bool full = k < kend && m + 8 <= mload && ((g.lda & 3) == 0) && ((((uintptr_t)p) & 15) == 0);
+        if (full) {
+            v4f u = *(const v4f *)p, w = *(const v4f *)(p + 4);
+            r[0] = u[0]; r[1] = u[1]; r[2] = u[2]; r[3] = u[3];
+            r[4] = w[0]; r[5] = w[1]; r[6] = w[2]; r[7] = w[3];
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) r[j] = (k < kend && m + j < mload) ? p[j] : 0.0f;
+        }
+        if (g.ones_row >= 0) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (m + j == g.ones_row) r[j] = k < kend ? 1.0f : 0.0f;
+        }
+    }
+}
+
+template <bool A_KCONTIG>
+__device__ __forceinline__ void store_a_tile(float (*As)[LDS_A], const float (&r)[8]) {
+    const int t = threadIdx.x;
+    if (A_KCONTIG) {
+        const int m = t >> 1, k = (t & 1) * 8;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) As[k + j][m] = r[j];
+    } else {
+        const int k = t >> 4, m = (t & 15) * 8;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) As[k][m + j] = r[j];
+    }
+}
+
+template <bool B_NCONTIG>
+__device__ __forceinline__ void load_b_tile(const GemmArgs &g, int n0, int k0, int kend, float (&r)[8]) {
+    const int t = threadIdx.x;
+    if (B_NCONTIG) {  // B[k*ldb + n]
+        const int k = k0 + (t >> 4), n = n0 + (t & 15) * 8;
+        const float *p = g.B + (int64_t)k * g.ldb + n;
+        const bool full = k < kend && n + 8 <= g.N && ((g.ldb & 3) == 0) && ((((uintptr_t)p) & 15) == 0);
+        if (full) {
+            v4f u = *(const v4f *)p, w = *(const v4f *)(p + 4);
+            r[0] = u[0]; r[1] = u[1]; r[2] = u[2]; r[3] = u[3];
+            r[4] = w[0]; r[5] = w[1]; r[6] = w[2]; r[7] = w[3];
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) r[j] = (k < kend && n + j < g.N) ? p[j] : 0.0f;
+        }
+    } else {  // B[n*ldb + k]
+        const int n = n0 + (t >> 1), k = k0 + (t & 1) * 8;
+        const float *p = g.B + (int64_t)n * g.ldb + k;
+        const bool full = n < g.N && k + 8 <= kend && ((g.ldb & 3) == 0) && ((((uintptr_t)p) & 15) == 0);
+        if (full) {
+            v4f u = *(const v4f *)p, w = *(const v4f *)(p + 4);
+            r[0] = u[0]; r[1] = u[1]; r[2] = u[2]; r[3] = u[3];
+            r[4] = w[0]; r[5] = w[1]; r[6] = w[2]; r[7] = w[3];
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) r[j] = (n < g.N && k + j < kend) ? p[j] : 0.0f;
+        }
+    }
+}
+
+template <bool B_NCONTIG>
+__device__ __forceinline__ void store_b_tile(float (*Bs)[LDS_B], const float (&r)[8]) {
+    const int t = threadIdx.x;
+    if (B_NCONTIG) {
+        const int k = t >> 4, n = (t & 15) * 8;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) Bs[k][n + j] = r[j];
+    } else {
+        const int n = t >> 1, k = (t & 1) * 8;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) Bs[k + j][n] = r[j];
+    }
+}
+
+template <bool A_KCONTIG, bool B_NCONTIG, int EPI>
+__global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g) {
+    __shared__ float As[BK][LDS_A];
+    __shared__ float Bs[BK][LDS_B];
+    const int tiles_n = (g.N + BN - 1) / BN;
+    const int tiles_m = (g.M + BM - 1) / BM;
+    const int L = xcd_remap(blockIdx.x, tiles_n * tiles_m);
+    const int m0 = (L / tiles_n) * BM, n0 = (L % tiles_n) * BN;
+    const int kbeg = blockIdx.z * g.k_chunk;
+    int kend = kbeg + g.k_chunk;
+    if (kend > g.K) kend = g.K;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int li = lane & 31, lk = lane >> 5;
+
+    v16f acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+    float ra[8], rb[8];
+    if (kbeg < kend) {
+        load_a_tile<A_KCONTIG>(g, m0, kbeg, kend, ra);
+        load_b_tile<B_NCONTIG>(g, n0, kbeg, kend, rb);
+    }
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+        __syncthreads();
+        store_a_tile<A_KCONTIG>(As, ra);
+        store_b_tile<B_NCONTIG>(Bs, rb);
+        __syncthreads();
+        if (k0 + BK < kend) {
+            load_a_tile<A_KCONTIG>(g, m0, k0 + BK, kend, ra);
+            load_b_tile<B_NCONTIG>(g, n0, k0 + BK, kend, rb);
+        }
+#pragma unroll
+        for (int kk = 0; kk < BK / 2; ++kk) {
+            float a0 = As[2 * kk + lk][wm + li];
+            float a1 = As[2 * kk + lk][wm + 32 + li];
+            float b0 = Bs[2 * kk + lk][wn + li];
+            float b1 = Bs[2 * kk + lk][wn + 32 + li];
+            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+        }
+    }
+    float *C = g.C + (int64_t)blockIdx.z * g.c_split_stride;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = n0 + wn + j * 32 + li;
+            if (col >= g.N) continue;
+            float bias = (EPI == EPI_BIAS || EPI == EPI_BIAS_TANH) ? g.bias[col] : 0.0f;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * lk + (r & 3);
+                if (row >= g.M) continue;
+                float v = acc[i][j][r];
+                if (EPI == EPI_BIAS) v += bias;
+                if (EPI == EPI_BIAS_TANH) v = tanhf(v + bias);
+                if (EPI == EPI_DTANH) {
+                    float hv = g.act[(int64_t)row * g.ldact + col];
+                    v *= (1.0f - hv * hv);
+                }
+                C[(int64_t)row * g.ldc + col] = v;
+            }
+        }
+}
+
+template <bool AK, bool BN_, int EPI>
+static void launch_gemm_t(hipStream_t st, const GemmArgs &g, int splits) {
+    int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
+    hipLaunchKernelGGL((k_gemm_f32<AK, BN_, EPI>), dim3(tiles, 1, splits), dim3(256), 0, st, g);
+}
+
+void launch_gemm_f32(hipStream_t st, const GemmArgs &g0, bool a_kcontig, bool b_ncontig, int epi, int splits) {
+    GemmArgs g = g0;
+    if (splits < 1) splits = 1;
+    int chunk = (g.K + splits - 1) / splits;
+    chunk = (chunk + BK - 1) / BK * BK;
+    g.k_chunk = chunk > 0 ? chunk : BK;
+#define DISPATCH(AK, BNC)                                                     \
+    switch (epi) {                                                            \
+        case EPI_STORE: launch_gemm_t<AK, BNC, EPI_STORE>(st, g, splits); break; \
+        case EPI_BIAS: launch_gemm_t<AK, BNC, EPI_BIAS>(st, g, splits); break;   \
+        case EPI_BIAS_TANH: launch_gemm_t<AK, BNC, EPI_BIAS_TANH>(st, g, splits); break; \
+        case EPI_DTANH: launch_gemm_t<AK, BNC, EPI_DTANH>(st, g, splits); break; \
+    }
+    if (a_kcontig && b_ncontig) { DISPATCH(true, true) }
+    else if (a_kcontig && !b_ncontig) { DISPATCH(true, false) }
+    else if (!a_kcontig && b_ncontig) { DISPATCH(false, true) }
+    else { DISPATCH(false, false) }
+#undef DISPATCH
+}
+
+// out[i] = sum_z part[z*count + i], fixed order
+__global__ void k_reduce_splits(const float *__restrict__ part, int splits, int64_t count, float *__restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < count; i += stride) {
+        float s = 0.0f;
+        for (int z = 0; z < splits; ++z) s += part[(int64_t)z * count + i];
+        out[i] = s;
+    }
+}
+
+void launch_reduce_splits(hipStream_t st, const float *part, int splits, int64_t count, float *out) {
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)blocks), dim3(256), 0, st, part, splits, count, out);
+}
+
+// ------------------------------------------------------------------ orbital rows + LU
+// spin-orbital index of the r-th occupied spin-orbital (ascending), alpha block first
+__device__ __forceinline__ int occupied_so(uint64_t a, uint64_t b, int M, int na, int r) {
+    uint64_t s = r < na ? a : b;
+    int k = r < na ? r : r - na;
+    for (int i = 0; i < k; ++i) s &= s - 1;
+    int p = ctz64(s);
+    return r < na ? p : M + p;
+}
+
+// G lanes per configuration; lane r of a group holds row r of [A | I].
+template <int G>
+__global__ __launch_bounds__(256) void k_orb_lu(const uint64_t *__restrict__ dets, int64_t n, int M, int na, int nb,
+                                                const float *__restrict__ O, const float *__restrict__ Phi0,
+                                                double *__restrict__ logabs, int8_t *__restrict__ sign,
+                                                float *__restrict__ Ainv) {
+    const int Ne = na + nb, No = 2 * M;
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t x = gt / G;
+    const int r = (int)(gt % G);
+    const bool live = x < n;
+    const bool row_live = live && r < Ne;
+    float a[G], inv[G];
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+        a[c] = 0.0f;
+        inv[c] = (c == r && row_live) ? 1.0f : 0.0f;
+    }
+    if (row_live) {
+        const uint64_t da = dets[2 * x], db = dets[2 * x + 1];
+        const int p = occupied_so(da, db, M, na, r);
+        const float *orow = O + x * (int64_t)(No * Ne) + (int64_t)p * Ne;
+        const float *prow = Phi0 + (int64_t)p * Ne;
+#pragma unroll
+        for (int c = 0; c < G; ++c)
+            if (c < Ne) a[c] = prow[c] + orow[c];
+    }
+    double lsum = 0.0;
+    int sgn = 1;
+    bool singular = false;
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+        if (k >= Ne) continue;  // uniform; keeps the loop fully unrolled
+        // partial pivoting: largest |a[k]| among rows >= k, lowest row on ties
+        float cand = (r >= k && r < Ne) ? fabsf(a[k]) : -1.0f;
+        int ci = r;
+#pragma unroll
+        for (int o = G / 2; o >= 1; o >>= 1) {
+            float oc = __shfl_xor(cand, o, G);
+            int oi = __shfl_xor(ci, o, G);
+            if (oc > cand || (oc == cand && oi < ci)) {
+                cand = oc;
+                ci = oi;
+            }
+        }
+        const int piv = ci;
+        if (piv != k) sgn = -sgn;
+        const int src = (r == k) ? piv : ((r == piv) ? k : r);
+#pragma unroll
+        for (int c = 0; c < G; ++c) {
+            a[c] = __shfl(a[c], src, G);
+            inv[c] = __shfl(inv[c], src, G);
+        }
+        float pa[G], pi[G];
+#pragma unroll
+        for (int c = 0; c < G; ++c) {
+            pa[c] = __shfl(a[c], k, G);
+            pi[c] = __shfl(inv[c], k, G);
+        }
+        float d = pa[k];
+        if (d == 0.0f) {
+            singular = true;
+            d = 1.0f;
+        } else {
+            lsum += log(fabs((double)d));
+            if (d < 0.0f) sgn = -sgn;
+        }
+        const float rd = 1.0f / d;
+        if (r == k) {
+#pragma unroll
+            for (int c = 0; c < G; ++c) {
+                a[c] = pa[c] * rd;
+                inv[c] = pi[c] * rd;
+            }
+        } else {
+            const float f = a[k] * rd;
+#pragma unroll
+            for (int c = 0; c < G; ++c) {
+                a[c] = fmaf(-f, pa[c], a[c]);
+                inv[c] = fmaf(-f, pi[c], inv[c]);
+            }
+        }
+    }
+    if (live && r == 0) {
+        logabs[x] = singular ? -INFINITY : lsum;
+        sign[x] = singular ? (int8_t)0 : (int8_t)sgn;
+    }
+    if (Ainv && row_live) {
+        float *out = Ainv + x * (int64_t)(Ne * Ne) + (int64_t)r * Ne;
+#pragma unroll
+        for (int c = 0; c < G; ++c)
+            if (c < Ne) out[c] = singular ? 0.0f : inv[c];
+    }
+}
+
+int orb_lu_group(int ne) { return ne <= 8 ? 8 : ne <= 16 ? 16 : ne <= 32 ? 32 : 0; }
+
+void launch_orb_lu(hipStream_t st, const uint64_t *dets, int64_t n, int M, int na, int nb, const float *O,
+                   const float *Phi0, double *logabs, int8_t *sign, float *Ainv) {
+    const int G = orb_lu_group(na + nb);
+    const int64_t threads = n * G;
+    const unsigned blocks = (unsigned)((threads + 255) / 256);
+    if (G == 8)
+        hipLaunchKernelGGL(k_orb_lu<8>, dim3(blocks), dim3(256), 0, st, dets, n, M, na, nb, O, Phi0, logabs, sign,
+                           Ainv);
+    else if (G == 16)
+        hipLaunchKernelGGL(k_orb_lu<16>, dim3(blocks), dim3(256), 0, st, dets, n, M, na, nb, O, Phi0, logabs, sign,
+                           Ainv);
+    else
+        hipLaunchKernelGGL(k_orb_lu<32>, dim3(blocks), dim3(256), 0, st, dets, n, M, na, nb, O, Phi0, logabs, sign,
+                           Ainv);
+}
+
+// ------------------------------------------------------------------ det backward + scatter
+// dO[x][p*Ne+k] = c_x * Ainv_x[k][j] if p = i_j is occupied, else 0
+constexpr int kBwdCfg = 4;
+
+__global__ __launch_bounds__(256) void k_det_bwd(const uint64_t *__restrict__ dets, int64_t n, int M, int na,
+                                                 int nb, const double *__restrict__ psi,
+                                                 const double *__restrict__ v, const double *__restrict__ energy,
+                                                 const double *__restrict__ stats, const float *__restrict__ Ainv,
+                                                 float *__restrict__ dO) {
+    const int Ne = na + nb, No = 2 * M;
+    const int width = No * Ne;
+    const double E = energy[0], norm = stats[0];
+    const bool ok = norm > 0.0 && isfinite(E);
+    for (int i = 0; i < kBwdCfg; ++i) {
+        const int64_t x = (int64_t)blockIdx.x * kBwdCfg + i;
+        if (x >= n) return;
+        const uint64_t a = dets[2 * x], b = dets[2 * x + 1];
+        const double px = psi[x];
+        const float c = ok ? (float)(2.0 * (v[x] - E * px) * px / norm) : 0.0f;
+        const float *ai = Ainv + x * (int64_t)(Ne * Ne);
+        for (int t = threadIdx.x; t < width; t += blockDim.x) {
+            const int p = t / Ne, k = t % Ne;
+            float out = 0.0f;
+            const uint64_t s = p < M ? a : b;
+            const int q = p < M ? p : p - M;
+            if ((s >> q) & 1ull) {
+                const int j = (p < M ? 0 : na) + popc64(s & ((1ull << q) - 1ull));
+                out = c * ai[k * Ne + j];
+            }
+            dO[x * width + t] = out;
+        }
+    }
+}
+
+void launch_det_bwd(hipStream_t st, const uint64_t *dets, int64_t n, int M, int na, int nb, const double *psi,
+                    const double *v, const double *energy, const double *stats, const float *Ainv, float *dO) {
+    hipLaunchKernelGGL(k_det_bwd, dim3((unsigned)((n + kBwdCfg - 1) / kBwdCfg)), dim3(256), 0, st, dets, n, M, na,
+                       nb, psi, v, energy, stats, Ainv, dO);
+}
+
+// y[i] = x[i]
+__global__ void k_copy_f32(const float *__restrict__ x, float *__restrict__ y, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = x[i];
+}
+
+void launch_copy_f32(hipStream_t st, const float *x, float *y, int64_t n) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_copy_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, y, n);
+}
+
+}  // namespace dnqs
