@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--out-scale", type=float, default=1.0)
     ap.add_argument("--cpu-sample", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="only run a device copy of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the multi-GPU sharding is a "
@@ -88,6 +90,17 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_MiB": args.copy_calibration, "launches": 5}))
+        return
 
     import paper_2601_21310_amd as dnqs
     import synth
@@ -124,21 +137,21 @@ def main():
         print(f"[bench] step {i}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    fam = {f: ctx.timing_get(f) for f in ("hss", "egrad", "pt2", "pt2_gen")}
+    fam = {f: ctx.timing_get(f) for f in ("hss", "egrad", "pt2", "pt2_l1", "pt2_l1_fill", "pt2_l2", "pt2_reduce")}
     ctx.timing(False)
     ms_step = (t1 - t0) * 1e3 / args.steps
     t_h = fam["hss"][0] / max(fam["hss"][1], 1)
     t_e = fam["egrad"][0] / max(fam["egrad"][1], 1)
     t_p = fam["pt2"][0] / max(fam["pt2"][1], 1)
-    t_g = fam["pt2_gen"][0] / max(fam["pt2_gen"][1], 1)
+    avg = {k: v[0] / max(v[1], 1) for k, v in fam.items()}
     E = res["E"].item()
     o = out["out"].cpu().numpy()
     c = out["counts"].cpu().numpy()
     pairs = int(c[0])
-    # dominant kernel: PT2 generation + reduce-by-key; algorithmic bytes per pair:
-    # 16 B key + 4 B value written and read back once = 40 B (group-by model)
+    # PT2 traffic model: an 8-byte descriptor per (x, a) pair is written by L1, read
+    # twice and written once by L2, and read by the reduce: 40 B/pair over the phase.
     pt2_bytes = 40.0 * pairs
-    achieved = pt2_bytes / (t_g * 1e-3) / 1e9
+    achieved = pt2_bytes / (t_p * 1e-3) / 1e9
     line = {
         "metric": "amps+grads/s and H/PT2 elements/s at |S|=1e5; mixed vs FP32 at 1e-5 Ha",
         "value": n / (t_e * 1e-3),
@@ -151,13 +164,15 @@ def main():
         "config": {"workload": wl.name, "M": wl.M, "n_alpha": wl.n_alpha, "n_beta": wl.n_beta, "n_dets": n,
                    "widths": list(wl.widths), "precision": args.precision, "out_scale": args.out_scale},
         "phases": {
-            "build_connections_ms": t_h, "energy_and_grad_ms": t_e, "pt2_ms": t_p, "pt2_gen_ms": t_g,
+            "build_connections_ms": t_h, "energy_and_grad_ms": t_e, "pt2_ms": t_p,
+            "pt2_l1_ms": avg["pt2_l1"], "pt2_l1_fill_ms": avg["pt2_l1_fill"], "pt2_l2_ms": avg["pt2_l2"],
+            "pt2_reduce_ms": avg["pt2_reduce"],
             "h_elements_per_s": n * (nexc + 1) / (t_h * 1e-3), "h_nnz": nnz,
             "pt2_pairs_per_s": pairs / (t_p * 1e-3), "pt2_pairs": pairs, "pt2_unique_P": int(c[1]),
-            "pt2_passes": int(c[3]),
+            "pt2_sub_buckets": int(c[3]),
         },
         "results": {"E": E, "dE_pt2": float(o[0]), "E_total": E + float(o[0]), "min_denominator": float(o[3])},
-        "roofline": {"kernel": "k_pt2_gen", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": {"kernel": "pt2 (L1 + L2 + reduce)", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": pt2_bytes},
     }

@@ -151,10 +151,10 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
  *   dE = ( sum_{a in S} (v_a - E psi_a)^2 / (E - H_aa)
  *        + sum_{a in P} w_a^2 / (E - H_aa) ) / psi^T psi,
  *   v = H_SS psi, w_a = sum_{x in S} H_ax psi_x, P = C(S) \ S (unscreened).
- * A term whose numerator is exactly 0 contributes 0.
+ * A term whose numerator is exactly 0 contributes 0.  |S| <= 2^24 (DNQS_EINVAL otherwise).
  * out (dev FP64[4]) = {dE, internal sum, external sum (both unnormalised), min|E-H_aa|}
  * counts (dev int64[4]) = {(x,a) pairs generated, |P|, terms with |E-H_aa| < 1e-8,
- *                          hash-table passes used}.
+ *                          sub-buckets of the on-chip reduction}.
  * opts may be NULL.  With opts->sample_mask != 0 only keys a whose
  * SplitMix64-based key hash h(a) = mix(alpha ^ mix(beta)) has (h & sample_mask) == 0
  * enter the external sum and |P| (the internal sum is always complete).  With
@@ -176,7 +176,8 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
 /* ------------------------------------------------------------------ timing
  * Average device time (ms) of the most recent launches of the named kernel family
  * recorded with HIP events on the context's stream since dnqs_timing_reset, and the
- * number of launches; families: "hss", "amp", "egrad", "pt2_gen", "pt2".  Timing is
+ * number of launches; families: "hss", "amp", "egrad", "pt2", "pt2_l1",
+ * "pt2_l1_fill", "pt2_l2", "pt2_reduce".  Timing is
  * recorded only after dnqs_timing_enable(ctx, 1). */
 dnqs_status dnqs_timing_enable(dnqs_ctx *ctx, int on);
 dnqs_status dnqs_timing_reset(dnqs_ctx *ctx);

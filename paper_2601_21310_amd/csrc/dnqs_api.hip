@@ -22,7 +22,7 @@ struct Slot {
     bool set = false;
     int M = 0, na = 0, nb = 0;
     double ecore = 0.0;
-    double *h64 = nullptr, *eri64 = nullptr, *J = nullptr, *K = nullptr;
+    double *h64 = nullptr, *eri64 = nullptr, *J = nullptr, *K = nullptr, *eri_pk = nullptr;
     float *eri32 = nullptr;
 };
 
@@ -175,6 +175,7 @@ Ham make_ham(const Slot &s) {
     H.h64 = s.h64;
     H.eri64 = s.eri64;
     H.eri32 = s.eri32;
+    H.eri_pk = s.eri_pk;
     H.J = s.J;
     H.K = s.K;
     return H;
@@ -345,6 +346,7 @@ void dnqs_destroy(dnqs_ctx *ctx) {
         (void)hipFree(s.h64);
         (void)hipFree(s.eri64);
         (void)hipFree(s.eri32);
+        (void)hipFree(s.eri_pk);
         (void)hipFree(s.J);
         (void)hipFree(s.K);
     }
@@ -388,6 +390,7 @@ dnqs_status dnqs_set_integrals(dnqs_ctx *ctx, int slot, int M, int n_alpha, int 
         (void)hipFree(s.h64);
         (void)hipFree(s.eri64);
         (void)hipFree(s.eri32);
+        (void)hipFree(s.eri_pk);
         (void)hipFree(s.J);
         (void)hipFree(s.K);
         s = Slot();
@@ -398,9 +401,11 @@ dnqs_status dnqs_set_integrals(dnqs_ctx *ctx, int slot, int M, int n_alpha, int 
     HIPCHK(ctx, hipMalloc(&s.eri32, m4 * sizeof(float)));
     HIPCHK(ctx, hipMalloc(&s.J, m2 * sizeof(double)));
     HIPCHK(ctx, hipMalloc(&s.K, m2 * sizeof(double)));
+    HIPCHK(ctx, hipMalloc(&s.eri_pk, packed_eri_size(M) * sizeof(double)));
     HIPCHK(ctx, hipMemcpyAsync(s.h64, h, m2 * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(s.eri64, eri, m4 * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
     launch_stage_integrals(ctx->stream, M, s.eri64, s.eri32, s.J, s.K);
+    launch_pack_eri(ctx->stream, M, s.eri64, s.eri_pk);
     CHECK_LAUNCH(ctx);
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     s.M = M;
@@ -659,6 +664,9 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
     if (opts) o = *opts;
     if (o.export_cap > 0 && (!o.export_keys || !o.export_w || !o.export_haa || !o.export_count))
         return fail(ctx, DNQS_EINVAL, "export buffers missing");
+    if (conn->n > pt2_max_dets())
+        return fail(ctx, DNQS_EINVAL, "pt2 supports |S| <= %d (24-bit determinant index in a pair descriptor)",
+                    pt2_max_dets());
     TRY(set_device(ctx));
     hipStream_t st = ctx->stream;
     const int64_t n = conn->n;
@@ -680,23 +688,7 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
     launch_pt2_internal(st, psi, v, conn->diag, n, energy, part, acc);
     launch_pt2_init_acc(st, acc + 4);
     CHECK_LAUNCH(ctx);
-    if (o.export_cap > 0) HIPCHK(ctx, hipMemsetAsync(o.export_count, 0, sizeof(int64_t), st));
-    // table sizing: unique keys <= pairs; start from pairs/4 and grow on overflow
-    const int64_t nexc = n_excitations(sl.M, sl.na, sl.nb);
-    const int64_t pairs = n * nexc;
-    const bool packed = sl.M <= 32 && !(sl.M == 32 && sl.na == 32 && sl.nb == 32);
-    const size_t slot_bytes = packed ? sizeof(Slot16) : sizeof(Slot32);
-    size_t free_b = 0, total_b = 0;
-    HIPCHK(ctx, hipMemGetInfo(&free_b, &total_b));
-    const size_t budget = free_b / 3;
-    uint64_t max_cap = 1;
-    while (max_cap * 2 * slot_bytes <= budget && max_cap < (1ull << 33)) max_cap <<= 1;
-    uint64_t cap = 1 << 12;
-    while (cap < (uint64_t)(pairs / 4) && cap < max_cap) cap <<= 1;
-    int npass = 1;
-    unsigned long long *n_unique = nullptr;
     int *overflow = nullptr;
-    TRY(ws_t(ctx, "pt2_nuniq", 1, &n_unique));
     TRY(ws_t(ctx, "pt2_ovf", 1, &overflow));
     DetSet S;
     S.keys = conn->set_keys;
@@ -708,43 +700,127 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
     ex.w = o.export_w;
     ex.haa = o.export_haa;
     ex.count = o.export_count;
+    // external sum: partitioned reduce-by-key (k_pt2_part.hip)
+    const int64_t nexc = n_excitations(sl.M, sl.na, sl.nb);
+    const int64_t pairs = n * nexc;
+    const bool packed = sl.M <= 32 && !(sl.M == 32 && sl.na == 32 && sl.nb == 32);
+    // sub-buckets of ~6000 pairs: ~2k unique keys at the measured 3.4 pairs per key,
+    // half of the 4096-slot LDS table
+    const int64_t nsb_target = std::max<int64_t>(1, pairs / 6000);
+    int s1 = 0;
+    while (((int64_t)1 << s1) < nsb_target && (1 << s1) < pt2_max_k1()) ++s1;
+    int s2 = 0;
+    while (((int64_t)1 << (s1 + s2)) < nsb_target && (1 << s2) < pt2_max_k2()) ++s2;
+    const int K1 = 1 << s1;
+    const int64_t nwg = pt2_l1_groups(n);
+    uint32_t *c1 = nullptr;
+    int32_t *c1t = nullptr;
+    int64_t *offs1 = nullptr, *bsum = nullptr, *tot = nullptr, *bstart_d = nullptr;
+    TRY(ws_t(ctx, "pt2_c1", (size_t)nwg * K1, &c1));
+    TRY(ws_t(ctx, "pt2_c1t", (size_t)nwg * K1, &c1t));
+    TRY(ws_t(ctx, "pt2_offs1", (size_t)nwg * K1, &offs1));
+    TRY(ws_t(ctx, "pt2_bsum", (size_t)scan_blocks(nwg * K1) + 1, &bsum));
+    TRY(ws_t(ctx, "pt2_tot", 2, &tot));
+    TRY(ws_t(ctx, "pt2_bstart", (size_t)K1 + 1, &bstart_d));
+    Timer t1(ctx, "pt2_l1");
+    launch_pt2_l1(st, H, conn->dets, n, psi, s1, nwg, c1, nullptr, nullptr, false, packed);
+    CHECK_LAUNCH(ctx);
+    launch_transpose_u32(st, c1, nwg, K1, c1t);
+    launch_exclusive_scan(st, c1t, nwg * K1, offs1, bsum, tot);
+    CHECK_LAUNCH(ctx);
+    int64_t total1 = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&total1, tot, sizeof total1, hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    uint64_t *desc1 = nullptr;
+    TRY(ws_t(ctx, "pt2_desc1", (size_t)std::max<int64_t>(total1, 1), &desc1));
+    Timer t1f(ctx, "pt2_l1_fill");
+    launch_pt2_l1(st, H, conn->dets, n, psi, s1, nwg, nullptr, offs1, desc1, true, packed);
+    CHECK_LAUNCH(ctx);
+    t1f.stop();
+    t1.stop();
+    launch_gather_starts(st, offs1, K1, nwg, tot, bstart_d);
+    CHECK_LAUNCH(ctx);
+    std::vector<int64_t> bstart(K1 + 1);
+    HIPCHK(ctx, hipMemcpyAsync(bstart.data(), bstart_d, sizeof(int64_t) * (K1 + 1), hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    int64_t nsb_used = 0;
     for (int attempt = 0;; ++attempt) {
-        if (attempt > 24) return fail(ctx, DNQS_ECAPACITY, "PT2 table did not fit after %d attempts", attempt);
-        void *slots = nullptr;
-        TRY(ws_get(ctx, "pt2_table", cap * slot_bytes, &slots));
-        PT2Table T;
-        T.slots = slots;
-        T.mask = cap - 1;
-        T.n_unique = n_unique;
-        T.overflow = overflow;
-        bool ok = true;
+        const int K2 = 1 << s2;
+        const uint64_t *desc = desc1;
+        const int64_t *sb = bstart_d;
+        int64_t nsb = K1;
+        if (s2 > 0) {
+            const int64_t CH = 65536;
+            std::vector<PT2Chunk> chunks;
+            std::vector<int64_t> bcb0(K1), bnc(K1);
+            for (int b = 0; b < K1; ++b) {
+                const int64_t size = bstart[b + 1] - bstart[b];
+                const int64_t nc = (size + CH - 1) / CH;
+                bcb0[b] = (int64_t)chunks.size();
+                bnc[b] = nc;
+                for (int64_t c = 0; c < nc; ++c)
+                    chunks.push_back({bstart[b] + c * CH, std::min(CH, size - c * CH), bcb0[b], nc});
+            }
+            const int64_t nchunk = (int64_t)chunks.size();
+            PT2Chunk *chunks_d = nullptr;
+            int64_t *bcb0_d = nullptr, *bnc_d = nullptr, *offs2 = nullptr, *bsum2 = nullptr, *sb_d = nullptr;
+            uint32_t *c2 = nullptr;
+            int32_t *c2t = nullptr;
+            uint64_t *desc2 = nullptr;
+            TRY(ws_t(ctx, "pt2_chunks", (size_t)std::max<int64_t>(nchunk, 1), &chunks_d));
+            TRY(ws_t(ctx, "pt2_bcb0", (size_t)K1, &bcb0_d));
+            TRY(ws_t(ctx, "pt2_bnc", (size_t)K1, &bnc_d));
+            TRY(ws_t(ctx, "pt2_c2", (size_t)std::max<int64_t>(nchunk * K2, 1), &c2));
+            TRY(ws_t(ctx, "pt2_c2t", (size_t)std::max<int64_t>(nchunk * K2, 1), &c2t));
+            TRY(ws_t(ctx, "pt2_offs2", (size_t)std::max<int64_t>(nchunk * K2, 1), &offs2));
+            TRY(ws_t(ctx, "pt2_bsum2", (size_t)scan_blocks(nchunk * K2) + 1, &bsum2));
+            TRY(ws_t(ctx, "pt2_sb", (size_t)K1 * K2 + 1, &sb_d));
+            TRY(ws_t(ctx, "pt2_desc2", (size_t)std::max<int64_t>(total1, 1), &desc2));
+            if (nchunk > 0)
+                HIPCHK(ctx, hipMemcpyAsync(chunks_d, chunks.data(), sizeof(PT2Chunk) * nchunk, hipMemcpyHostToDevice, st));
+            HIPCHK(ctx, hipMemcpyAsync(bcb0_d, bcb0.data(), sizeof(int64_t) * K1, hipMemcpyHostToDevice, st));
+            HIPCHK(ctx, hipMemcpyAsync(bnc_d, bnc.data(), sizeof(int64_t) * K1, hipMemcpyHostToDevice, st));
+            Timer t2(ctx, "pt2_l2");
+            if (nchunk > 0) {
+                launch_pt2_l2(st, desc1, chunks_d, nchunk, s2, c2, nullptr, nullptr, false);
+                CHECK_LAUNCH(ctx);
+                launch_l2_transpose(st, c2, chunks_d, nchunk, K2, c2t);
+                launch_exclusive_scan(st, c2t, nchunk * K2, offs2, bsum2, tot + 1);
+                CHECK_LAUNCH(ctx);
+                launch_pt2_l2(st, desc1, chunks_d, nchunk, s2, nullptr, offs2, desc2, true);
+                CHECK_LAUNCH(ctx);
+            }
+            launch_sub_starts(st, offs2, bstart_d, bcb0_d, bnc_d, K1, K2, sb_d);
+            CHECK_LAUNCH(ctx);
+            t2.stop();
+            // the host vectors are read by the copies above: wait before they go out of scope
+            HIPCHK(ctx, hipStreamSynchronize(st));
+            desc = desc2;
+            sb = sb_d;
+            nsb = (int64_t)K1 * K2;
+        }
+        double *part_r = nullptr;
+        TRY(ws_t(ctx, "pt2_part_r", (size_t)nsb * 4, &part_r));
         launch_pt2_init_acc(st, acc + 4);
         if (o.export_cap > 0) HIPCHK(ctx, hipMemsetAsync(o.export_count, 0, sizeof(int64_t), st));
-        for (int pass = 0; pass < npass && ok; ++pass) {
-            launch_pt2_clear(st, T, packed);
-            Timer tg(ctx, "pt2_gen");
-            launch_pt2_gen(st, H, conn->dets, n, psi, npass, pass, T, packed);
-            tg.stop();
-            CHECK_LAUNCH(ctx);
-            unsigned long long nu = 0;
-            int ov = 0;
-            HIPCHK(ctx, hipMemcpyAsync(&nu, n_unique, sizeof nu, hipMemcpyDeviceToHost, st));
-            HIPCHK(ctx, hipMemcpyAsync(&ov, overflow, sizeof ov, hipMemcpyDeviceToHost, st));
-            HIPCHK(ctx, hipStreamSynchronize(st));
-            if (ov || nu > (cap / 4) * 3) {
-                ok = false;
-                break;
-            }
-            launch_pt2_finalize(st, H, T, packed, S, energy, o.sample_mask, ex, part, acc + 4);
-            CHECK_LAUNCH(ctx);
-        }
-        if (ok) break;
-        if (cap < max_cap)
-            cap <<= 1;
-        else
-            npass *= 2;
+        HIPCHK(ctx, hipMemsetAsync(overflow, 0, sizeof(int), st));
+        Timer tr(ctx, "pt2_reduce");
+        launch_pt2_reduce(st, H, conn->dets, psi, desc, sb, nsb, S, energy, o.sample_mask, ex, part_r, overflow,
+                          packed);
+        CHECK_LAUNCH(ctx);
+        tr.stop();
+        launch_pt2_accumulate(st, part_r, nsb, acc + 4);
+        CHECK_LAUNCH(ctx);
+        int ov = 0;
+        HIPCHK(ctx, hipMemcpyAsync(&ov, overflow, sizeof ov, hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));
+        nsb_used = nsb;
+        if (!ov) break;
+        if ((1 << s2) >= pt2_max_k2() || attempt > 8)
+            return fail(ctx, DNQS_ECAPACITY, "PT2: a sub-bucket holds more than %d unique keys", pt2_red_tab());
+        ++s2;
     }
-    launch_pt2_final(st, acc, acc + 4, stats, out, counts, pairs, npass);
+    launch_pt2_final(st, acc, acc + 4, stats, out, counts, pairs, nsb_used);
     CHECK_LAUNCH(ctx);
     tm.stop();
     HIPCHK(ctx, hipStreamSynchronize(st));

@@ -16,6 +16,7 @@ struct Ham {
     const double *h64;    // [M*M]
     const double *eri64;  // [M^4], (pq|rs) at ((p*M+q)*M+r)*M+s
     const float *eri32;   // [M^4]
+    const double *eri_pk; // 8-fold packed (pq|rs): index pair(pair(p,q), pair(r,s))
     const double *J;      // [M*M], (pp|qq)
     const double *K;      // [M*M], (pq|qp)
 };
@@ -75,25 +76,46 @@ __device__ inline double h_diag(const Ham &H, uint64_t a, uint64_t b) {
     return e;
 }
 
+// index of an unordered pair (p, q) in the lower triangle
+__device__ __forceinline__ int tri_index(int p, int q) { return p >= q ? p * (p + 1) / 2 + q : q * (q + 1) / 2 + p; }
+
+// (pq|rs) from the dense M^4 table
+template <typename T>
+struct EriDense {
+    const T *e;
+    int M;
+    __device__ __forceinline__ double operator()(int p, int q, int r, int s) const {
+        return (double)e[eri_index(M, p, q, r, s)];
+    }
+};
+
+// (pq|rs) from the 8-fold packed FP64 table (M = 28: 661 KB, resident in L2)
+struct EriPacked {
+    const double *e;
+    __device__ __forceinline__ double operator()(int p, int q, int r, int s) const {
+        return e[tri_index(tri_index(p, q), tri_index(r, s))];
+    }
+};
+
 // Single excitation q -> p on spin string `same` (the ket's string of that spin,
 // q occupied, p empty); `other` is the ket's opposite-spin string.
 // value (without phase) = h_pq + sum_{r in same, r != q} [(pq|rr) - (pr|rq)]
 //                               + sum_{r in other} (pq|rr)
-template <typename T>
-__device__ inline double single_value(const Ham &H, const T *eri, int p, int q, uint64_t same, uint64_t other) {
+template <typename ERI>
+__device__ inline double single_value(const Ham &H, const ERI &eri, int p, int q, uint64_t same, uint64_t other) {
     const int M = H.M;
     double v = H.h64[p * M + q];
     uint64_t s = same & ~(1ull << q);
     while (s) {
         int r = ctz64(s);
         s &= s - 1;
-        v += (double)eri[eri_index(M, p, q, r, r)] - (double)eri[eri_index(M, p, r, r, q)];
+        v += eri(p, q, r, r) - eri(p, r, r, q);
     }
     uint64_t o = other;
     while (o) {
         int r = ctz64(o);
         o &= o - 1;
-        v += (double)eri[eri_index(M, p, q, r, r)];
+        v += eri(p, q, r, r);
     }
     return v;
 }
@@ -101,9 +123,8 @@ __device__ inline double single_value(const Ham &H, const T *eri, int p, int q, 
 // <x|H|y> for x != y of one sector, by comparing the strings.  Returns 0 for rank > 2.
 // Holes (occupied in y only) and particles (occupied in x only) are paired in
 // ascending order; the phase is that of applying the pairs one after the other.
-template <typename T>
-__device__ inline double h_offdiag(const Ham &H, const T *eri, uint64_t xa, uint64_t xb, uint64_t ya, uint64_t yb) {
-    const int M = H.M;
+template <typename ERI>
+__device__ inline double h_offdiag(const Ham &H, const ERI &eri, uint64_t xa, uint64_t xb, uint64_t ya, uint64_t yb) {
     uint64_t da = xa ^ ya, db = xb ^ yb;
     int na = popc64(da), nb = popc64(db);
     if (na + nb == 2) {
@@ -127,14 +148,14 @@ __device__ inline double h_offdiag(const Ham &H, const T *eri, uint64_t xa, uint
         int s1 = phase_between(s, i, a);
         uint64_t s_1 = (s & ~(1ull << i)) | (1ull << a);
         int s2 = phase_between(s_1, j, b);
-        double v = (double)eri[eri_index(M, a, i, b, j)] - (double)eri[eri_index(M, a, j, b, i)];
+        double v = eri(a, i, b, j) - eri(a, j, b, i);
         return s1 * s2 * v;
     }
     // alpha-beta double
     int i = ctz64(ya & da), a = ctz64(xa & da);
     int j = ctz64(yb & db), b = ctz64(xb & db);
     int sg = phase_between(ya, i, a) * phase_between(yb, j, b);
-    return sg * (double)eri[eri_index(M, a, i, b, j)];
+    return sg * eri(a, i, b, j);
 }
 
 // SplitMix64 output function (Steele, Lea and Flood 2014).

@@ -1,0 +1,118 @@
+// Enumeration of the single and double excitations of one determinant by a wavefront.
+//
+// The wave writes the occupied and empty orbitals of each spin string to LDS once;
+// lanes then map excitation ids e in [0, n_exc) in closed form onto
+//   [alpha singles | beta singles | alpha-alpha doubles | beta-beta doubles | alpha-beta doubles]
+// and return the flipped spin-orbitals as four 7-bit positions (alpha p -> p,
+// beta p -> 64 + p, unused -> 127).  The target is x XOR those bits.
+#pragma once
+#include "dnqs_device.h"
+
+namespace dnqs {
+
+constexpr uint32_t kNoPos = 127u;
+
+struct ExcLists {
+    const uint8_t *oa, *va, *ob, *vb;  // occupied / empty orbitals per spin string
+    int nva, nvb;
+    int64_t pva, pvb, nsb;
+    int64_t c1, c2, c3, c4, total;     // class boundaries
+};
+
+// pair index t over n items (i < j), ordered by j then i: t = j(j-1)/2 + i
+__device__ __forceinline__ void unrank_pair(int t, int &i, int &j) {
+    int jj = (int)((1.0 + sqrt(1.0 + 8.0 * (double)t)) * 0.5);
+    while (jj * (jj - 1) / 2 > t) --jj;
+    while ((jj + 1) * jj / 2 <= t) ++jj;
+    j = jj;
+    i = t - jj * (jj - 1) / 2;
+}
+
+// Fill lists[4][64] for det (xa, xb) with one wavefront (lanes 0..M-1 take part).
+__device__ inline void wave_build_lists(uint8_t (*lists)[64], int M, uint64_t xa, uint64_t xb) {
+    const int lane = __lane_id();
+    const bool in = lane < M;
+    const bool ba = in && ((xa >> lane) & 1ull), bb = in && ((xb >> lane) & 1ull);
+    const uint64_t moa = __ballot(ba), mva = __ballot(in && !ba), mob = __ballot(bb), mvb = __ballot(in && !bb);
+    if (ba) lists[0][mbcnt(moa)] = (uint8_t)lane;
+    if (in && !ba) lists[1][mbcnt(mva)] = (uint8_t)lane;
+    if (bb) lists[2][mbcnt(mob)] = (uint8_t)lane;
+    if (in && !bb) lists[3][mbcnt(mvb)] = (uint8_t)lane;
+}
+
+__device__ inline ExcLists make_exc_lists(const uint8_t (*lists)[64], int M, int na, int nb) {
+    ExcLists c;
+    c.oa = lists[0];
+    c.va = lists[1];
+    c.ob = lists[2];
+    c.vb = lists[3];
+    c.nva = M - na;
+    c.nvb = M - nb;
+    const int64_t nsa = (int64_t)na * c.nva;
+    c.nsb = (int64_t)nb * c.nvb;
+    c.pva = (int64_t)c.nva * (c.nva - 1) / 2;
+    c.pvb = (int64_t)c.nvb * (c.nvb - 1) / 2;
+    const int64_t ndaa = (int64_t)na * (na - 1) / 2 * c.pva, ndbb = (int64_t)nb * (nb - 1) / 2 * c.pvb;
+    c.c1 = nsa;
+    c.c2 = c.c1 + c.nsb;
+    c.c3 = c.c2 + ndaa;
+    c.c4 = c.c3 + ndbb;
+    c.total = c.c4 + nsa * c.nsb;
+    return c;
+}
+
+__device__ __forceinline__ uint32_t pack_pos(uint32_t p0, uint32_t p1, uint32_t p2, uint32_t p3) {
+    return p0 | (p1 << 7) | (p2 << 14) | (p3 << 21);
+}
+
+// flipped positions of excitation e
+__device__ inline uint32_t excitation_positions(const ExcLists &c, int64_t e) {
+    if (e < c.c1) {
+        const int t = (int)e;
+        return pack_pos(c.oa[t / c.nva], c.va[t % c.nva], kNoPos, kNoPos);
+    }
+    if (e < c.c2) {
+        const int t = (int)(e - c.c1);
+        return pack_pos(64u + c.ob[t / c.nvb], 64u + c.vb[t % c.nvb], kNoPos, kNoPos);
+    }
+    if (e < c.c3) {
+        const int64_t t = e - c.c2;
+        int i, j, a, b;
+        unrank_pair((int)(t / c.pva), i, j);
+        unrank_pair((int)(t % c.pva), a, b);
+        return pack_pos(c.oa[i], c.oa[j], c.va[a], c.va[b]);
+    }
+    if (e < c.c4) {
+        const int64_t t = e - c.c3;
+        int i, j, a, b;
+        unrank_pair((int)(t / c.pvb), i, j);
+        unrank_pair((int)(t % c.pvb), a, b);
+        return pack_pos(64u + c.ob[i], 64u + c.ob[j], 64u + c.vb[a], 64u + c.vb[b]);
+    }
+    const int64_t t = e - c.c4;
+    const int sa = (int)(t / c.nsb), sb = (int)(t % c.nsb);
+    return pack_pos(c.oa[sa / c.nva], c.va[sa % c.nva], 64u + c.ob[sb / c.nvb], 64u + c.vb[sb % c.nvb]);
+}
+
+// target = x with the bits at the packed positions flipped
+__device__ __forceinline__ void apply_positions(uint32_t pos, uint64_t &a, uint64_t &b) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t p = (pos >> (7 * k)) & 127u;
+        if (p == kNoPos) continue;
+        if (p < 64u)
+            a ^= 1ull << p;
+        else
+            b ^= 1ull << (p - 64u);
+    }
+}
+
+__device__ __forceinline__ uint64_t pack_key(uint64_t a, uint64_t b) { return a | (b << 32); }
+
+// key hash of a target; packed keys (M <= 32) hash the packed word
+template <bool PACKED>
+__device__ __forceinline__ uint64_t target_hash(uint64_t a, uint64_t b) {
+    return PACKED ? mix64(pack_key(a, b)) : key_hash(a, b);
+}
+
+}  // namespace dnqs

@@ -11,6 +11,8 @@ struct DetSet;
 
 // ---------------------------------------------------------------- Hamiltonian side
 void launch_stage_integrals(hipStream_t st, int M, const double *eri64, float *eri32, double *J, double *K);
+size_t packed_eri_size(int M);
+void launch_pack_eri(hipStream_t st, int M, const double *eri64, double *pk);
 void launch_validate_dets(hipStream_t st, const uint64_t *dets, int64_t n, int M, int na, int nb, int check_order,
                           int *err);
 void launch_fill_u64(hipStream_t st, uint64_t *p, size_t n, uint64_t v);
@@ -71,20 +73,6 @@ void launch_set_f64(hipStream_t st, double *p, double v);
 void launch_copy_f64(hipStream_t st, const double *a, double *b, int64_t n);
 
 // ---------------------------------------------------------------- PT2
-struct Slot16 {
-    unsigned long long key;
-    double w;
-};
-struct Slot32 {
-    unsigned long long ka, kb;
-    double w, pad;
-};
-struct PT2Table {
-    void *slots;
-    uint64_t mask;  // capacity - 1
-    unsigned long long *n_unique;
-    int *overflow;
-};
 struct PT2Export {
     int64_t cap;
     uint64_t *keys;
@@ -92,13 +80,31 @@ struct PT2Export {
     double *haa;
     int64_t *count;
 };
+// one L2 chunk: desc1[start, start+len) in L1 bucket b1, whose chunks are cb0..cb0+nc-1
+struct PT2Chunk {
+    int64_t start, len, cb0, nc;
+};
 
-void launch_pt2_gen(hipStream_t st, const Ham &H, const uint64_t *dets, int64_t n, const double *psi, int npass,
-                    int pass, const PT2Table &T, bool packed);
-void launch_pt2_clear(hipStream_t st, const PT2Table &T, bool packed);
-int pt2_fin_blocks(uint64_t cap);
-void launch_pt2_finalize(hipStream_t st, const Ham &H, const PT2Table &T, bool packed, const DetSet &S,
-                         const double *energy, uint64_t sample_mask, const PT2Export &ex, double *part, double *acc);
+int64_t pt2_l1_groups(int64_t n);
+int pt2_red_tab();
+int pt2_max_k1();
+int pt2_max_k2();
+void launch_pt2_l1(hipStream_t st, const Ham &H, const uint64_t *dets, int64_t n, const double *psi, int s1,
+                   int64_t nwg, uint32_t *counts, const int64_t *offs, uint64_t *desc, bool fill, bool packed);
+void launch_transpose_u32(hipStream_t st, const uint32_t *in, int64_t R, int64_t C, int32_t *out);
+void launch_gather_starts(hipStream_t st, const int64_t *offs, int K, int64_t stride, const int64_t *total,
+                          int64_t *starts);
+void launch_pt2_l2(hipStream_t st, const uint64_t *desc1, const PT2Chunk *chunks, int64_t nchunk, int s2,
+                   uint32_t *counts, const int64_t *offs, uint64_t *desc2, bool fill);
+int pt2_max_dets();
+void launch_l2_transpose(hipStream_t st, const uint32_t *counts, const PT2Chunk *chunks, int64_t nchunk, int K2,
+                         int32_t *out);
+void launch_sub_starts(hipStream_t st, const int64_t *offs2, const int64_t *bstart, const int64_t *bcb0,
+                       const int64_t *bnc, int K1, int K2, int64_t *sb);
+void launch_pt2_reduce(hipStream_t st, const Ham &H, const uint64_t *dets, const double *psi, const uint64_t *desc,
+                       const int64_t *sb, int64_t nsb, const DetSet &S, const double *energy, uint64_t sample_mask,
+                       const PT2Export &ex, double *part, int *overflow, bool packed);
+void launch_pt2_accumulate(hipStream_t st, const double *part, int64_t nb, double *acc);
 void launch_pt2_internal(hipStream_t st, const double *psi, const double *v, const double *diag, int64_t n,
                          const double *energy, double *part, double *acc_int);
 void launch_pt2_init_acc(hipStream_t st, double *acc);

@@ -31,6 +31,30 @@ __global__ void k_stage_integrals(int M, const double *__restrict__ eri64, float
     }
 }
 
+// packed[tri(tri(p,q), tri(r,s))] = (pq|rs) for the canonical p>=q, r>=s, pq>=rs
+__global__ void k_pack_eri(int M, const double *__restrict__ eri64, double *__restrict__ pk) {
+    size_t n4 = (size_t)M * M * M * M;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x) {
+        const int s = (int)(i % M), r = (int)((i / M) % M), q = (int)((i / M / M) % M), p = (int)(i / M / M / M);
+        if (p < q || r < s) continue;
+        const int pq = tri_index(p, q), rs = tri_index(r, s);
+        if (pq < rs) continue;
+        pk[tri_index(pq, rs)] = eri64[i];
+    }
+}
+
+size_t packed_eri_size(int M) {
+    size_t np = (size_t)M * (M + 1) / 2;
+    return np * (np + 1) / 2;
+}
+
+void launch_pack_eri(hipStream_t st, int M, const double *eri64, double *pk) {
+    size_t n4 = (size_t)M * M * M * M;
+    int blocks = (int)((n4 + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_pack_eri, dim3(blocks), dim3(256), 0, st, M, eri64, pk);
+}
+
 void launch_stage_integrals(hipStream_t st, int M, const double *eri64, float *eri32, double *J, double *K) {
     size_t n4 = (size_t)M * M * M * M;
     int blocks = (int)((n4 + 255) / 256);
@@ -155,7 +179,7 @@ __global__ __launch_bounds__(256) void k_hss_pairs(Ham H, const uint64_t *__rest
                     if (hit) {
                         const int64_t pos = cursor[wave][r] + mbcnt(m);
                         col[pos] = (int32_t)y;
-                        val[pos] = (float)h_offdiag(H, H.eri64, xa, xb, ya, ybb);
+                        val[pos] = (float)h_offdiag(H, EriPacked{H.eri_pk}, xa, xb, ya, ybb);
                     }
                 }
                 if (lane == 0) cursor[wave][r] += __popcll(m);
