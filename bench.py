@@ -69,6 +69,11 @@ def cpu_baseline(p, sample_n: int):
     }
 
 
+# network GEMM arithmetic: FP32 MFMA; split-BF16 hidden layers with an FP32 orbital
+# output layer; split-BF16 everywhere
+PRECISIONS = {"fp32": "FP32", "mixed": "MIXED", "split_bf16": "SPLIT_BF16"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,8 +81,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="m28_7a7b_s100k")
     ap.add_argument("--n-dets", type=int, default=None)
-    ap.add_argument("--precision", choices=["fp32", "mixed"], default="fp32")
-    ap.add_argument("--out-scale", type=float, default=1.0)
+    ap.add_argument("--precision", choices=list(PRECISIONS), default="mixed")
+    ap.add_argument("--out-scale", type=float, default=1e-2,
+                    help="scale of the Glorot output layer (small, as the paper initialises it)")
     ap.add_argument("--cpu-sample", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -109,7 +115,7 @@ def main():
     print(f"[bench] building inputs for {wl.name}", file=sys.stderr, flush=True)
     p = synth.make_problem(wl, n_dets=args.n_dets, out_scale=args.out_scale)
     n = p.dets.shape[0]
-    prec = dnqs.FP32 if args.precision == "fp32" else dnqs.MIXED
+    prec = getattr(dnqs, PRECISIONS[args.precision])
     ctx = dnqs.Context(0)
     ctx.set_integrals(p.h, p.eri, p.e_core, wl.n_alpha, wl.n_beta)
     dets = dnqs.dets_to_device(p.dets)
@@ -138,6 +144,20 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     fam = {f: ctx.timing_get(f) for f in ("hss", "egrad", "pt2", "pt2_l1", "pt2_l1_fill", "pt2_l2", "pt2_reduce")}
+    # energy_and_grad in every precision on the same S, for the speed/accuracy comparison
+    conn = ctx.build_connections(dets, validate=False)
+    forms = {}
+    for name, attr in PRECISIONS.items():
+        pr = getattr(dnqs, attr)
+        r = ctx.energy_and_grad(wl.widths, theta, conn, want_grad=True, precision=pr)
+        torch.cuda.synchronize()
+        ctx.timing_reset()
+        for i in range(max(args.steps, 3)):
+            r = ctx.energy_and_grad(wl.widths, theta, conn, want_grad=True, precision=pr)
+        torch.cuda.synchronize()
+        tg = ctx.timing_get("egrad")
+        forms[name] = (tg[0] / max(tg[1], 1), r["E"].item(), r["grad"].double())
+    conn.free()
     ctx.timing(False)
     ms_step = (t1 - t0) * 1e3 / args.steps
     t_h = fam["hss"][0] / max(fam["hss"][1], 1)
@@ -145,6 +165,12 @@ def main():
     t_p = fam["pt2"][0] / max(fam["pt2"][1], 1)
     avg = {k: v[0] / max(v[1], 1) for k, v in fam.items()}
     E = res["E"].item()
+    t32, E32, g32 = forms["fp32"]
+    compare = {}
+    for name, (t, Ef, gf) in forms.items():
+        compare[name] = {"ms": t, "amps_grads_per_s": n / (t * 1e-3), "speedup_vs_fp32": t32 / t,
+                         "abs_E_minus_E_fp32": abs(Ef - E32),
+                         "grad_rel_l2_vs_fp32": float(torch.linalg.vector_norm(gf - g32) / torch.linalg.vector_norm(g32))}
     o = out["out"].cpu().numpy()
     c = out["counts"].cpu().numpy()
     pairs = int(c[0])
@@ -159,7 +185,7 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if prec == dnqs.FP32 else "bf16/f32",
+        "dtype": "f32" if prec == dnqs.FP32 else "bf16x3+f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "M": wl.M, "n_alpha": wl.n_alpha, "n_beta": wl.n_beta, "n_dets": n,
                    "widths": list(wl.widths), "precision": args.precision, "out_scale": args.out_scale},
@@ -172,6 +198,7 @@ def main():
             "pt2_sub_buckets": int(c[3]),
         },
         "results": {"E": E, "dE_pt2": float(o[0]), "E_total": E + float(o[0]), "min_denominator": float(o[3])},
+        "precisions": compare,
         "roofline": {"kernel": "pt2 (L1 + L2 + reduce)", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": pt2_bytes},

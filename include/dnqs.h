@@ -62,10 +62,17 @@ typedef enum {
     DNQS_EDOMAIN = -6    /* numerical domain error (psi^T psi == 0) */
 } dnqs_status;
 
+/* Arithmetic of the network GEMMs.  Activations, weights and gradients are FP32 in
+ * memory in every form; the embedding, the LU and the orbital projection are FP32 and
+ * every reduction (log|det|, psi^T psi, psi^T H psi, PT2) is FP64.
+ * "Split BF16": each FP32 operand x is held as x_hi = bf16(x) plus x_lo = bf16(x - x_hi)
+ * and a product is a_lo b_hi + a_hi b_lo + a_hi b_hi on BF16 MFMA with FP32
+ * accumulation (relative error near 2^-17 per product instead of 2^-9 for one BF16
+ * product). */
 typedef enum {
-    DNQS_FP32 = 0,  /* every network GEMM in FP32 on MFMA */
-    DNQS_MIXED = 1  /* hidden-layer GEMMs in BF16 on MFMA with FP32 accumulation;
-                       embedding, output layer and LU in FP32; reductions in FP64 */
+    DNQS_FP32 = 0,      /* every network GEMM on FP32 MFMA */
+    DNQS_MIXED = 1,     /* hidden-layer GEMMs in split BF16; orbital output layer on FP32 MFMA */
+    DNQS_SPLIT_BF16 = 2 /* every network GEMM, the orbital output layer included, in split BF16 */
 } dnqs_precision;
 
 #define DNQS_MAX_LAYERS 8
@@ -172,6 +179,53 @@ typedef struct {
 } dnqs_pt2_opts;
 dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const double *log_abs, const int8_t *sign,
                      const double *energy, const dnqs_pt2_opts *opts, double *out, int64_t *counts);
+
+/* ------------------------------------------------------------------ batched geometries
+ * Several independent problems (e.g. the geometries of a dissociation curve), each with
+ * its own integrals (slot), variational set and H_SS (conn), parameters and outputs,
+ * evaluated together: every stage of energy_and_grad (embedding, each GEMM, LU, SpMV,
+ * reductions, adjoint) is one launch over all problems, with work items ordered by
+ * problem.  All problems share (M, n_alpha, n_beta) and the network shape.  The first
+ * call with a new set of conns builds a plan (copies of S and H_SS in a concatenated
+ * layout) and synchronises; later calls with the same conns and pointers only enqueue
+ * (so they may be captured in a graph).  Per problem the results equal those of
+ * dnqs_energy_and_grad up to the summation order of the weight gradients.
+ * theta, grad, energy, stats: dev pointers as in dnqs_energy_and_grad (grad NULL for
+ * every problem: no backward pass).  1 <= n_problems <= DNQS_MAX_SLOTS. */
+typedef struct {
+    int slot;
+    const dnqs_conn *conn;
+    float *theta;
+    float *grad;
+    double *energy;
+    double *stats;
+} dnqs_problem;
+dnqs_status dnqs_energy_and_grad_batched(dnqs_ctx *ctx, const dnqs_net *net, int n_problems,
+                                         const dnqs_problem *problems, int precision, unsigned flags);
+
+/* AdamW (the inner-loop optimiser, Sec. 3.3) for every problem of a batch:
+ * m, v: dev FP32 [n_problems * param_count] (problem-major, zero before the first step);
+ * step: dev int32[1], read as t - 1 and incremented; lr follows the cosine decay
+ * lr_min + (lr_max - lr_min) (1 + cos(pi min(t, decay_steps) / decay_steps)) / 2.
+ * theta[i] -= lr (mhat / (sqrt(vhat) + eps) + weight_decay theta[i]).  Enqueue only. */
+typedef struct {
+    float lr_max, lr_min;
+    int decay_steps;
+    float beta1, beta2, eps, weight_decay;
+} dnqs_adamw_cfg;
+dnqs_status dnqs_adamw_batched(dnqs_ctx *ctx, const dnqs_net *net, int n_problems, const dnqs_problem *problems,
+                               float *m, float *v, const dnqs_adamw_cfg *cfg, int *step);
+
+/* HIP graph capture of the work a context enqueues between begin and end (the context's
+ * stream must not be the null stream).  Only calls that do not synchronise may be made
+ * in between: dnqs_energy_and_grad(_batched) after a first un-captured call with the
+ * same arguments, dnqs_adamw_batched, dnqs_amplitudes.  dnqs_graph_launch replays the
+ * graph on the context's stream. */
+typedef struct dnqs_graph dnqs_graph;
+dnqs_status dnqs_capture_begin(dnqs_ctx *ctx);
+dnqs_status dnqs_capture_end(dnqs_ctx *ctx, dnqs_graph **out);
+dnqs_status dnqs_graph_launch(dnqs_ctx *ctx, dnqs_graph *graph);
+void dnqs_graph_free(dnqs_graph *graph);
 
 /* ------------------------------------------------------------------ timing
  * Average device time (ms) of the most recent launches of the named kernel family

@@ -165,14 +165,7 @@ int or_dense_opalg(int M, const double *h, const double *eri, double ecore, cons
 }
 
 /* ------------------------------------------------------------------ Slater-Condon */
-static int popc64(uint64_t v) {
-    int c = 0;
-    while (v) {
-        v &= v - 1;
-        ++c;
-    }
-    return c;
-}
+static int popc64(uint64_t v) { return __builtin_popcountll(v); }
 
 /* spin-orbital string as a 2M-long bit array; occupied count strictly between lo and hi */
 static int occ_between(fock_t z, int M, int lo, int hi) {

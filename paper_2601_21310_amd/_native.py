@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdnqs.so")
 
 MAX_LAYERS = 8
-FP32, MIXED = 0, 1
+FP32, MIXED, SPLIT_BF16 = 0, 1, 2
 VALIDATE = 1
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ECAPACITY", -5: "ESTATE", -6: "EDOMAIN"}
@@ -41,6 +41,16 @@ class Net(C.Structure):
         for i, v in enumerate(w):
             net.width[i] = int(v)
         return net
+
+
+class Problem(C.Structure):
+    _fields_ = [("slot", C.c_int), ("conn", C.c_void_p), ("theta", C.c_void_p), ("grad", C.c_void_p),
+                ("energy", C.c_void_p), ("stats", C.c_void_p)]
+
+
+class AdamwCfg(C.Structure):
+    _fields_ = [("lr_max", C.c_float), ("lr_min", C.c_float), ("decay_steps", C.c_int), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("weight_decay", C.c_float)]
 
 
 class PT2Opts(C.Structure):
@@ -77,12 +87,20 @@ def lib():
         L.dnqs_amplitudes.argtypes = [vp, i32, C.POINTER(Net), vp, vp, i64, i32, vp, vp]
         L.dnqs_energy_and_grad.argtypes = [vp, i32, C.POINTER(Net), vp, vp, i32, C.c_uint, vp, vp, vp, vp, vp, vp]
         L.dnqs_pt2.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(PT2Opts), vp, vp]
+        L.dnqs_energy_and_grad_batched.argtypes = [vp, C.POINTER(Net), i32, C.POINTER(Problem), i32, C.c_uint]
+        L.dnqs_adamw_batched.argtypes = [vp, C.POINTER(Net), i32, C.POINTER(Problem), vp, vp, C.POINTER(AdamwCfg), vp]
+        L.dnqs_capture_begin.argtypes = [vp]
+        L.dnqs_capture_end.argtypes = [vp, C.POINTER(vp)]
+        L.dnqs_graph_launch.argtypes = [vp, vp]
+        L.dnqs_graph_free.argtypes = [vp]
+        L.dnqs_graph_free.restype = None
         L.dnqs_timing_enable.argtypes = [vp, i32]
         L.dnqs_timing_reset.argtypes = [vp]
         L.dnqs_timing_get.argtypes = [vp, C.c_char_p, C.POINTER(dbl), C.POINTER(i64)]
         for fn in ("dnqs_create", "dnqs_set_stream", "dnqs_set_integrals", "dnqs_build_connections",
                    "dnqs_conn_info", "dnqs_conn_export", "dnqs_amplitudes", "dnqs_energy_and_grad", "dnqs_pt2",
-                   "dnqs_timing_enable", "dnqs_timing_reset", "dnqs_timing_get"):
+                   "dnqs_energy_and_grad_batched", "dnqs_adamw_batched", "dnqs_capture_begin", "dnqs_capture_end",
+                   "dnqs_graph_launch", "dnqs_timing_enable", "dnqs_timing_reset", "dnqs_timing_get"):
             getattr(L, fn).restype = C.c_int
         _lib = L
     return _lib
@@ -258,6 +276,48 @@ class Context:
             res["export"] = ex
         return res
 
+    # -------------------------------------------------------------- batched geometries
+    def batch(self, widths, slots, conns, thetas, want_grad=True):
+        """Device buffers and the C problem table for a batch (one entry per geometry)."""
+        dev = thetas[0].device
+        G = len(conns)
+        probs = (Problem * G)()
+        keep = []
+        for g in range(G):
+            th = _dev_tensor(thetas[g], torch.float32, "theta", self.device)
+            E = torch.empty(1, dtype=torch.float64, device=dev)
+            st = torch.empty(3, dtype=torch.float64, device=dev)
+            gr = torch.empty_like(th) if want_grad else None
+            probs[g].slot = slots[g]
+            probs[g].conn = conns[g].handle
+            probs[g].theta = th.data_ptr()
+            probs[g].grad = gr.data_ptr() if gr is not None else None
+            probs[g].energy = E.data_ptr()
+            probs[g].stats = st.data_ptr()
+            keep.append({"theta": th, "E": E, "stats": st, "grad": gr})
+        return {"widths": tuple(widths), "probs": probs, "buffers": keep, "conns": conns}
+
+    def energy_and_grad_batched(self, batch, precision=FP32):
+        net = Net.from_widths(batch["widths"])
+        self._check(lib().dnqs_energy_and_grad_batched(self.handle, C.byref(net), len(batch["buffers"]),
+                                                       batch["probs"], precision, 0))
+        return batch["buffers"]
+
+    def adamw_batched(self, batch, m, v, step, lr_max=1e-3, lr_min=5e-5, decay_steps=800, beta1=0.9, beta2=0.999,
+                      eps=1e-8, weight_decay=1e-2):
+        cfg = AdamwCfg(lr_max, lr_min, decay_steps, beta1, beta2, eps, weight_decay)
+        net = Net.from_widths(batch["widths"])
+        self._check(lib().dnqs_adamw_batched(self.handle, C.byref(net), len(batch["buffers"]), batch["probs"],
+                                             _ptr(m), _ptr(v), C.byref(cfg), _ptr(step)))
+
+    def capture_begin(self):
+        self._check(lib().dnqs_capture_begin(self.handle))
+
+    def capture_end(self):
+        g = C.c_void_p()
+        self._check(lib().dnqs_capture_end(self.handle, C.byref(g)))
+        return Graph(self, g)
+
     # -------------------------------------------------------------- timing
     def timing(self, on=True):
         self._check(lib().dnqs_timing_enable(self.handle, 1 if on else 0))
@@ -269,6 +329,28 @@ class Context:
         ms, k = C.c_double(), C.c_int64()
         self._check(lib().dnqs_timing_get(self.handle, family.encode(), C.byref(ms), C.byref(k)))
         return ms.value, k.value
+
+
+class Graph:
+    """A captured sequence of library calls, replayed on the context's stream."""
+
+    def __init__(self, ctx, handle):
+        self._ctx = ctx
+        self.handle = handle
+
+    def launch(self):
+        self._ctx._check(lib().dnqs_graph_launch(self._ctx.handle, self.handle))
+
+    def free(self):
+        if self.handle:
+            lib().dnqs_graph_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def dets_to_device(dets_np, device=0):

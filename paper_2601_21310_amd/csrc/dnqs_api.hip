@@ -39,6 +39,31 @@ thread_local std::string g_create_error;
 
 }  // namespace
 
+// Concatenated layout of a batch of problems (built once per set of conns).
+struct BatchPlan {
+    bool valid = false;
+    std::vector<const dnqs_conn *> conns;
+    int G = 0;
+    int64_t ntot = 0, nnz = 0;
+    std::vector<int64_t> off, nn;
+    uint64_t *dets = nullptr;
+    int32_t *pid = nullptr;
+    int64_t *row_ptr = nullptr;
+    int32_t *col = nullptr;
+    float *val = nullptr;
+    double *diag = nullptr;
+    int *tile_pid = nullptr;  // per 128-row tile
+    int2 *ksplit = nullptr;   // weight-gradient k ranges, problem by problem
+    int *zoff = nullptr;      // first ksplit entry of each problem
+    int nz = 0;
+    // per-call pointers (rebuilt when they change, outside any capture)
+    std::vector<ProbDev> P_h;
+    ProbDev *P_d = nullptr;
+    std::vector<const void *> ptr_h;  // [layer][G] weights then [layer][G] biases
+    const void **ptr_d = nullptr;
+    int ptr_layers = 0;
+};
+
 struct dnqs_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -48,6 +73,14 @@ struct dnqs_ctx {
     bool timing = false;
     std::map<std::string, TimingRec> times;
     std::vector<hipEvent_t> event_pool;
+    BatchPlan plan;
+    bool capturing = false;
+};
+
+struct dnqs_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int device = 0;
 };
 
 struct dnqs_conn {
@@ -235,27 +268,40 @@ int splitk_splits(int M, int N, int64_t K) {
     return s;
 }
 
-// Forward pass: activations h_1..h_{L-1} kept in workspaces "h1".., output layer in "O",
-// then orbital rows + LU.  With want_grad also U (occupations) and A^-1.
+// GEMM engine of one layer: FP32 MFMA, or split-BF16 MFMA for the hidden layers of
+// DNQS_MIXED and for every layer of DNQS_SPLIT_BF16.
+void mlp_gemm(hipStream_t st, int precision, bool out_layer, const GemmArgs &g, bool a_kcontig, bool b_ncontig,
+              int epi, int splits) {
+    const bool x3 = precision == DNQS_SPLIT_BF16 || (precision == DNQS_MIXED && !out_layer);
+    if (x3)
+        launch_gemm_x3(st, g, a_kcontig, b_ncontig, epi, splits);
+    else
+        launch_gemm_f32(st, g, a_kcontig, b_ncontig, epi, splits);
+}
+
+bool precision_ok(int p) { return p == DNQS_FP32 || p == DNQS_MIXED || p == DNQS_SPLIT_BF16; }
+
+// Forward pass: activations h_1..h_{L-1} kept in workspaces "h1".. (FP32), output layer
+// in "O" (FP32), then orbital rows + LU.  With want_grad also U (occupations) and A^-1.
 dnqs_status forward(dnqs_ctx *ctx, const Slot &sl, const NetView &nv, const float *theta, const uint64_t *dets,
                     int64_t n, int precision, bool want_grad, double *logabs, int8_t *sign, float **Ainv_out) {
-    (void)precision;
     hipStream_t st = ctx->stream;
+    const size_t esz = sizeof(float);
     const int M = sl.M, No = 2 * M, Ne = sl.na + sl.nb, L = nv.L;
     const int *w = nv.w;
-    float *U = nullptr;
-    if (want_grad) TRY(ws_t(ctx, "U", (size_t)n * No, &U));
-    float *h = nullptr;
-    TRY(ws_t(ctx, "h1", (size_t)n * w[1], &h));
-    launch_embed(st, dets, n, M, w[1], theta + nv.offW[1], theta + nv.offb[1], h, U);
+    void *U = nullptr;
+    if (want_grad) TRY(ws_get(ctx, "U", (size_t)n * No * esz, &U));
+    void *h = nullptr;
+    TRY(ws_get(ctx, "h1", (size_t)n * w[1] * esz, &h));
+    launch_embed(st, dets, n, M, w[1], theta + nv.offW[1], theta + nv.offb[1], (float *)h, (float *)U);
     CHECK_LAUNCH(ctx);
-    float *prev = h;
+    void *prev = h;
     for (int l = 2; l <= L; ++l) {
-        float *out = nullptr;
+        void *out = nullptr;
         if (l < L)
-            TRY(ws_t(ctx, "h" + std::to_string(l), (size_t)n * w[l], &out));
+            TRY(ws_get(ctx, "h" + std::to_string(l), (size_t)n * w[l] * esz, &out));
         else
-            TRY(ws_t(ctx, "O", (size_t)n * w[l], &out));
+            TRY(ws_get(ctx, "O", (size_t)n * w[l] * sizeof(float), &out));
         GemmArgs g{};
         g.M = (int)n;
         g.N = w[l];
@@ -268,13 +314,13 @@ dnqs_status forward(dnqs_ctx *ctx, const Slot &sl, const NetView &nv, const floa
         g.ldc = w[l];
         g.bias = theta + nv.offb[l];
         g.ones_row = -1;
-        launch_gemm_f32(st, g, true, true, l < L ? EPI_BIAS_TANH : EPI_BIAS, 1);
+        mlp_gemm(st, precision, l == L, g, true, true, l < L ? EPI_BIAS_TANH : EPI_BIAS, 1);
         CHECK_LAUNCH(ctx);
         prev = out;
     }
     float *Ainv = nullptr;
     if (want_grad) TRY(ws_t(ctx, "Ainv", (size_t)n * Ne * Ne, &Ainv));
-    launch_orb_lu(st, dets, n, M, sl.na, sl.nb, prev, theta + nv.offPhi0, logabs, sign, Ainv);
+    launch_orb_lu(st, dets, n, M, sl.na, sl.nb, (const float *)prev, theta + nv.offPhi0, logabs, sign, Ainv);
     CHECK_LAUNCH(ctx);
     if (Ainv_out) *Ainv_out = Ainv;
     return DNQS_OK;
@@ -356,6 +402,10 @@ void dnqs_destroy(dnqs_ctx *ctx) {
             (void)hipEventDestroy(p.second);
         }
     for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+    BatchPlan &b = ctx->plan;
+    for (void *q : {(void *)b.dets, (void *)b.pid, (void *)b.row_ptr, (void *)b.col, (void *)b.val, (void *)b.diag,
+                    (void *)b.tile_pid, (void *)b.ksplit, (void *)b.zoff, (void *)b.P_d, (void *)b.ptr_d})
+        if (q) (void)hipFree(q);
     delete ctx;
 }
 
@@ -539,7 +589,8 @@ dnqs_status dnqs_amplitudes(dnqs_ctx *ctx, int slot, const dnqs_net *net, const 
     if (!theta || !dets || !log_abs || !sign) return fail(ctx, DNQS_EINVAL, "NULL pointer argument");
     if (n < 1 || n >= (int64_t)1 << 31) return fail(ctx, DNQS_EINVAL, "n out of range");
     if (orb_lu_group(sl.na + sl.nb) == 0) return fail(ctx, DNQS_EINVAL, "N_e > 32 is not supported");
-    if (precision != DNQS_FP32) return fail(ctx, DNQS_EINVAL, "precision %d not supported", precision);
+    if (!precision_ok(precision))
+        return fail(ctx, DNQS_EINVAL, "precision %d not supported", precision);
     TRY(set_device(ctx));
     Timer tm(ctx, "amp");
     return forward(ctx, sl, nv, theta, dets, n, precision, false, log_abs, sign, nullptr);
@@ -558,7 +609,8 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
     if (conn->M != sl.M || conn->na != sl.na || conn->nb != sl.nb)
         return fail(ctx, DNQS_EINVAL, "connections were built for another sector");
     if (orb_lu_group(sl.na + sl.nb) == 0) return fail(ctx, DNQS_EINVAL, "N_e > 32 is not supported");
-    if (precision != DNQS_FP32) return fail(ctx, DNQS_EINVAL, "precision %d not supported", precision);
+    if (!precision_ok(precision))
+        return fail(ctx, DNQS_EINVAL, "precision %d not supported", precision);
     TRY(set_device(ctx));
     hipStream_t st = ctx->stream;
     const int64_t n = conn->n;
@@ -587,29 +639,24 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
     TRY(ws_t(ctx, "dO", (size_t)n * w[L], &dO));
     launch_det_bwd(st, conn->dets, n, M, sl.na, sl.nb, psi, v, energy, stats, Ainv, dO);
     CHECK_LAUNCH(ctx);
+    const size_t esz = sizeof(float);
     int maxw = 0;
     for (int l = 1; l < L; ++l) maxw = std::max(maxw, w[l]);
-    float *dbuf[2];
-    TRY(ws_t(ctx, "delta0", (size_t)n * maxw, &dbuf[0]));
-    TRY(ws_t(ctx, "delta1", (size_t)n * maxw, &dbuf[1]));
-    const float *delta = dO;  // delta_l, starting at l = L
+    void *dbuf[2];
+    TRY(ws_get(ctx, "delta0", (size_t)n * maxw * esz, &dbuf[0]));
+    TRY(ws_get(ctx, "delta1", (size_t)n * maxw * esz, &dbuf[1]));
+    const void *delta = dO;  // delta_l, starting at l = L
     int which = 0;
     for (int l = L; l >= 1; --l) {
         // [h_{l-1}; 1]^T delta_l -> (dW_l, db_l)
-        const float *hprev = nullptr;
         void *hp = nullptr;
-        if (l == 1) {
-            TRY(ws_get(ctx, "U", 1, &hp));
-        } else {
-            TRY(ws_get(ctx, "h" + std::to_string(l - 1), 1, &hp));
-        }
-        hprev = (const float *)hp;
+        TRY(ws_get(ctx, l == 1 ? std::string("U") : "h" + std::to_string(l - 1), 1, &hp));
         const int din = w[l - 1], dout = w[l];
         GemmArgs g{};
         g.M = din + 1;
         g.N = dout;
         g.K = (int)n;
-        g.A = hprev;
+        g.A = hp;
         g.lda = din;
         g.B = delta;
         g.ldb = dout;
@@ -621,13 +668,13 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
         TRY(ws_t(ctx, "splitk", (size_t)cnt * splits, &partial));
         g.C = partial;
         g.c_split_stride = cnt;
-        launch_gemm_f32(st, g, false, true, EPI_STORE, splits);
+        mlp_gemm(st, precision, l == L, g, false, true, EPI_STORE, splits);
         CHECK_LAUNCH(ctx);
         launch_reduce_splits(st, partial, splits, cnt, grad + nv.offW[l]);
         CHECK_LAUNCH(ctx);
         if (l == 1) break;
         // delta_{l-1} = (delta_l W_l^T) * (1 - h_{l-1}^2)
-        float *dnext = dbuf[which];
+        void *dnext = dbuf[which];
         which ^= 1;
         GemmArgs d{};
         d.M = (int)n;
@@ -639,10 +686,10 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
         d.ldb = dout;
         d.C = dnext;
         d.ldc = din;
-        d.act = hprev;
+        d.act = hp;
         d.ldact = din;
         d.ones_row = -1;
-        launch_gemm_f32(st, d, true, false, EPI_DTANH, 1);
+        mlp_gemm(st, precision, l == L, d, true, false, EPI_DTANH, 1);
         CHECK_LAUNCH(ctx);
         delta = dnext;
     }
@@ -825,6 +872,325 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
     tm.stop();
     HIPCHK(ctx, hipStreamSynchronize(st));
     return DNQS_OK;
+}
+
+namespace {
+
+void plan_free(BatchPlan &b) {
+    for (void *q : {(void *)b.dets, (void *)b.pid, (void *)b.row_ptr, (void *)b.col, (void *)b.val, (void *)b.diag,
+                    (void *)b.tile_pid, (void *)b.ksplit, (void *)b.zoff, (void *)b.P_d, (void *)b.ptr_d})
+        if (q) (void)hipFree(q);
+    b = BatchPlan();
+}
+
+// rows of weight-gradient split-K per work item
+constexpr int64_t kSplitRows = 4096;
+
+dnqs_status plan_build(dnqs_ctx *ctx, int G, const dnqs_problem *pr) {
+    BatchPlan &b = ctx->plan;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    plan_free(b);
+    b.G = G;
+    int64_t off = 0, nnz = 0;
+    for (int g = 0; g < G; ++g) {
+        b.conns.push_back(pr[g].conn);
+        b.off.push_back(off);
+        b.nn.push_back(pr[g].conn->n);
+        off += (pr[g].conn->n + 127) / 128 * 128;
+        nnz += pr[g].conn->nnz;
+    }
+    b.ntot = off;
+    b.nnz = nnz;
+    HIPCHK(ctx, hipMalloc(&b.dets, (size_t)b.ntot * 16));
+    HIPCHK(ctx, hipMalloc(&b.pid, (size_t)b.ntot * 4));
+    HIPCHK(ctx, hipMalloc(&b.row_ptr, (size_t)(b.ntot + 1) * 8));
+    HIPCHK(ctx, hipMalloc(&b.col, (size_t)std::max<int64_t>(nnz, 1) * 4));
+    HIPCHK(ctx, hipMalloc(&b.val, (size_t)std::max<int64_t>(nnz, 1) * 4));
+    HIPCHK(ctx, hipMalloc(&b.diag, (size_t)b.ntot * 8));
+    int64_t nnz_off = 0;
+    for (int g = 0; g < G; ++g) {
+        const dnqs_conn *c = pr[g].conn;
+        const int64_t end = g + 1 < G ? b.off[g + 1] : b.ntot;
+        launch_cat_problem(ctx->stream, g, b.off[g], c->n, end, c->dets, c->row_ptr, c->col, c->val, c->diag, c->nnz,
+                           nnz_off, b.dets, b.pid, b.row_ptr, b.col, b.val, b.diag);
+        CHECK_LAUNCH(ctx);
+        nnz_off += c->nnz;
+    }
+    launch_set_i64(ctx->stream, b.row_ptr + b.ntot, nnz);
+    // tile -> problem, split-K ranges
+    std::vector<int> tp(b.ntot / 128);
+    for (int g = 0; g < G; ++g) {
+        const int64_t end = g + 1 < G ? b.off[g + 1] : b.ntot;
+        for (int64_t t = b.off[g] / 128; t < end / 128; ++t) tp[t] = g;
+    }
+    std::vector<int2> ks;
+    std::vector<int> zo;
+    for (int g = 0; g < G; ++g) {
+        zo.push_back((int)ks.size());
+        for (int64_t r = 0; r < b.nn[g]; r += kSplitRows)
+            ks.push_back(make_int2((int)(b.off[g] + r), (int)(b.off[g] + std::min(b.nn[g], r + kSplitRows))));
+    }
+    zo.push_back((int)ks.size());
+    b.nz = (int)ks.size();
+    HIPCHK(ctx, hipMalloc(&b.tile_pid, tp.size() * sizeof(int)));
+    HIPCHK(ctx, hipMalloc(&b.ksplit, ks.size() * sizeof(int2)));
+    HIPCHK(ctx, hipMalloc(&b.zoff, zo.size() * sizeof(int)));
+    HIPCHK(ctx, hipMemcpyAsync(b.tile_pid, tp.data(), tp.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(b.ksplit, ks.data(), ks.size() * sizeof(int2), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(b.zoff, zo.data(), zo.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMalloc(&b.P_d, (size_t)G * sizeof(ProbDev)));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    b.valid = true;
+    return DNQS_OK;
+}
+
+// refresh the device tables of per-problem pointers if they changed
+dnqs_status plan_pointers(dnqs_ctx *ctx, const NetView &nv, int G, const dnqs_problem *pr) {
+    BatchPlan &b = ctx->plan;
+    std::vector<ProbDev> P(G);
+    for (int g = 0; g < G; ++g) P[g] = {pr[g].theta, pr[g].grad, pr[g].energy, pr[g].stats, b.off[g], b.nn[g]};
+    std::vector<const void *> ptr;
+    for (int l = 0; l <= nv.L; ++l)
+        for (int g = 0; g < G; ++g) ptr.push_back(l == 0 ? nullptr : (const void *)(pr[g].theta + nv.offW[l]));
+    for (int l = 0; l <= nv.L; ++l)
+        for (int g = 0; g < G; ++g) ptr.push_back(l == 0 ? nullptr : (const void *)(pr[g].theta + nv.offb[l]));
+    bool same = b.P_h.size() == P.size() && b.ptr_h == ptr && b.ptr_layers == nv.L;
+    for (int g = 0; same && g < G; ++g)
+        same = !std::memcmp(&b.P_h[g], &P[g], sizeof(ProbDev));
+    if (same) return DNQS_OK;
+    if (ctx->capturing) return fail(ctx, DNQS_ESTATE, "batched pointers changed during graph capture");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (b.ptr_d) HIPCHK(ctx, hipFree(b.ptr_d));
+    b.ptr_d = nullptr;
+    HIPCHK(ctx, hipMalloc(&b.ptr_d, ptr.size() * sizeof(void *)));
+    b.P_h = P;
+    b.ptr_h = ptr;
+    b.ptr_layers = nv.L;
+    HIPCHK(ctx, hipMemcpyAsync(b.P_d, b.P_h.data(), G * sizeof(ProbDev), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(b.ptr_d, b.ptr_h.data(), ptr.size() * sizeof(void *), hipMemcpyHostToDevice,
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return DNQS_OK;
+}
+
+}  // namespace
+
+dnqs_status dnqs_energy_and_grad_batched(dnqs_ctx *ctx, const dnqs_net *net, int G, const dnqs_problem *pr,
+                                         int precision, unsigned flags) {
+    (void)flags;
+    if (!ctx) return DNQS_EINVAL;
+    if (!pr || G < 1 || G > DNQS_MAX_SLOTS) return fail(ctx, DNQS_EINVAL, "n_problems = %d out of range", G);
+    if (!precision_ok(precision))
+        return fail(ctx, DNQS_EINVAL, "precision %d not supported", precision);
+    TRY(check_slot(ctx, pr[0].slot));
+    const Slot &s0 = ctx->slots[pr[0].slot];
+    NetView nv;
+    TRY(net_view(ctx, net, s0.M, s0.na, s0.nb, &nv));
+    const bool want_grad = pr[0].grad != nullptr;
+    for (int g = 0; g < G; ++g) {
+        TRY(check_slot(ctx, pr[g].slot));
+        const Slot &sg = ctx->slots[pr[g].slot];
+        if (!pr[g].conn || !pr[g].theta || !pr[g].energy || !pr[g].stats)
+            return fail(ctx, DNQS_EINVAL, "problem %d: NULL pointer", g);
+        if (sg.M != s0.M || sg.na != s0.na || sg.nb != s0.nb || pr[g].conn->M != s0.M || pr[g].conn->na != s0.na ||
+            pr[g].conn->nb != s0.nb)
+            return fail(ctx, DNQS_EINVAL, "problem %d: sector differs from problem 0", g);
+        if ((pr[g].grad != nullptr) != want_grad) return fail(ctx, DNQS_EINVAL, "grad must be given for all or none");
+    }
+    if (orb_lu_group(s0.na + s0.nb) == 0) return fail(ctx, DNQS_EINVAL, "N_e > 32 is not supported");
+    TRY(set_device(ctx));
+    BatchPlan &b = ctx->plan;
+    bool same = b.valid && b.G == G;
+    for (int g = 0; same && g < G; ++g) same = b.conns[g] == pr[g].conn && b.nn[g] == pr[g].conn->n;
+    if (!same) {
+        if (ctx->capturing) return fail(ctx, DNQS_ESTATE, "a new batch cannot be planned during graph capture");
+        TRY(plan_build(ctx, G, pr));
+    }
+    TRY(plan_pointers(ctx, nv, G, pr));
+    hipStream_t st = ctx->stream;
+    Timer tm(ctx, "egrad_batched");
+    const size_t esz = sizeof(float);
+    const int M = s0.M, No = 2 * M, Ne = s0.na + s0.nb, L = nv.L;
+    const int *w = nv.w;
+    const int64_t n = b.ntot;
+    const RowProblems rp{b.pid, b.P_d};
+    auto Wg = [&](int l) { return (const void *const *)(b.ptr_d + (size_t)l * G); };
+    auto bg = [&](int l) { return (const float *const *)(b.ptr_d + (size_t)(L + 1 + l) * G); };
+    // ---- forward
+    void *U = nullptr, *h = nullptr;
+    if (want_grad) TRY(ws_get(ctx, "bU", (size_t)n * No * esz, &U));
+    TRY(ws_get(ctx, "bh1", (size_t)n * w[1] * esz, &h));
+    launch_embed(st, b.dets, n, M, w[1], nullptr, nullptr, (float *)h, (float *)U, rp, nv.offW[1], nv.offb[1]);
+    CHECK_LAUNCH(ctx);
+    void *prev = h;
+    for (int l = 2; l <= L; ++l) {
+        void *out = nullptr;
+        if (l < L)
+            TRY(ws_get(ctx, "bh" + std::to_string(l), (size_t)n * w[l] * esz, &out));
+        else
+            TRY(ws_get(ctx, "bO", (size_t)n * w[l] * sizeof(float), &out));
+        GemmArgs g{};
+        g.M = (int)n;
+        g.N = w[l];
+        g.K = w[l - 1];
+        g.A = prev;
+        g.lda = w[l - 1];
+        g.ldb = w[l];
+        g.C = out;
+        g.ldc = w[l];
+        g.ones_row = -1;
+        g.tile_pid = b.tile_pid;
+        g.Bg = Wg(l);
+        g.biasg = bg(l);
+        mlp_gemm(st, precision, l == L, g, true, true, l < L ? EPI_BIAS_TANH : EPI_BIAS, 1);
+        CHECK_LAUNCH(ctx);
+        prev = out;
+    }
+    double *la = nullptr, *psi = nullptr, *v = nullptr, *pv = nullptr, *pp = nullptr;
+    int8_t *sg = nullptr;
+    float *Ainv = nullptr;
+    TRY(ws_t(ctx, "b_la", (size_t)n, &la));
+    TRY(ws_t(ctx, "b_sg", (size_t)n, &sg));
+    TRY(ws_t(ctx, "b_psi", (size_t)n, &psi));
+    TRY(ws_t(ctx, "b_v", (size_t)n, &v));
+    TRY(ws_t(ctx, "b_pv", (size_t)n, &pv));
+    TRY(ws_t(ctx, "b_pp", (size_t)n, &pp));
+    if (want_grad) TRY(ws_t(ctx, "b_Ainv", (size_t)n * Ne * Ne, &Ainv));
+    launch_orb_lu(st, b.dets, n, M, s0.na, s0.nb, (const float *)prev, nullptr, la, sg, Ainv, rp, nv.offPhi0);
+    CHECK_LAUNCH(ctx);
+    launch_energy_grouped(st, la, sg, n, G, rp, b.row_ptr, b.col, b.val, b.diag, psi, v, pv, pp);
+    CHECK_LAUNCH(ctx);
+    if (!want_grad) return DNQS_OK;
+    // ---- adjoint
+    float *dO = nullptr;
+    TRY(ws_t(ctx, "b_dO", (size_t)n * w[L], &dO));
+    launch_det_bwd(st, b.dets, n, M, s0.na, s0.nb, psi, v, nullptr, nullptr, Ainv, dO, rp);
+    CHECK_LAUNCH(ctx);
+    int maxw = 0;
+    for (int l = 1; l < L; ++l) maxw = std::max(maxw, w[l]);
+    void *dbuf[2];
+    TRY(ws_get(ctx, "b_delta0", (size_t)n * maxw * esz, &dbuf[0]));
+    TRY(ws_get(ctx, "b_delta1", (size_t)n * maxw * esz, &dbuf[1]));
+    const void *delta = dO;
+    int which = 0;
+    for (int l = L; l >= 1; --l) {
+        void *hp = nullptr;
+        TRY(ws_get(ctx, l == 1 ? std::string("bU") : "bh" + std::to_string(l - 1), 1, &hp));
+        const int din = w[l - 1], dout = w[l];
+        GemmArgs g{};
+        g.M = din + 1;
+        g.N = dout;
+        g.K = (int)n;
+        g.A = hp;
+        g.lda = din;
+        g.B = delta;
+        g.ldb = dout;
+        g.ldc = dout;
+        g.ones_row = din;
+        g.ksplit = b.ksplit;
+        float *partial = nullptr;
+        const int64_t cnt = (int64_t)(din + 1) * dout;
+        TRY(ws_t(ctx, "b_splitk", (size_t)cnt * b.nz, &partial));
+        g.C = partial;
+        g.c_split_stride = cnt;
+        mlp_gemm(st, precision, l == L, g, false, true, EPI_STORE, b.nz);
+        CHECK_LAUNCH(ctx);
+        launch_reduce_splits_grouped(st, partial, b.zoff, cnt, G, b.P_d, nv.offW[l]);
+        CHECK_LAUNCH(ctx);
+        if (l == 1) break;
+        void *dnext = dbuf[which];
+        which ^= 1;
+        GemmArgs d{};
+        d.M = (int)n;
+        d.N = din;
+        d.K = dout;
+        d.A = delta;
+        d.lda = dout;
+        d.ldb = dout;
+        d.C = dnext;
+        d.ldc = din;
+        d.act = hp;
+        d.ldact = din;
+        d.ones_row = -1;
+        d.tile_pid = b.tile_pid;
+        d.Bg = Wg(l);
+        mlp_gemm(st, precision, l == L, d, true, false, EPI_DTANH, 1);
+        CHECK_LAUNCH(ctx);
+        delta = dnext;
+    }
+    launch_copy_grouped(st, b.P_d, G, nv.offb[L], nv.offPhi0, (int64_t)No * Ne);
+    CHECK_LAUNCH(ctx);
+    return DNQS_OK;
+}
+
+dnqs_status dnqs_adamw_batched(dnqs_ctx *ctx, const dnqs_net *net, int G, const dnqs_problem *pr, float *m, float *v,
+                               const dnqs_adamw_cfg *cfg, int *step) {
+    if (!ctx) return DNQS_EINVAL;
+    if (!pr || G < 1 || G > DNQS_MAX_SLOTS || !m || !v || !cfg || !step)
+        return fail(ctx, DNQS_EINVAL, "bad argument");
+    if (cfg->decay_steps < 1 || !(cfg->eps > 0.0f)) return fail(ctx, DNQS_EINVAL, "bad AdamW configuration");
+    TRY(check_slot(ctx, pr[0].slot));
+    const Slot &s0 = ctx->slots[pr[0].slot];
+    NetView nv;
+    TRY(net_view(ctx, net, s0.M, s0.na, s0.nb, &nv));
+    BatchPlan &b = ctx->plan;
+    bool same = b.valid && b.G == G;
+    for (int g = 0; same && g < G; ++g) same = b.conns[g] == pr[g].conn;
+    if (!same) return fail(ctx, DNQS_ESTATE, "call dnqs_energy_and_grad_batched with these problems first");
+    for (int g = 0; g < G; ++g)
+        if (!pr[g].grad || !pr[g].theta) return fail(ctx, DNQS_EINVAL, "problem %d: theta and grad needed", g);
+    TRY(set_device(ctx));
+    TRY(plan_pointers(ctx, nv, G, pr));
+    AdamCfg c{cfg->lr_max, cfg->lr_min, cfg->decay_steps, cfg->beta1, cfg->beta2, cfg->eps, cfg->weight_decay};
+    launch_adamw_grouped(ctx->stream, b.P_d, G, m, v, nv.total, c, step);
+    CHECK_LAUNCH(ctx);
+    return DNQS_OK;
+}
+
+dnqs_status dnqs_capture_begin(dnqs_ctx *ctx) {
+    if (!ctx) return DNQS_EINVAL;
+    if (!ctx->stream) return fail(ctx, DNQS_ESTATE, "graph capture needs a non-null stream");
+    if (ctx->capturing) return fail(ctx, DNQS_ESTATE, "already capturing");
+    TRY(set_device(ctx));
+    HIPCHK(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    ctx->capturing = true;
+    return DNQS_OK;
+}
+
+dnqs_status dnqs_capture_end(dnqs_ctx *ctx, dnqs_graph **out) {
+    if (!ctx) return DNQS_EINVAL;
+    if (!out) return fail(ctx, DNQS_EINVAL, "out is NULL");
+    if (!ctx->capturing) return fail(ctx, DNQS_ESTATE, "not capturing");
+    ctx->capturing = false;
+    hipGraph_t g = nullptr;
+    HIPCHK(ctx, hipStreamEndCapture(ctx->stream, &g));
+    dnqs_graph *dg = new dnqs_graph();
+    dg->graph = g;
+    dg->device = ctx->device;
+    hipError_t e = hipGraphInstantiate(&dg->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        delete dg;
+        return fail(ctx, DNQS_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    *out = dg;
+    return DNQS_OK;
+}
+
+dnqs_status dnqs_graph_launch(dnqs_ctx *ctx, dnqs_graph *graph) {
+    if (!ctx) return DNQS_EINVAL;
+    if (!graph) return fail(ctx, DNQS_EINVAL, "graph is NULL");
+    TRY(set_device(ctx));
+    HIPCHK(ctx, hipGraphLaunch(graph->exec, ctx->stream));
+    return DNQS_OK;
+}
+
+void dnqs_graph_free(dnqs_graph *graph) {
+    if (!graph) return;
+    (void)hipSetDevice(graph->device);
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    delete graph;
 }
 
 dnqs_status dnqs_timing_enable(dnqs_ctx *ctx, int on) {

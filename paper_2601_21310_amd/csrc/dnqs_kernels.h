@@ -34,32 +34,82 @@ enum { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_TANH = 2, EPI_DTANH = 3 };
 // C[M x N] (+ split index * c_split_stride) = epi(A[M x K] * B[K x N])
 //   A: a_kcontig ? A[m*lda + k] : A[k*lda + m]     (rows m >= ones_row >= 0 read as 1)
 //   B: b_ncontig ? B[k*ldb + n] : B[n*ldb + k]
+// Element types are fixed by the kernel that takes the struct; the pointers are untyped.
 struct GemmArgs {
     int M, N, K;
-    const float *A;
+    const void *A;
     int64_t lda;
-    const float *B;
+    const void *B;
     int64_t ldb;
-    float *C;
+    void *C;
     int64_t ldc;
     const float *bias;
-    const float *act;
+    const void *act;
     int64_t ldact;
     int ones_row;
     int k_chunk;
     int64_t c_split_stride;
+    // grouped launches over several problems (batched geometries), all optional:
+    const int *tile_pid;        // problem of each 128-row tile: B = Bg[pid], bias = biasg[pid]
+    const void *const *Bg;
+    const float *const *biasg;
+    const int2 *ksplit;         // k range [x, y) of each blockIdx.z (split-K over problems)
+};
+
+// One problem of a batched launch (rows off .. off+n-1 of the concatenated layout;
+// rows from off+n to the next problem's off are padding and contribute nothing).
+struct ProbDev {
+    const float *theta;
+    float *grad;
+    double *energy;
+    double *stats;
+    int64_t off, n;
+};
+
+// Optional per-row problem lookup: with pid != nullptr, row x belongs to problem
+// pid[x] and its parameters are P[pid[x]].theta + the given offsets.
+struct RowProblems {
+    const int32_t *pid;
+    const ProbDev *P;
 };
 
 void launch_embed(hipStream_t st, const uint64_t *dets, int64_t n, int M, int d1, const float *W1, const float *b1,
-                  float *h1, float *U);
+                  float *h1, float *U, RowProblems rp = {}, int64_t offW1 = 0, int64_t offb1 = 0);
+// C = epi(A B): FP32 MFMA, or split-BF16 MFMA (three BF16 products per operand pair);
+// same arguments and layouts for both
 void launch_gemm_f32(hipStream_t st, const GemmArgs &g, bool a_kcontig, bool b_ncontig, int epi, int splits);
+void launch_gemm_x3(hipStream_t st, const GemmArgs &g, bool a_kcontig, bool b_ncontig, int epi, int splits);
 void launch_reduce_splits(hipStream_t st, const float *part, int splits, int64_t count, float *out);
 int orb_lu_group(int ne);
 void launch_orb_lu(hipStream_t st, const uint64_t *dets, int64_t n, int M, int na, int nb, const float *O,
-                   const float *Phi0, double *logabs, int8_t *sign, float *Ainv);
+                   const float *Phi0, double *logabs, int8_t *sign, float *Ainv, RowProblems rp = {},
+                   int64_t offPhi0 = 0);
 void launch_det_bwd(hipStream_t st, const uint64_t *dets, int64_t n, int M, int na, int nb, const double *psi,
-                    const double *v, const double *energy, const double *stats, const float *Ainv, float *dO);
+                    const double *v, const double *energy, const double *stats, const float *Ainv, float *dO,
+                    RowProblems rp = {});
 void launch_copy_f32(hipStream_t st, const float *x, float *y, int64_t n);
+
+// ---------------------------------------------------------------- batched problems, optimiser
+struct AdamCfg {
+    float lr_max, lr_min;
+    int decay_steps;
+    float beta1, beta2, eps, weight_decay;
+};
+void launch_adamw(hipStream_t st, float *theta, const float *grad, float *m, float *v, int64_t n, const AdamCfg &c,
+                  int *step);
+void launch_cat_problem(hipStream_t st, int g, int64_t off, int64_t n, int64_t end, const uint64_t *dets,
+                        const int64_t *row_ptr, const int32_t *col, const float *val, const double *diag, int64_t nnz,
+                        int64_t nnz_off, uint64_t *dets_cat, int32_t *pid, int64_t *row_ptr_cat, int32_t *col_cat,
+                        float *val_cat, double *diag_cat);
+void launch_set_i64(hipStream_t st, int64_t *p, int64_t v);
+void launch_energy_grouped(hipStream_t st, const double *la, const int8_t *sg, int64_t ntot, int G, RowProblems rp,
+                           const int64_t *row_ptr, const int32_t *col, const float *val, const double *diag,
+                           double *psi, double *v, double *pv, double *pp);
+void launch_reduce_splits_grouped(hipStream_t st, const float *part, const int *zoff, int64_t cnt, int G,
+                                  const ProbDev *P, int64_t off);
+void launch_copy_grouped(hipStream_t st, const ProbDev *P, int G, int64_t src, int64_t dst, int64_t cnt);
+void launch_adamw_grouped(hipStream_t st, const ProbDev *P, int G, float *m, float *v, int64_t np, const AdamCfg &c,
+                          int *step);
 
 // ---------------------------------------------------------------- energy
 int reduce_blocks(int64_t n);

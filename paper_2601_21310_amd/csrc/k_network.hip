@@ -19,12 +19,19 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int kEmbedCfg = 4;  // configurations per workgroup
 
 __global__ __launch_bounds__(256) void k_embed(const uint64_t *__restrict__ dets, int64_t n, int M, int d1,
-                                               const float *__restrict__ W1, const float *__restrict__ b1,
-                                               float *__restrict__ h1, float *__restrict__ U) {
+                                               const float *__restrict__ W1g, const float *__restrict__ b1g,
+                                               float *__restrict__ h1, float *__restrict__ U, RowProblems rp,
+                                               int64_t offW1, int64_t offb1) {
     const int No = 2 * M;
     for (int i = 0; i < kEmbedCfg; ++i) {
         const int64_t x = (int64_t)blockIdx.x * kEmbedCfg + i;
         if (x >= n) return;
+        const float *W1 = W1g, *b1 = b1g;
+        if (rp.pid) {
+            const float *th = rp.P[rp.pid[x]].theta;
+            W1 = th + offW1;
+            b1 = th + offb1;
+        }
         const uint64_t a = dets[2 * x], b = dets[2 * x + 1];
         for (int c = threadIdx.x; c < d1; c += blockDim.x) {
             float s = b1[c];
@@ -53,9 +60,9 @@ __global__ __launch_bounds__(256) void k_embed(const uint64_t *__restrict__ dets
 }
 
 void launch_embed(hipStream_t st, const uint64_t *dets, int64_t n, int M, int d1, const float *W1, const float *b1,
-                  float *h1, float *U) {
-    hipLaunchKernelGGL(k_embed, dim3((unsigned)((n + kEmbedCfg - 1) / kEmbedCfg)), dim3(256), 0, st, dets, n, M,
-                       d1, W1, b1, h1, U);
+                  float *h1, float *U, RowProblems rp, int64_t offW1, int64_t offb1) {
+    dim3 grid((unsigned)((n + kEmbedCfg - 1) / kEmbedCfg));
+    hipLaunchKernelGGL(k_embed, grid, dim3(256), 0, st, dets, n, M, d1, W1, b1, h1, U, rp, offW1, offb1);
 }
 
 // ------------------------------------------------------------------ FP32 MFMA GEMM
@@ -73,38 +80,39 @@ __device__ __forceinline__ int xcd_remap(int L, int total) {
     return (L % nx) * per + (L / nx);
 }
 
+// 8 consecutive floats at p; `ok(j)` says whether element j is in range.  Vector loads
+// when all 8 are in range and the address is 16-byte aligned.
+template <typename OK>
+__device__ __forceinline__ void load8(const float *p, bool full, OK ok, float (&r)[8]) {
+    if (full && ((((uintptr_t)p) & 15) == 0)) {
+        const v4f u = *(const v4f *)p, w = *(const v4f *)(p + 4);
+        r[0] = u[0]; r[1] = u[1]; r[2] = u[2]; r[3] = u[3];
+        r[4] = w[0]; r[5] = w[1]; r[6] = w[2]; r[7] = w[3];
+    } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) r[j] = ok(j) ? p[j] : 0.0f;
+    }
+}
+
 template <bool A_KCONTIG>
 __device__ __forceinline__ void load_a_tile(const GemmArgs &g, int m0, int k0, int kend, float (&r)[8]) {
     const int t = threadIdx.x;
     const int mload = g.ones_row >= 0 ? g.ones_row : g.M;
+    const float *A = (const float *)g.A;
     if (A_KCONTIG) {  // A[m*lda + k]; thread: one m, 8 consecutive k
         const int m = m0 + (t >> 1), k = k0 + (t & 1) * 8;
-        const float *p = g.A + (int64_t)m * g.lda + k;
-        const bool full = m < mload && k + 8 <= kend && ((g.lda & 3) == 0) && ((((uintptr_t)p) & 15) == 0);
-        if (full) {
-            v4f u = *(const v4f *)p, w = *(const v4f *)(p + 4);
-            r[0] = u[0]; r[1] = u[1]; r[2] = u[2]; r[3] = u[3];
-            r[4] = w[0]; r[5] = w[1]; r[6] = w[2]; r[7] = w[3];
-        } else {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) r[j] = (m < mload && k + j < kend) ? p[j] : 0.0f;
-        }
+        const float *p = A + (int64_t)m * g.lda + k;
+        const bool full = m < mload && k + 8 <= kend && (g.lda & 3) == 0;
+        load8(p, full, [&](int j) { return m < mload && k + j < kend; }, r);
         if (m == g.ones_row) {
 #pragma unroll
             for (int j = 0; j < 8; ++j) r[j] = (k + j < kend) ? 1.0f : 0.0f;
         }
     } else {  // A[k*lda + m]; thread: one k, 8 consecutive m
         const int k = k0 + (t >> 4), m = m0 + (t & 15) * 8;
-        const float *p = g.A + (int64_t)k * g.lda + m;
-        const bool full = k < kend && m + 8 <= mload && ((g.lda & 3) == 0) && ((((uintptr_t)p) & 15) == 0);
-        if (full) {
-            v4f u = *(const v4f *)p, w = *(const v4f *)(p + 4);
-            r[0] = u[0]; r[1] = u[1]; r[2] = u[2]; r[3] = u[3];
-            r[4] = w[0]; r[5] = w[1]; r[6] = w[2]; r[7] = w[3];
-        } else {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) r[j] = (k < kend && m + j < mload) ? p[j] : 0.0f;
-        }
+        const float *p = A + (int64_t)k * g.lda + m;
+        const bool full = k < kend && m + 8 <= mload && (g.lda & 3) == 0;
+        load8(p, full, [&](int j) { return k < kend && m + j < mload; }, r);
         if (g.ones_row >= 0) {
 #pragma unroll
             for (int j = 0; j < 8; ++j)
@@ -130,30 +138,17 @@ __device__ __forceinline__ void store_a_tile(float (*As)[LDS_A], const float (&r
 template <bool B_NCONTIG>
 __device__ __forceinline__ void load_b_tile(const GemmArgs &g, int n0, int k0, int kend, float (&r)[8]) {
     const int t = threadIdx.x;
+    const float *B = (const float *)g.B;
     if (B_NCONTIG) {  // B[k*ldb + n]
         const int k = k0 + (t >> 4), n = n0 + (t & 15) * 8;
-        const float *p = g.B + (int64_t)k * g.ldb + n;
-        const bool full = k < kend && n + 8 <= g.N && ((g.ldb & 3) == 0) && ((((uintptr_t)p) & 15) == 0);
-        if (full) {
-            v4f u = *(const v4f *)p, w = *(const v4f *)(p + 4);
-            r[0] = u[0]; r[1] = u[1]; r[2] = u[2]; r[3] = u[3];
-            r[4] = w[0]; r[5] = w[1]; r[6] = w[2]; r[7] = w[3];
-        } else {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) r[j] = (k < kend && n + j < g.N) ? p[j] : 0.0f;
-        }
+        const float *p = B + (int64_t)k * g.ldb + n;
+        const bool full = k < kend && n + 8 <= g.N && (g.ldb & 3) == 0;
+        load8(p, full, [&](int j) { return k < kend && n + j < g.N; }, r);
     } else {  // B[n*ldb + k]
         const int n = n0 + (t >> 1), k = k0 + (t & 1) * 8;
-        const float *p = g.B + (int64_t)n * g.ldb + k;
-        const bool full = n < g.N && k + 8 <= kend && ((g.ldb & 3) == 0) && ((((uintptr_t)p) & 15) == 0);
-        if (full) {
-            v4f u = *(const v4f *)p, w = *(const v4f *)(p + 4);
-            r[0] = u[0]; r[1] = u[1]; r[2] = u[2]; r[3] = u[3];
-            r[4] = w[0]; r[5] = w[1]; r[6] = w[2]; r[7] = w[3];
-        } else {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) r[j] = (n < g.N && k + j < kend) ? p[j] : 0.0f;
-        }
+        const float *p = B + (int64_t)n * g.ldb + k;
+        const bool full = n < g.N && k + 8 <= kend && (g.ldb & 3) == 0;
+        load8(p, full, [&](int j) { return n < g.N && k + j < kend; }, r);
     }
 }
 
@@ -171,16 +166,27 @@ __device__ __forceinline__ void store_b_tile(float (*Bs)[LDS_B], const float (&r
     }
 }
 
+// FP32 MFMA GEMM, operands and output in FP32.
 template <bool A_KCONTIG, bool B_NCONTIG, int EPI>
-__global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g) {
+__global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g0) {
+    GemmArgs g = g0;
     __shared__ float As[BK][LDS_A];
     __shared__ float Bs[BK][LDS_B];
     const int tiles_n = (g.N + BN - 1) / BN;
     const int tiles_m = (g.M + BM - 1) / BM;
     const int L = xcd_remap(blockIdx.x, tiles_n * tiles_m);
     const int m0 = (L / tiles_n) * BM, n0 = (L % tiles_n) * BN;
-    const int kbeg = blockIdx.z * g.k_chunk;
+    if (g.tile_pid) {
+        const int pg = g.tile_pid[L / tiles_n];
+        g.B = g.Bg[pg];
+        if (g.biasg) g.bias = g.biasg[pg];
+    }
+    int kbeg = blockIdx.z * g.k_chunk;
     int kend = kbeg + g.k_chunk;
+    if (g.ksplit) {
+        kbeg = g.ksplit[blockIdx.z].x;
+        kend = g.ksplit[blockIdx.z].y;
+    }
     if (kend > g.K) kend = g.K;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
@@ -220,7 +226,8 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g) {
             acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
         }
     }
-    float *C = g.C + (int64_t)blockIdx.z * g.c_split_stride;
+    float *C = (float *)g.C + (int64_t)blockIdx.z * g.c_split_stride;
+    const float *act = (const float *)g.act;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -236,7 +243,7 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g) {
                 if (EPI == EPI_BIAS) v += bias;
                 if (EPI == EPI_BIAS_TANH) v = tanhf(v + bias);
                 if (EPI == EPI_DTANH) {
-                    float hv = g.act[(int64_t)row * g.ldact + col];
+                    float hv = act[(int64_t)row * g.ldact + col];
                     v *= (1.0f - hv * hv);
                 }
                 C[(int64_t)row * g.ldc + col] = v;
@@ -250,18 +257,22 @@ static void launch_gemm_t(hipStream_t st, const GemmArgs &g, int splits) {
     hipLaunchKernelGGL((k_gemm_f32<AK, BN_, EPI>), dim3(tiles, 1, splits), dim3(256), 0, st, g);
 }
 
+static int split_chunk(int K, int splits) {
+    int chunk = (K + splits - 1) / splits;
+    chunk = (chunk + BK - 1) / BK * BK;
+    return chunk > 0 ? chunk : BK;
+}
+
 void launch_gemm_f32(hipStream_t st, const GemmArgs &g0, bool a_kcontig, bool b_ncontig, int epi, int splits) {
     GemmArgs g = g0;
     if (splits < 1) splits = 1;
-    int chunk = (g.K + splits - 1) / splits;
-    chunk = (chunk + BK - 1) / BK * BK;
-    g.k_chunk = chunk > 0 ? chunk : BK;
-#define DISPATCH(AK, BNC)                                                     \
-    switch (epi) {                                                            \
-        case EPI_STORE: launch_gemm_t<AK, BNC, EPI_STORE>(st, g, splits); break; \
-        case EPI_BIAS: launch_gemm_t<AK, BNC, EPI_BIAS>(st, g, splits); break;   \
+    g.k_chunk = split_chunk(g.K, splits);
+#define DISPATCH(AK, BNC)                                                                               \
+    switch (epi) {                                                                                      \
+        case EPI_STORE: launch_gemm_t<AK, BNC, EPI_STORE>(st, g, splits); break;   \
+        case EPI_BIAS: launch_gemm_t<AK, BNC, EPI_BIAS>(st, g, splits); break;     \
         case EPI_BIAS_TANH: launch_gemm_t<AK, BNC, EPI_BIAS_TANH>(st, g, splits); break; \
-        case EPI_DTANH: launch_gemm_t<AK, BNC, EPI_DTANH>(st, g, splits); break; \
+        case EPI_DTANH: launch_gemm_t<AK, BNC, EPI_DTANH>(st, g, splits); break;   \
     }
     if (a_kcontig && b_ncontig) { DISPATCH(true, true) }
     else if (a_kcontig && !b_ncontig) { DISPATCH(true, false) }
@@ -300,9 +311,9 @@ __device__ __forceinline__ int occupied_so(uint64_t a, uint64_t b, int M, int na
 // G lanes per configuration; lane r of a group holds row r of [A | I].
 template <int G>
 __global__ __launch_bounds__(256) void k_orb_lu(const uint64_t *__restrict__ dets, int64_t n, int M, int na, int nb,
-                                                const float *__restrict__ O, const float *__restrict__ Phi0,
+                                                const float *__restrict__ O, const float *__restrict__ Phi0g,
                                                 double *__restrict__ logabs, int8_t *__restrict__ sign,
-                                                float *__restrict__ Ainv) {
+                                                float *__restrict__ Ainv, RowProblems rp, int64_t offPhi0) {
     const int Ne = na + nb, No = 2 * M;
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t x = gt / G;
@@ -319,6 +330,7 @@ __global__ __launch_bounds__(256) void k_orb_lu(const uint64_t *__restrict__ det
         const uint64_t da = dets[2 * x], db = dets[2 * x + 1];
         const int p = occupied_so(da, db, M, na, r);
         const float *orow = O + x * (int64_t)(No * Ne) + (int64_t)p * Ne;
+        const float *Phi0 = rp.pid ? rp.P[rp.pid[x]].theta + offPhi0 : Phi0g;
         const float *prow = Phi0 + (int64_t)p * Ne;
 #pragma unroll
         for (int c = 0; c < G; ++c)
@@ -395,19 +407,19 @@ __global__ __launch_bounds__(256) void k_orb_lu(const uint64_t *__restrict__ det
 int orb_lu_group(int ne) { return ne <= 8 ? 8 : ne <= 16 ? 16 : ne <= 32 ? 32 : 0; }
 
 void launch_orb_lu(hipStream_t st, const uint64_t *dets, int64_t n, int M, int na, int nb, const float *O,
-                   const float *Phi0, double *logabs, int8_t *sign, float *Ainv) {
+                   const float *Phi0, double *logabs, int8_t *sign, float *Ainv, RowProblems rp, int64_t offPhi0) {
     const int G = orb_lu_group(na + nb);
     const int64_t threads = n * G;
     const unsigned blocks = (unsigned)((threads + 255) / 256);
     if (G == 8)
         hipLaunchKernelGGL(k_orb_lu<8>, dim3(blocks), dim3(256), 0, st, dets, n, M, na, nb, O, Phi0, logabs, sign,
-                           Ainv);
+                           Ainv, rp, offPhi0);
     else if (G == 16)
         hipLaunchKernelGGL(k_orb_lu<16>, dim3(blocks), dim3(256), 0, st, dets, n, M, na, nb, O, Phi0, logabs, sign,
-                           Ainv);
+                           Ainv, rp, offPhi0);
     else
         hipLaunchKernelGGL(k_orb_lu<32>, dim3(blocks), dim3(256), 0, st, dets, n, M, na, nb, O, Phi0, logabs, sign,
-                           Ainv);
+                           Ainv, rp, offPhi0);
 }
 
 // ------------------------------------------------------------------ det backward + scatter
@@ -418,14 +430,24 @@ __global__ __launch_bounds__(256) void k_det_bwd(const uint64_t *__restrict__ de
                                                  int nb, const double *__restrict__ psi,
                                                  const double *__restrict__ v, const double *__restrict__ energy,
                                                  const double *__restrict__ stats, const float *__restrict__ Ainv,
-                                                 float *__restrict__ dO) {
+                                                 float *__restrict__ dO, RowProblems rp) {
     const int Ne = na + nb, No = 2 * M;
     const int width = No * Ne;
-    const double E = energy[0], norm = stats[0];
-    const bool ok = norm > 0.0 && isfinite(E);
     for (int i = 0; i < kBwdCfg; ++i) {
         const int64_t x = (int64_t)blockIdx.x * kBwdCfg + i;
         if (x >= n) return;
+        double E, norm;
+        bool pad = false;
+        if (rp.pid) {
+            const ProbDev &P = rp.P[rp.pid[x]];
+            E = P.energy[0];
+            norm = P.stats[0];
+            pad = x - P.off >= P.n;
+        } else {
+            E = energy[0];
+            norm = stats[0];
+        }
+        const bool ok = norm > 0.0 && isfinite(E) && !pad;
         const uint64_t a = dets[2 * x], b = dets[2 * x + 1];
         const double px = psi[x];
         const float c = ok ? (float)(2.0 * (v[x] - E * px) * px / norm) : 0.0f;
@@ -445,9 +467,10 @@ __global__ __launch_bounds__(256) void k_det_bwd(const uint64_t *__restrict__ de
 }
 
 void launch_det_bwd(hipStream_t st, const uint64_t *dets, int64_t n, int M, int na, int nb, const double *psi,
-                    const double *v, const double *energy, const double *stats, const float *Ainv, float *dO) {
+                    const double *v, const double *energy, const double *stats, const float *Ainv, float *dO,
+                    RowProblems rp) {
     hipLaunchKernelGGL(k_det_bwd, dim3((unsigned)((n + kBwdCfg - 1) / kBwdCfg)), dim3(256), 0, st, dets, n, M, na,
-                       nb, psi, v, energy, stats, Ainv, dO);
+                       nb, psi, v, energy, stats, Ainv, dO, rp);
 }
 
 // y[i] = x[i]

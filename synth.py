@@ -342,3 +342,26 @@ def make_problem(wl: Workload, n_dets: int | None = None, out_scale: float = 1.0
     theta = init_theta(wl.widths, wl.M, wl.n_alpha, wl.n_beta, ra, rb, 2000 + s, 3000 + s,
                        out_scale=out_scale, bias_scale=bias_scale)
     return Problem(wl, h, eri, ec, ra, rb, dets, theta)
+
+
+def make_curve(wl: Workload, n_geoms: int = 64, size_lo: int = 10, size_hi: int = 16, out_scale: float = 1e-2,
+               sizes=None) -> list:
+    """A synthetic dissociation curve: integrals (1-t) A + t B between two seeded
+    endpoint sets, t = g / (n_geoms - 1); |S_g| = round(2^(size_lo + (size_hi - size_lo) u_g))
+    with u_g ~ U(0, 1) (or the given sizes); an independent theta per geometry."""
+    s = wl.seed
+    hA, eA, _ = make_integrals(wl.M, wl.rank, 1000 + 10 * s + 1, lattice=wl.lattice, xi=wl.xi)
+    hB, eB, _ = make_integrals(wl.M, wl.rank, 1000 + 10 * s + 2, lattice=wl.lattice, xi=wl.xi)
+    rng = np.random.default_rng(4000 + 10 * s)
+    if sizes is None:
+        sizes = [int(round(2.0 ** (size_lo + (size_hi - size_lo) * u))) for u in rng.uniform(size=n_geoms)]
+    out = []
+    for g in range(n_geoms):
+        t = g / max(n_geoms - 1, 1)
+        h, eri = interpolate_integrals(hA, eA, hB, eB, t)
+        ra, rb = reference_occupation(h, wl.n_alpha, wl.n_beta)
+        dets = sample_dets(wl.M, wl.n_alpha, wl.n_beta, ra, rb, int(sizes[g]), 4000 + 100 * s + g)
+        theta = init_theta(wl.widths, wl.M, wl.n_alpha, wl.n_beta, ra, rb, 2000 + 100 * s + g, 3000 + 100 * s + g,
+                           out_scale=out_scale)
+        out.append(Problem(wl, h, eri, 0.0, ra, rb, dets, theta, {"t": t}))
+    return out

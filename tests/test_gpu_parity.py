@@ -228,3 +228,74 @@ def test_invalid_inputs_rejected(dnqs, ctx):
         ctx.build_connections(dnqs.dets_to_device(dup))
     with pytest.raises(dnqs.DnqsError, match="ESTATE"):
         ctx.build_connections(dnqs.dets_to_device(p.dets), slot=5)
+
+
+# ------------------------------------------------------------------ mixed precision
+# Split-BF16 GEMMs carry a relative error near 2^-16 per product (operands split into
+# two BF16 parts, the lo*lo term dropped) against 2^-24 for FP32; the bars below are the
+# FP32 ones with that unit roundoff, and |dE| <= 1e-5 Ha for the energy.
+U_SPLIT = 2.0 ** -16
+
+
+@pytest.mark.parametrize("prec", ["MIXED", "SPLIT_BF16"])
+@pytest.mark.parametrize("name,n", [("m8_4a4b_full", None), ("m16_5a5b_s16k", None), ("m20_6a6b_curve", 1500)])
+def test_mixed_energy_small_backflow(dnqs, ctx, name, n, prec):
+    """Split-BF16 network GEMMs (output layer FP32 in MIXED, split too in SPLIT_BF16;
+    LU FP32, reductions FP64) in the regime of a small output layer (Delta Phi ~ 1e-2):
+    |dE| <= 1e-5 Ha against the FP64 oracle, gradient relative L2 <= 1e-3."""
+    p = P.problem(name, n, 1e-2, 0.0)
+    ctx.set_integrals(p.h, p.eri, p.e_core, p.wl.n_alpha, p.wl.n_beta)
+    dets = dnqs.dets_to_device(p.dets)
+    theta = torch.from_numpy(p.theta).cuda()
+    conn = ctx.build_connections(dets)
+    rm = ctx.energy_and_grad(p.wl.widths, theta, conn, precision=getattr(dnqs, prec))
+    torch.cuda.synchronize()
+    o = P.oracle_energy(name, n, 1e-2, 0.0)
+    dEm = abs(rm["E"].item() - o["E"])
+    gm = P.rel_l2(rm["grad"].double().cpu().numpy(), o["grad"])
+    print(f"  {prec} {name} |dE| {dEm:.2e} grad rel {gm:.2e}")
+    assert dEm <= 1e-5
+    assert gm <= 1e-3
+
+
+@pytest.mark.parametrize("prec", ["MIXED", "SPLIT_BF16"])
+def test_mixed_energy_full_backflow(dnqs, ctx, prec):
+    """A full-scale random output layer (out_scale 1): the same bars."""
+    name = "m16_5a5b_s16k"
+    p, dets, theta = _setup(dnqs, ctx, name, None)
+    conn = ctx.build_connections(dets)
+    rm = ctx.energy_and_grad(p.wl.widths, theta, conn, precision=getattr(dnqs, prec))
+    torch.cuda.synchronize()
+    o = P.oracle_energy(name, None)
+    dEm = abs(rm["E"].item() - o["E"])
+    gm = P.rel_l2(rm["grad"].double().cpu().numpy(), o["grad"])
+    print(f"  {prec} at out_scale 1: |dE| {dEm:.2e} Ha, grad rel {gm:.2e}")
+    assert dEm <= 1e-5
+    assert gm <= 1e-3
+
+
+@pytest.mark.parametrize("prec", ["MIXED", "SPLIT_BF16"])
+@pytest.mark.parametrize("out_scale", [1e-2, 1.0])
+def test_mixed_amplitudes(dnqs, ctx, prec, out_scale):
+    """Per configuration |d log|psi|| <= 1e-6 + 2 N_e u kappa_2(A) with u = 2^-16, the
+    FP32 bound with the split-BF16 unit roundoff; signs agree wherever that bound is
+    below log(2) away from a sign change (all but near-singular A)."""
+    p = P.problem("m16_5a5b_s16k", None, out_scale, 0.0 if out_scale < 1 else 0.1)
+    ctx.set_integrals(p.h, p.eri, p.e_core, p.wl.n_alpha, p.wl.n_beta)
+    dets = dnqs.dets_to_device(p.dets)
+    theta = torch.from_numpy(p.theta).cuda()
+    la, sg = ctx.amplitudes(p.wl.widths, theta, dets, precision=getattr(dnqs, prec))
+    from oracle import ansatz
+    ola, osg = ansatz.amplitudes(p.theta, p.wl.widths, p.dets, p.wl.M, p.wl.n_elec)
+    with torch.no_grad():
+        A = ansatz.amplitude_matrices(ansatz.params(p.theta, p.wl.widths, p.wl.n_orb, p.wl.n_elec), p.wl.widths,
+                                      p.dets, p.wl.M, p.wl.n_elec).numpy()
+    kappa = np.linalg.cond(A)
+    bound = 1e-6 + 2.0 * p.wl.n_elec * U_SPLIT * kappa
+    la, sg = la.cpu().numpy(), sg.cpu().numpy()
+    err = np.abs(la - ola)
+    print(f"  {prec} out_scale {out_scale}: |dlog psi| median {np.median(err):.2e} max {err.max():.2e}; "
+          f"max err/bound {np.max(err / bound):.3f}")
+    assert np.all(err <= bound)
+    safe = bound < np.log(2.0)
+    assert np.array_equal(sg[safe], osg.astype(np.int8)[safe])
