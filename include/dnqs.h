@@ -227,6 +227,26 @@ dnqs_status dnqs_capture_end(dnqs_ctx *ctx, dnqs_graph **out);
 dnqs_status dnqs_graph_launch(dnqs_ctx *ctx, dnqs_graph *graph);
 void dnqs_graph_free(dnqs_graph *graph);
 
+/* ------------------------------------------------------------------ autotuner
+ * Tile shapes of the network GEMMs (Sec. 3.3's batched inner loop is dominated by
+ * them): each GEMM shape (engine, kind, M, N, K) has a configuration: tile height
+ * (128 or 64 rows by 128 columns) and, for weight gradients, the split-K count.  With
+ * tuning enabled, the first call that meets a shape times every candidate on the
+ * context's stream (HIP events; one warm-up and three timed runs each) and keeps the
+ * fastest for the context's lifetime; without it (the default) or during graph capture
+ * a shape not in the table uses the default (128 rows, split-K for about 2048
+ * workgroups).  Results do not depend on the tile height; the split-K count changes
+ * the summation order of weight gradients only.
+ * dnqs_tune_export writes the table as text, one line "engine kind M N K tm splits"
+ * per shape (engine 0 FP32, 1 split BF16; kind 0 forward, 1 weight gradient, 2 data
+ * gradient, 3 batched weight gradient with splits 0), NUL-terminated, at most cap
+ * bytes, and returns the full length (-1 for a NULL ctx).  dnqs_tune_import merges
+ * such text into the table (EINVAL on a malformed or out-of-range line, leaving the
+ * table unchanged). */
+dnqs_status dnqs_autotune(dnqs_ctx *ctx, int enable);
+int64_t dnqs_tune_export(const dnqs_ctx *ctx, char *buf, int64_t cap);
+dnqs_status dnqs_tune_import(dnqs_ctx *ctx, const char *text);
+
 /* ------------------------------------------------------------------ timing
  * Average device time (ms) of the most recent launches of the named kernel family
  * recorded with HIP events on the context's stream since dnqs_timing_reset, and the

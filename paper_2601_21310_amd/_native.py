@@ -97,10 +97,15 @@ def lib():
         L.dnqs_timing_enable.argtypes = [vp, i32]
         L.dnqs_timing_reset.argtypes = [vp]
         L.dnqs_timing_get.argtypes = [vp, C.c_char_p, C.POINTER(dbl), C.POINTER(i64)]
+        L.dnqs_autotune.argtypes = [vp, i32]
+        L.dnqs_tune_export.argtypes = [vp, C.c_char_p, i64]
+        L.dnqs_tune_export.restype = i64
+        L.dnqs_tune_import.argtypes = [vp, C.c_char_p]
         for fn in ("dnqs_create", "dnqs_set_stream", "dnqs_set_integrals", "dnqs_build_connections",
                    "dnqs_conn_info", "dnqs_conn_export", "dnqs_amplitudes", "dnqs_energy_and_grad", "dnqs_pt2",
                    "dnqs_energy_and_grad_batched", "dnqs_adamw_batched", "dnqs_capture_begin", "dnqs_capture_end",
-                   "dnqs_graph_launch", "dnqs_timing_enable", "dnqs_timing_reset", "dnqs_timing_get"):
+                   "dnqs_graph_launch", "dnqs_timing_enable", "dnqs_timing_reset", "dnqs_timing_get",
+                   "dnqs_autotune", "dnqs_tune_import"):
             getattr(L, fn).restype = C.c_int
         _lib = L
     return _lib
@@ -319,6 +324,19 @@ class Context:
         return Graph(self, g)
 
     # -------------------------------------------------------------- timing
+    def autotune(self, on=True):
+        """Time the GEMM tile candidates of each new shape on first use (see dnqs.h)."""
+        self._check(lib().dnqs_autotune(self.handle, 1 if on else 0))
+
+    def tune_export(self) -> str:
+        n = lib().dnqs_tune_export(self.handle, None, 0)
+        buf = C.create_string_buffer(n + 1)
+        lib().dnqs_tune_export(self.handle, buf, n + 1)
+        return buf.value.decode()
+
+    def tune_import(self, text: str):
+        self._check(lib().dnqs_tune_import(self.handle, text.encode()))
+
     def timing(self, on=True):
         self._check(lib().dnqs_timing_enable(self.handle, 1 if on else 0))
 

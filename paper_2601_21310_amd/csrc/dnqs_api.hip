@@ -2,6 +2,7 @@
 // and the order of kernel launches for each call.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -33,6 +34,25 @@ struct Buf {
 
 struct TimingRec {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+};
+
+// Autotuner entry: a GEMM shape and the configuration chosen for it.
+//   engine: 0 FP32 MFMA, 1 split BF16
+//   kind: 0 forward, 1 weight gradient, 2 data gradient, 3 weight gradient of a batch
+//         (split-K ranges from the batch plan)
+struct TuneKey {
+    int engine, kind, M, N, K;
+    bool operator<(const TuneKey &o) const {
+        if (engine != o.engine) return engine < o.engine;
+        if (kind != o.kind) return kind < o.kind;
+        if (M != o.M) return M < o.M;
+        if (N != o.N) return N < o.N;
+        return K < o.K;
+    }
+};
+struct GemmCfg {
+    int tm = 128;     // tile height (128 or 64)
+    int splits = 1;   // split-K count (weight gradients; 0 = the batch plan's table)
 };
 
 thread_local std::string g_create_error;
@@ -75,6 +95,8 @@ struct dnqs_ctx {
     std::vector<hipEvent_t> event_pool;
     BatchPlan plan;
     bool capturing = false;
+    bool autotune = false;
+    std::map<TuneKey, GemmCfg> tuned;
 };
 
 struct dnqs_graph {
@@ -257,8 +279,8 @@ dnqs_status net_view(dnqs_ctx *ctx, const dnqs_net *net, int M, int na, int nb, 
     return DNQS_OK;
 }
 
-int splitk_splits(int M, int N, int64_t K) {
-    int tiles = ((M + 127) / 128) * ((N + 127) / 128);
+int splitk_splits(int M, int N, int64_t K, int tm = 128) {
+    int tiles = ((M + tm - 1) / tm) * ((N + 127) / 128);
     int s = (2048 + tiles - 1) / tiles;
     int64_t maxs = K / 256;
     if (maxs < 1) maxs = 1;
@@ -268,15 +290,78 @@ int splitk_splits(int M, int N, int64_t K) {
     return s;
 }
 
-// GEMM engine of one layer: FP32 MFMA, or split-BF16 MFMA for the hidden layers of
-// DNQS_MIXED and for every layer of DNQS_SPLIT_BF16.
-void mlp_gemm(hipStream_t st, int precision, bool out_layer, const GemmArgs &g, bool a_kcontig, bool b_ncontig,
-              int epi, int splits) {
-    const bool x3 = precision == DNQS_SPLIT_BF16 || (precision == DNQS_MIXED && !out_layer);
-    if (x3)
-        launch_gemm_x3(st, g, a_kcontig, b_ncontig, epi, splits);
+// GEMM engine of one layer: FP32 MFMA (0), or split-BF16 MFMA (1) for the hidden layers
+// of DNQS_MIXED and for every layer of DNQS_SPLIT_BF16.
+int gemm_engine(int precision, bool out_layer) {
+    return (precision == DNQS_SPLIT_BF16 || (precision == DNQS_MIXED && !out_layer)) ? 1 : 0;
+}
+
+void launch_gemm(int engine, hipStream_t st, const GemmArgs &g, bool a_kcontig, bool b_ncontig, int epi,
+                 int splits, int tm) {
+    if (engine == 1)
+        launch_gemm_x3(st, g, a_kcontig, b_ncontig, epi, splits, tm);
     else
-        launch_gemm_f32(st, g, a_kcontig, b_ncontig, epi, splits);
+        launch_gemm_f32(st, g, a_kcontig, b_ncontig, epi, splits, tm);
+}
+
+// Runs launch(cfg) with the configuration of `key`: the tuned one if the table has it;
+// else, with tuning on and no capture in progress, every candidate is timed on the
+// context stream (one warm-up and three timed runs each, HIP events) and the fastest
+// kept; else the first candidate (the default).  launch() must be safe to repeat.
+template <typename F>
+dnqs_status tuned_launch(dnqs_ctx *ctx, const TuneKey &key, const std::vector<GemmCfg> &cands, F launch) {
+    auto it = ctx->tuned.find(key);
+    if (it != ctx->tuned.end()) return launch(it->second);
+    if (!ctx->autotune || ctx->capturing || cands.size() < 2) return launch(cands[0]);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(ctx, hipEventCreate(&e0));
+    HIPCHK(ctx, hipEventCreate(&e1));
+    float best = INFINITY;
+    GemmCfg bc = cands[0];
+    dnqs_status st = DNQS_OK;
+    for (const GemmCfg &c : cands) {
+        if ((st = launch(c)) != DNQS_OK) break;
+        if (hipEventRecord(e0, ctx->stream) != hipSuccess) { st = DNQS_EHIP; break; }
+        for (int r = 0; r < 3 && st == DNQS_OK; ++r) st = launch(c);
+        if (st != DNQS_OK) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            st = DNQS_EHIP;
+            break;
+        }
+        if (ms < best) {
+            best = ms;
+            bc = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != DNQS_OK) return st == DNQS_EHIP ? fail(ctx, st, "autotuner timing failed") : st;
+    ctx->tuned[key] = bc;
+    return launch(bc);
+}
+
+// Candidates: tile heights 128 and 64; for a weight gradient with its own split-K,
+// also 1/4, 1/2 and 2 times the default split count (default first).
+std::vector<GemmCfg> gemm_candidates(int M, int N, int64_t K, bool wgrad, bool plan_splits);
+
+std::vector<GemmCfg> gemm_candidates(int M, int N, int64_t K, bool wgrad, bool plan_splits) {
+    std::vector<GemmCfg> c;
+    for (int tm : {128, 64}) {
+        if (!wgrad || plan_splits) {
+            c.push_back({tm, wgrad ? 0 : 1});
+            continue;
+        }
+        const int s0 = splitk_splits(M, N, K, tm);
+        for (int s : {s0, s0 / 4, s0 / 2, 2 * s0}) {
+            if (s < 1 || s > 256 || (int64_t)s * 256 > K + 255) continue;
+            bool dup = false;
+            for (const GemmCfg &q : c) dup |= q.tm == tm && q.splits == s;
+            if (!dup) c.push_back({tm, s});
+        }
+    }
+    return c;
 }
 
 bool precision_ok(int p) { return p == DNQS_FP32 || p == DNQS_MIXED || p == DNQS_SPLIT_BF16; }
@@ -314,8 +399,14 @@ dnqs_status forward(dnqs_ctx *ctx, const Slot &sl, const NetView &nv, const floa
         g.ldc = w[l];
         g.bias = theta + nv.offb[l];
         g.ones_row = -1;
-        mlp_gemm(st, precision, l == L, g, true, true, l < L ? EPI_BIAS_TANH : EPI_BIAS, 1);
-        CHECK_LAUNCH(ctx);
+        const int eng = gemm_engine(precision, l == L);
+        const int epi = l < L ? EPI_BIAS_TANH : EPI_BIAS;
+        TRY(tuned_launch(ctx, TuneKey{eng, 0, g.M, g.N, g.K}, gemm_candidates(g.M, g.N, g.K, false, false),
+                         [&](const GemmCfg &c) -> dnqs_status {
+                             launch_gemm(eng, st, g, true, true, epi, 1, c.tm);
+                             CHECK_LAUNCH(ctx);
+                             return DNQS_OK;
+                         }));
         prev = out;
     }
     float *Ainv = nullptr;
@@ -662,16 +753,21 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
         g.ldb = dout;
         g.ldc = dout;
         g.ones_row = din;
-        const int splits = splitk_splits(g.M, g.N, n);
-        float *partial = nullptr;
         const int64_t cnt = (int64_t)(din + 1) * dout;
-        TRY(ws_t(ctx, "splitk", (size_t)cnt * splits, &partial));
-        g.C = partial;
-        g.c_split_stride = cnt;
-        mlp_gemm(st, precision, l == L, g, false, true, EPI_STORE, splits);
-        CHECK_LAUNCH(ctx);
-        launch_reduce_splits(st, partial, splits, cnt, grad + nv.offW[l]);
-        CHECK_LAUNCH(ctx);
+        const int eng = gemm_engine(precision, l == L);
+        TRY(tuned_launch(ctx, TuneKey{eng, 1, g.M, g.N, g.K}, gemm_candidates(g.M, g.N, g.K, true, false),
+                         [&](const GemmCfg &c) -> dnqs_status {
+                             float *partial = nullptr;
+                             TRY(ws_t(ctx, "splitk", (size_t)cnt * c.splits, &partial));
+                             GemmArgs gs = g;
+                             gs.C = partial;
+                             gs.c_split_stride = cnt;
+                             launch_gemm(eng, st, gs, false, true, EPI_STORE, c.splits, c.tm);
+                             CHECK_LAUNCH(ctx);
+                             launch_reduce_splits(st, partial, c.splits, cnt, grad + nv.offW[l]);
+                             CHECK_LAUNCH(ctx);
+                             return DNQS_OK;
+                         }));
         if (l == 1) break;
         // delta_{l-1} = (delta_l W_l^T) * (1 - h_{l-1}^2)
         void *dnext = dbuf[which];
@@ -689,8 +785,13 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
         d.act = hp;
         d.ldact = din;
         d.ones_row = -1;
-        mlp_gemm(st, precision, l == L, d, true, false, EPI_DTANH, 1);
-        CHECK_LAUNCH(ctx);
+        const int deng = gemm_engine(precision, l == L);
+        TRY(tuned_launch(ctx, TuneKey{deng, 2, d.M, d.N, d.K}, gemm_candidates(d.M, d.N, d.K, false, false),
+                         [&](const GemmCfg &c) -> dnqs_status {
+                             launch_gemm(deng, st, d, true, false, EPI_DTANH, 1, c.tm);
+                             CHECK_LAUNCH(ctx);
+                             return DNQS_OK;
+                         }));
         delta = dnext;
     }
     // dPhi0 equals db_L (Phi0 and b_L enter A(x) the same way)
@@ -737,16 +838,17 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
     CHECK_LAUNCH(ctx);
     int *overflow = nullptr;
     TRY(ws_t(ctx, "pt2_ovf", 1, &overflow));
-    DetSet S;
-    S.keys = conn->set_keys;
-    S.idx = conn->set_idx;
-    S.mask = conn->set_mask;
     PT2Export ex;
     ex.cap = o.export_cap;
     ex.keys = o.export_keys;
     ex.w = o.export_w;
     ex.haa = o.export_haa;
     ex.count = o.export_count;
+    // h_pp and V(p, q) for the diagonal rule in the reduce (M <= 32)
+    double *vt = nullptr;
+    TRY(ws_t(ctx, "pt2_vt", (size_t)pt2_diag_table_size(sl.M), &vt));
+    launch_diag_table(st, H, vt);
+    CHECK_LAUNCH(ctx);
     // external sum: partitioned reduce-by-key (k_pt2_part.hip)
     const int64_t nexc = n_excitations(sl.M, sl.na, sl.nb);
     const int64_t pairs = n * nexc;
@@ -846,14 +948,31 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
             sb = sb_d;
             nsb = (int64_t)K1 * K2;
         }
+        // S grouped by sub-bucket (same hash bits as the pairs)
+        int32_t *scnt = nullptr;
+        int64_t *soffs = nullptr, *sbsum = nullptr;
+        uint64_t *skeys = nullptr;
+        TRY(ws_t(ctx, "pt2_scnt", (size_t)nsb, &scnt));
+        TRY(ws_t(ctx, "pt2_soffs", (size_t)nsb, &soffs));
+        TRY(ws_t(ctx, "pt2_sbsum", (size_t)scan_blocks(nsb) + 1, &sbsum));
+        TRY(ws_t(ctx, "pt2_skeys", (size_t)2 * std::max<int64_t>(n, 1), &skeys));
+        const int sbits = s1 + (s2 > 0 ? s2 : 0);
+        HIPCHK(ctx, hipMemsetAsync(scnt, 0, sizeof(int32_t) * nsb, st));
+        launch_s_sub(st, conn->dets, n, sbits, packed, scnt, nullptr, nullptr, false);
+        CHECK_LAUNCH(ctx);
+        launch_exclusive_scan(st, scnt, nsb, soffs, sbsum, tot + 1);
+        CHECK_LAUNCH(ctx);
+        HIPCHK(ctx, hipMemsetAsync(scnt, 0, sizeof(int32_t) * nsb, st));
+        launch_s_sub(st, conn->dets, n, sbits, packed, scnt, soffs, skeys, true);
+        CHECK_LAUNCH(ctx);
         double *part_r = nullptr;
         TRY(ws_t(ctx, "pt2_part_r", (size_t)nsb * 4, &part_r));
         launch_pt2_init_acc(st, acc + 4);
         if (o.export_cap > 0) HIPCHK(ctx, hipMemsetAsync(o.export_count, 0, sizeof(int64_t), st));
         HIPCHK(ctx, hipMemsetAsync(overflow, 0, sizeof(int), st));
         Timer tr(ctx, "pt2_reduce");
-        launch_pt2_reduce(st, H, conn->dets, psi, desc, sb, nsb, S, energy, o.sample_mask, ex, part_r, overflow,
-                          packed);
+        launch_pt2_reduce(st, H, conn->dets, psi, desc, sb, nsb, skeys, soffs, n, vt, energy, o.sample_mask, ex,
+                          part_r, overflow, packed);
         CHECK_LAUNCH(ctx);
         tr.stop();
         launch_pt2_accumulate(st, part_r, nsb, acc + 4);
@@ -1042,8 +1161,14 @@ dnqs_status dnqs_energy_and_grad_batched(dnqs_ctx *ctx, const dnqs_net *net, int
         g.tile_pid = b.tile_pid;
         g.Bg = Wg(l);
         g.biasg = bg(l);
-        mlp_gemm(st, precision, l == L, g, true, true, l < L ? EPI_BIAS_TANH : EPI_BIAS, 1);
-        CHECK_LAUNCH(ctx);
+        const int eng = gemm_engine(precision, l == L);
+        const int epi = l < L ? EPI_BIAS_TANH : EPI_BIAS;
+        TRY(tuned_launch(ctx, TuneKey{eng, 0, g.M, g.N, g.K}, gemm_candidates(g.M, g.N, g.K, false, false),
+                         [&](const GemmCfg &c) -> dnqs_status {
+                             launch_gemm(eng, st, g, true, true, epi, 1, c.tm);
+                             CHECK_LAUNCH(ctx);
+                             return DNQS_OK;
+                         }));
         prev = out;
     }
     double *la = nullptr, *psi = nullptr, *v = nullptr, *pv = nullptr, *pp = nullptr;
@@ -1093,10 +1218,15 @@ dnqs_status dnqs_energy_and_grad_batched(dnqs_ctx *ctx, const dnqs_net *net, int
         TRY(ws_t(ctx, "b_splitk", (size_t)cnt * b.nz, &partial));
         g.C = partial;
         g.c_split_stride = cnt;
-        mlp_gemm(st, precision, l == L, g, false, true, EPI_STORE, b.nz);
-        CHECK_LAUNCH(ctx);
-        launch_reduce_splits_grouped(st, partial, b.zoff, cnt, G, b.P_d, nv.offW[l]);
-        CHECK_LAUNCH(ctx);
+        const int eng = gemm_engine(precision, l == L);
+        TRY(tuned_launch(ctx, TuneKey{eng, 3, g.M, g.N, g.K}, gemm_candidates(g.M, g.N, g.K, true, true),
+                         [&](const GemmCfg &c) -> dnqs_status {
+                             launch_gemm(eng, st, g, false, true, EPI_STORE, b.nz, c.tm);
+                             CHECK_LAUNCH(ctx);
+                             launch_reduce_splits_grouped(st, partial, b.zoff, cnt, G, b.P_d, nv.offW[l]);
+                             CHECK_LAUNCH(ctx);
+                             return DNQS_OK;
+                         }));
         if (l == 1) break;
         void *dnext = dbuf[which];
         which ^= 1;
@@ -1114,8 +1244,13 @@ dnqs_status dnqs_energy_and_grad_batched(dnqs_ctx *ctx, const dnqs_net *net, int
         d.ones_row = -1;
         d.tile_pid = b.tile_pid;
         d.Bg = Wg(l);
-        mlp_gemm(st, precision, l == L, d, true, false, EPI_DTANH, 1);
-        CHECK_LAUNCH(ctx);
+        const int deng = gemm_engine(precision, l == L);
+        TRY(tuned_launch(ctx, TuneKey{deng, 2, d.M, d.N, d.K}, gemm_candidates(d.M, d.N, d.K, false, false),
+                         [&](const GemmCfg &c) -> dnqs_status {
+                             launch_gemm(deng, st, d, true, false, EPI_DTANH, 1, c.tm);
+                             CHECK_LAUNCH(ctx);
+                             return DNQS_OK;
+                         }));
         delta = dnext;
     }
     launch_copy_grouped(st, b.P_d, G, nv.offb[L], nv.offPhi0, (int64_t)No * Ne);
@@ -1144,6 +1279,58 @@ dnqs_status dnqs_adamw_batched(dnqs_ctx *ctx, const dnqs_net *net, int G, const 
     AdamCfg c{cfg->lr_max, cfg->lr_min, cfg->decay_steps, cfg->beta1, cfg->beta2, cfg->eps, cfg->weight_decay};
     launch_adamw_grouped(ctx->stream, b.P_d, G, m, v, nv.total, c, step);
     CHECK_LAUNCH(ctx);
+    return DNQS_OK;
+}
+
+dnqs_status dnqs_autotune(dnqs_ctx *ctx, int enable) {
+    if (!ctx) return DNQS_EINVAL;
+    ctx->autotune = enable != 0;
+    return DNQS_OK;
+}
+
+int64_t dnqs_tune_export(const dnqs_ctx *ctx, char *buf, int64_t cap) {
+    if (!ctx) return -1;
+    std::string out;
+    char line[128];
+    for (const auto &kv : ctx->tuned) {
+        const TuneKey &k = kv.first;
+        std::snprintf(line, sizeof line, "%d %d %d %d %d %d %d\n", k.engine, k.kind, k.M, k.N, k.K, kv.second.tm,
+                      kv.second.splits);
+        out += line;
+    }
+    if (buf && cap > 0) {
+        const int64_t m = std::min<int64_t>(cap - 1, (int64_t)out.size());
+        std::memcpy(buf, out.data(), (size_t)m);
+        buf[m] = 0;
+    }
+    return (int64_t)out.size();
+}
+
+dnqs_status dnqs_tune_import(dnqs_ctx *ctx, const char *text) {
+    if (!ctx) return DNQS_EINVAL;
+    if (!text) return fail(ctx, DNQS_EINVAL, "text is NULL");
+    std::map<TuneKey, GemmCfg> add;
+    const char *p = text;
+    int lineno = 0;
+    while (*p) {
+        const char *e = std::strchr(p, '\n');
+        const std::string line = e ? std::string(p, e) : std::string(p);
+        p = e ? e + 1 : p + line.size();
+        ++lineno;
+        if (line.find_first_not_of(" \t\r") == std::string::npos) continue;
+        TuneKey k;
+        GemmCfg c;
+        char extra = 0;
+        if (std::sscanf(line.c_str(), "%d %d %d %d %d %d %d %c", &k.engine, &k.kind, &k.M, &k.N, &k.K, &c.tm,
+                        &c.splits, &extra) != 7)
+            return fail(ctx, DNQS_EINVAL, "tune table line %d: expected 7 integers", lineno);
+        const bool ok = (k.engine == 0 || k.engine == 1) && k.kind >= 0 && k.kind <= 3 && k.M > 0 && k.N > 0 &&
+                        k.K > 0 && (c.tm == 64 || c.tm == 128) &&
+                        (k.kind == 3 ? c.splits == 0 : (k.kind == 1 ? c.splits >= 1 && c.splits <= 256 : c.splits == 1));
+        if (!ok) return fail(ctx, DNQS_EINVAL, "tune table line %d: value out of range", lineno);
+        add[k] = c;
+    }
+    for (const auto &kv : add) ctx->tuned[kv.first] = kv.second;
     return DNQS_OK;
 }
 

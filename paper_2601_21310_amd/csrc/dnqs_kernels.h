@@ -76,9 +76,12 @@ struct RowProblems {
 void launch_embed(hipStream_t st, const uint64_t *dets, int64_t n, int M, int d1, const float *W1, const float *b1,
                   float *h1, float *U, RowProblems rp = {}, int64_t offW1 = 0, int64_t offb1 = 0);
 // C = epi(A B): FP32 MFMA, or split-BF16 MFMA (three BF16 products per operand pair);
-// same arguments and layouts for both
-void launch_gemm_f32(hipStream_t st, const GemmArgs &g, bool a_kcontig, bool b_ncontig, int epi, int splits);
-void launch_gemm_x3(hipStream_t st, const GemmArgs &g, bool a_kcontig, bool b_ncontig, int epi, int splits);
+// same arguments and layouts for both.  Tiles of tm (128 or 64) x 128; split-K over
+// `splits` chunks of K (or the ksplit table) into C + z * c_split_stride.
+void launch_gemm_f32(hipStream_t st, const GemmArgs &g, bool a_kcontig, bool b_ncontig, int epi, int splits,
+                     int tm = 128);
+void launch_gemm_x3(hipStream_t st, const GemmArgs &g, bool a_kcontig, bool b_ncontig, int epi, int splits,
+                    int tm = 128);
 void launch_reduce_splits(hipStream_t st, const float *part, int splits, int64_t count, float *out);
 int orb_lu_group(int ne);
 void launch_orb_lu(hipStream_t st, const uint64_t *dets, int64_t n, int M, int na, int nb, const float *O,
@@ -151,9 +154,16 @@ void launch_l2_transpose(hipStream_t st, const uint32_t *counts, const PT2Chunk 
                          int32_t *out);
 void launch_sub_starts(hipStream_t st, const int64_t *offs2, const int64_t *bstart, const int64_t *bcb0,
                        const int64_t *bnc, int K1, int K2, int64_t *sb);
+int pt2_diag_table_size(int M);
+void launch_diag_table(hipStream_t st, const Ham &H, double *vt);
+// S grouped by the reduce sub-bucket of its keys (top sbits of the key hash): count into
+// cnt (fill == false), or place into skeys at offs[sub] + cursor (cnt used as cursors)
+void launch_s_sub(hipStream_t st, const uint64_t *dets, int64_t n, int sbits, bool packed, int32_t *cnt,
+                  const int64_t *offs, uint64_t *skeys, bool fill);
 void launch_pt2_reduce(hipStream_t st, const Ham &H, const uint64_t *dets, const double *psi, const uint64_t *desc,
-                       const int64_t *sb, int64_t nsb, const DetSet &S, const double *energy, uint64_t sample_mask,
-                       const PT2Export &ex, double *part, int *overflow, bool packed);
+                       const int64_t *sb, int64_t nsb, const uint64_t *skeys, const int64_t *soffs, int64_t n_s,
+                       const double *vt, const double *energy, uint64_t sample_mask, const PT2Export &ex, double *part,
+                       int *overflow, bool packed);
 void launch_pt2_accumulate(hipStream_t st, const double *part, int64_t nb, double *acc);
 void launch_pt2_internal(hipStream_t st, const double *psi, const double *v, const double *diag, int64_t n,
                          const double *energy, double *part, double *acc_int);

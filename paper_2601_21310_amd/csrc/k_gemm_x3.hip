@@ -9,11 +9,12 @@
 // the split form keeps it near 1e-7 Ha at a sixth of the BF16 MFMA peak, which is still
 // more than five times the FP32 MFMA peak.
 //
-// Tiles: 128 x 128 per workgroup, K step 32; 4 waves, each 64 x 64 = 2 x 2 MFMA tiles.
-// LDS holds the hi and lo parts of both operands k-contiguous ([row][k], rows padded by 8
-// bf16 so a wave's 16-byte fragment reads are free of bank conflicts); 40 KB per
-// workgroup.  MFMA lane layout: A[i][k] comes from lane i + 32*(k/8), element k%8; B[k][j]
-// from lane j + 32*(k/8); C/D rows 8*(r/4) + 4*(lane/32) + r%4, column lane%32.
+// Tiles: TM x 128 per workgroup (TM = 128 or 64), K step 32; 4 waves as 2 x 2, each
+// (TM/2) x 64 = WI x 2 MFMA tiles.  LDS holds the hi and lo parts of both operands
+// k-contiguous ([row][k], rows padded by 8 bf16 so a wave's 16-byte fragment reads are
+// free of bank conflicts); 40 KB per workgroup at TM = 128.  MFMA lane layout: A[i][k]
+// comes from lane i + 32*(k/8), element k%8; B[k][j] from lane j + 32*(k/8); C/D rows
+// 8*(r/4) + 4*(lane/32) + r%4, column lane%32.
 //
 // Operands are FP32 in either orientation: "k-contiguous" (row r, k at r*ld + k) or
 // "row-contiguous" (k at k*ld + r).  The epilogues and the split-K / grouped-problem
@@ -29,7 +30,7 @@ typedef __bf16 bf16_t;
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
 
-constexpr int XBM = 128, XBN = 128, XBK = 32, XPAD = 8;
+constexpr int XBN = 128, XBK = 32, XPAD = 8;
 constexpr int XLD = XBK + XPAD;  // bf16 per LDS row
 
 __device__ __forceinline__ int xcd_remap_x(int L, int total) {
@@ -45,15 +46,17 @@ __device__ __forceinline__ void split_bf16(float x, bf16_t &hi, bf16_t &lo) {
     lo = (bf16_t)(x - (float)hi);
 }
 
-// One operand tile: 128 rows x 32 k of an FP32 matrix P into registers r[16].
+// One operand tile: ROWS rows x 32 k of an FP32 matrix P into registers r[16]; threads
+// t < 2*ROWS take part.
 //   KC (k-contiguous, P[row*ld + k]):   thread = (row t/2, k 16*(t%2) .. +15)
-//   !KC (row-contiguous, P[k*ld + row]): thread = (rows 4*(t%32) .. +3, k 4*(t/32) .. +3),
-//                                        r[4*kk + rr] = P[k+kk][row+rr]
+//   !KC (row-contiguous, P[k*ld + row]): thread = (rows 4*(t%(ROWS/4)) .. +3,
+//                                        k 4*(t/(ROWS/4)) .. +3), r[4*kk + rr] = P[k+kk][row+rr]
 // Rows >= rows_ld and k >= kend read as 0; row `ones` (if >= 0) reads as 1 for k < kend.
-template <bool KC>
+template <bool KC, int ROWS>
 __device__ __forceinline__ void xload(const float *__restrict__ P, int ld, int r0, int rows_ld, int ones, int k0,
                                       int kend, float (&r)[16]) {
     const int t = threadIdx.x;
+    if (t >= 2 * ROWS) return;
     if (KC) {
         const int row = r0 + (t >> 1), k = k0 + (t & 1) * 16;
         const float *p = P + (int64_t)row * ld + k;
@@ -75,7 +78,7 @@ __device__ __forceinline__ void xload(const float *__restrict__ P, int ld, int r
             for (int j = 0; j < 16; ++j) r[j] = (k + j < kend) ? 1.0f : 0.0f;
         }
     } else {
-        const int row = r0 + 4 * (t & 31), k = k0 + 4 * (t >> 5);
+        const int row = r0 + 4 * (t % (ROWS / 4)), k = k0 + 4 * (t / (ROWS / 4));
         const bool vec = row + 4 <= rows_ld && (ld & 3) == 0 && ((((uintptr_t)(P + row)) & 15) == 0);
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
@@ -99,9 +102,10 @@ __device__ __forceinline__ void xload(const float *__restrict__ P, int ld, int r
 }
 
 // Split the tile in r into the hi / lo LDS arrays ([row][k]).
-template <bool KC>
+template <bool KC, int ROWS>
 __device__ __forceinline__ void xstore(bf16_t (*Hs)[XLD], bf16_t (*Ls)[XLD], const float (&r)[16]) {
     const int t = threadIdx.x;
+    if (t >= 2 * ROWS) return;
     if (KC) {
         const int row = t >> 1, k = (t & 1) * 16;
 #pragma unroll
@@ -118,7 +122,7 @@ __device__ __forceinline__ void xstore(bf16_t (*Hs)[XLD], bf16_t (*Ls)[XLD], con
             *(bf16x8_t *)&Ls[row][k + 8 * q] = l;
         }
     } else {
-        const int row = 4 * (t & 31), k = 4 * (t >> 5);
+        const int row = 4 * (t % (ROWS / 4)), k = 4 * (t / (ROWS / 4));
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
             bf16x4_t h, l;
@@ -137,19 +141,20 @@ __device__ __forceinline__ void xstore(bf16_t (*Hs)[XLD], bf16_t (*Ls)[XLD], con
 
 // AK: A k-contiguous (A[m*lda + k]) else A[k*lda + m].  BNC: B n-contiguous
 // (B[k*ldb + n], i.e. row-contiguous in the [n][k] view) else B[n*ldb + k].
-template <bool AK, bool BNC, int EPI>
+template <bool AK, bool BNC, int EPI, int TM>
 __global__ __launch_bounds__(256) void k_gemm_x3(GemmArgs g0) {
+    constexpr int WI = TM / 64;
     GemmArgs g = g0;
-    __shared__ __attribute__((aligned(16))) bf16_t Ah[XBM][XLD];
-    __shared__ __attribute__((aligned(16))) bf16_t Al[XBM][XLD];
+    __shared__ __attribute__((aligned(16))) bf16_t Ah[TM][XLD];
+    __shared__ __attribute__((aligned(16))) bf16_t Al[TM][XLD];
     __shared__ __attribute__((aligned(16))) bf16_t Bh[XBN][XLD];
     __shared__ __attribute__((aligned(16))) bf16_t Bl[XBN][XLD];
     const int tiles_n = (g.N + XBN - 1) / XBN;
-    const int tiles_m = (g.M + XBM - 1) / XBM;
+    const int tiles_m = (g.M + TM - 1) / TM;
     const int L = xcd_remap_x(blockIdx.x, tiles_n * tiles_m);
-    const int m0 = (L / tiles_n) * XBM, n0 = (L % tiles_n) * XBN;
+    const int m0 = (L / tiles_n) * TM, n0 = (L % tiles_n) * XBN;
     if (g.tile_pid) {
-        const int pg = g.tile_pid[L / tiles_n];
+        const int pg = g.tile_pid[(int64_t)(L / tiles_n) * TM / 128];
         g.B = g.Bg[pg];
         if (g.biasg) g.bias = g.biasg[pg];
     }
@@ -164,12 +169,12 @@ __global__ __launch_bounds__(256) void k_gemm_x3(GemmArgs g0) {
     const float *B = (const float *)g.B;
     const int mload = g.ones_row >= 0 ? g.ones_row : g.M;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int wm = (wave >> 1) * (TM / 2), wn = (wave & 1) * 64;
     const int li = lane & 31, lk = (lane >> 5) * 8;
 
-    v16f_x acc[2][2];
+    v16f_x acc[WI][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -177,30 +182,33 @@ __global__ __launch_bounds__(256) void k_gemm_x3(GemmArgs g0) {
 
     float ra[16], rb[16];
     if (kbeg < kend) {
-        xload<AK>(A, g.lda, m0, mload, g.ones_row, kbeg, kend, ra);
-        xload<!BNC>(B, g.ldb, n0, g.N, -1, kbeg, kend, rb);
+        xload<AK, TM>(A, g.lda, m0, mload, g.ones_row, kbeg, kend, ra);
+        xload<!BNC, XBN>(B, g.ldb, n0, g.N, -1, kbeg, kend, rb);
     }
     for (int k0 = kbeg; k0 < kend; k0 += XBK) {
         __syncthreads();
-        xstore<AK>(Ah, Al, ra);
-        xstore<!BNC>(Bh, Bl, rb);
+        xstore<AK, TM>(Ah, Al, ra);
+        xstore<!BNC, XBN>(Bh, Bl, rb);
         __syncthreads();
         if (k0 + XBK < kend) {
-            xload<AK>(A, g.lda, m0, mload, g.ones_row, k0 + XBK, kend, ra);
-            xload<!BNC>(B, g.ldb, n0, g.N, -1, k0 + XBK, kend, rb);
+            xload<AK, TM>(A, g.lda, m0, mload, g.ones_row, k0 + XBK, kend, ra);
+            xload<!BNC, XBN>(B, g.ldb, n0, g.N, -1, k0 + XBK, kend, rb);
         }
 #pragma unroll
         for (int ks = 0; ks < XBK; ks += 16) {
-            bf16x8_t ah[2], al[2], bh[2], bl[2];
+            bf16x8_t ah[WI], al[WI], bh[2], bl[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
+            for (int i = 0; i < WI; ++i) {
                 ah[i] = *(const bf16x8_t *)&Ah[wm + 32 * i + li][ks + lk];
                 al[i] = *(const bf16x8_t *)&Al[wm + 32 * i + li][ks + lk];
-                bh[i] = *(const bf16x8_t *)&Bh[wn + 32 * i + li][ks + lk];
-                bl[i] = *(const bf16x8_t *)&Bl[wn + 32 * i + li][ks + lk];
             }
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) {
+                bh[j] = *(const bf16x8_t *)&Bh[wn + 32 * j + li][ks + lk];
+                bl[j] = *(const bf16x8_t *)&Bl[wn + 32 * j + li][ks + lk];
+            }
+#pragma unroll
+            for (int i = 0; i < WI; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
@@ -213,7 +221,7 @@ __global__ __launch_bounds__(256) void k_gemm_x3(GemmArgs g0) {
     const float *act = (const float *)g.act;
     const int lrow = (lane >> 5) * 4;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int col = n0 + wn + j * 32 + li;
@@ -235,32 +243,39 @@ __global__ __launch_bounds__(256) void k_gemm_x3(GemmArgs g0) {
         }
 }
 
-template <bool AK, bool BNC, int EPI>
+template <bool AK, bool BNC, int EPI, int TM>
 static void launch_x(hipStream_t st, GemmArgs g, int splits) {
-    const int tiles = ((g.M + XBM - 1) / XBM) * ((g.N + XBN - 1) / XBN);
-    hipLaunchKernelGGL((k_gemm_x3<AK, BNC, EPI>), dim3(tiles, 1, splits), dim3(256), 0, st, g);
+    const int tiles = ((g.M + TM - 1) / TM) * ((g.N + XBN - 1) / XBN);
+    hipLaunchKernelGGL((k_gemm_x3<AK, BNC, EPI, TM>), dim3(tiles, 1, splits), dim3(256), 0, st, g);
 }
 
 int gemm_x3_kstep() { return XBK; }
 
-void launch_gemm_x3(hipStream_t st, const GemmArgs &g0, bool a_kcontig, bool b_ncontig, int epi, int splits) {
+void launch_gemm_x3(hipStream_t st, const GemmArgs &g0, bool a_kcontig, bool b_ncontig, int epi, int splits,
+                    int tm) {
     GemmArgs g = g0;
     if (splits < 1) splits = 1;
     int chunk = (g.K + splits - 1) / splits;
     chunk = (chunk + XBK - 1) / XBK * XBK;
     g.k_chunk = chunk > 0 ? chunk : XBK;
-#define DISPATCH(AK, BNC)                                                              \
-    switch (epi) {                                                                     \
-        case EPI_STORE: launch_x<AK, BNC, EPI_STORE>(st, g, splits); break;            \
-        case EPI_BIAS: launch_x<AK, BNC, EPI_BIAS>(st, g, splits); break;              \
-        case EPI_BIAS_TANH: launch_x<AK, BNC, EPI_BIAS_TANH>(st, g, splits); break;    \
-        case EPI_DTANH: launch_x<AK, BNC, EPI_DTANH>(st, g, splits); break;            \
+#define DISPATCH_TM(AK, BNC, EPI)                    \
+    if (tm == 64)                                    \
+        launch_x<AK, BNC, EPI, 64>(st, g, splits);   \
+    else                                             \
+        launch_x<AK, BNC, EPI, 128>(st, g, splits);
+#define DISPATCH(AK, BNC)                                              \
+    switch (epi) {                                                     \
+        case EPI_STORE: DISPATCH_TM(AK, BNC, EPI_STORE) break;         \
+        case EPI_BIAS: DISPATCH_TM(AK, BNC, EPI_BIAS) break;           \
+        case EPI_BIAS_TANH: DISPATCH_TM(AK, BNC, EPI_BIAS_TANH) break; \
+        case EPI_DTANH: DISPATCH_TM(AK, BNC, EPI_DTANH) break;         \
     }
     if (a_kcontig && b_ncontig) { DISPATCH(true, true) }
     else if (a_kcontig && !b_ncontig) { DISPATCH(true, false) }
     else if (!a_kcontig && b_ncontig) { DISPATCH(false, true) }
     else { DISPATCH(false, false) }
 #undef DISPATCH
+#undef DISPATCH_TM
 }
 
 }  // namespace dnqs

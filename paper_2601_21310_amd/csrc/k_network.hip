@@ -66,8 +66,8 @@ void launch_embed(hipStream_t st, const uint64_t *dets, int64_t n, int M, int d1
 }
 
 // ------------------------------------------------------------------ FP32 MFMA GEMM
-constexpr int BM = 128, BN = 128, BK = 16;
-constexpr int LDS_A = BM + 4, LDS_B = BN + 4;
+constexpr int BN = 128, BK = 16;
+constexpr int LDS_B = BN + 4;
 
 // Workgroups are dispatched round-robin over the 8 XCDs.  Remap the linear id so that
 // consecutive logical tiles (which share an A row-tile) land on the same XCD and hit
@@ -94,9 +94,11 @@ __device__ __forceinline__ void load8(const float *p, bool full, OK ok, float (&
     }
 }
 
-template <bool A_KCONTIG>
+// A tile (TM rows m x BK k) into registers: threads t < 2*TM take 8 elements each.
+template <bool A_KCONTIG, int TM>
 __device__ __forceinline__ void load_a_tile(const GemmArgs &g, int m0, int k0, int kend, float (&r)[8]) {
     const int t = threadIdx.x;
+    if (t >= 2 * TM) return;
     const int mload = g.ones_row >= 0 ? g.ones_row : g.M;
     const float *A = (const float *)g.A;
     if (A_KCONTIG) {  // A[m*lda + k]; thread: one m, 8 consecutive k
@@ -109,7 +111,7 @@ __device__ __forceinline__ void load_a_tile(const GemmArgs &g, int m0, int k0, i
             for (int j = 0; j < 8; ++j) r[j] = (k + j < kend) ? 1.0f : 0.0f;
         }
     } else {  // A[k*lda + m]; thread: one k, 8 consecutive m
-        const int k = k0 + (t >> 4), m = m0 + (t & 15) * 8;
+        const int k = k0 + t / (TM / 8), m = m0 + (t % (TM / 8)) * 8;
         const float *p = A + (int64_t)k * g.lda + m;
         const bool full = k < kend && m + 8 <= mload && (g.lda & 3) == 0;
         load8(p, full, [&](int j) { return k < kend && m + j < mload; }, r);
@@ -121,15 +123,16 @@ __device__ __forceinline__ void load_a_tile(const GemmArgs &g, int m0, int k0, i
     }
 }
 
-template <bool A_KCONTIG>
-__device__ __forceinline__ void store_a_tile(float (*As)[LDS_A], const float (&r)[8]) {
+template <bool A_KCONTIG, int TM>
+__device__ __forceinline__ void store_a_tile(float (*As)[TM + 4], const float (&r)[8]) {
     const int t = threadIdx.x;
+    if (t >= 2 * TM) return;
     if (A_KCONTIG) {
         const int m = t >> 1, k = (t & 1) * 8;
 #pragma unroll
         for (int j = 0; j < 8; ++j) As[k + j][m] = r[j];
     } else {
-        const int k = t >> 4, m = (t & 15) * 8;
+        const int k = t / (TM / 8), m = (t % (TM / 8)) * 8;
 #pragma unroll
         for (int j = 0; j < 8; ++j) As[k][m + j] = r[j];
     }
@@ -166,18 +169,20 @@ __device__ __forceinline__ void store_b_tile(float (*Bs)[LDS_B], const float (&r
     }
 }
 
-// FP32 MFMA GEMM, operands and output in FP32.
-template <bool A_KCONTIG, bool B_NCONTIG, int EPI>
+// FP32 MFMA GEMM, operands and output in FP32.  Tile TM x 128 (TM = 128 or 64); the
+// four waves are 2 x 2, each (TM/2) x 64 = WI x 2 MFMA blocks of 32 x 32.
+template <bool A_KCONTIG, bool B_NCONTIG, int EPI, int TM>
 __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g0) {
+    constexpr int WI = TM / 64;
     GemmArgs g = g0;
-    __shared__ float As[BK][LDS_A];
+    __shared__ float As[BK][TM + 4];
     __shared__ float Bs[BK][LDS_B];
     const int tiles_n = (g.N + BN - 1) / BN;
-    const int tiles_m = (g.M + BM - 1) / BM;
+    const int tiles_m = (g.M + TM - 1) / TM;
     const int L = xcd_remap(blockIdx.x, tiles_n * tiles_m);
-    const int m0 = (L / tiles_n) * BM, n0 = (L % tiles_n) * BN;
+    const int m0 = (L / tiles_n) * TM, n0 = (L % tiles_n) * BN;
     if (g.tile_pid) {
-        const int pg = g.tile_pid[L / tiles_n];
+        const int pg = g.tile_pid[(int64_t)(L / tiles_n) * TM / 128];
         g.B = g.Bg[pg];
         if (g.biasg) g.bias = g.biasg[pg];
     }
@@ -189,12 +194,12 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g0) {
     }
     if (kend > g.K) kend = g.K;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int wm = (wave >> 1) * (TM / 2), wn = (wave & 1) * 64;
     const int li = lane & 31, lk = lane >> 5;
 
-    v16f acc[2][2];
+    v16f acc[WI][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -202,34 +207,36 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g0) {
 
     float ra[8], rb[8];
     if (kbeg < kend) {
-        load_a_tile<A_KCONTIG>(g, m0, kbeg, kend, ra);
+        load_a_tile<A_KCONTIG, TM>(g, m0, kbeg, kend, ra);
         load_b_tile<B_NCONTIG>(g, n0, kbeg, kend, rb);
     }
     for (int k0 = kbeg; k0 < kend; k0 += BK) {
         __syncthreads();
-        store_a_tile<A_KCONTIG>(As, ra);
+        store_a_tile<A_KCONTIG, TM>(As, ra);
         store_b_tile<B_NCONTIG>(Bs, rb);
         __syncthreads();
         if (k0 + BK < kend) {
-            load_a_tile<A_KCONTIG>(g, m0, k0 + BK, kend, ra);
+            load_a_tile<A_KCONTIG, TM>(g, m0, k0 + BK, kend, ra);
             load_b_tile<B_NCONTIG>(g, n0, k0 + BK, kend, rb);
         }
 #pragma unroll
         for (int kk = 0; kk < BK / 2; ++kk) {
-            float a0 = As[2 * kk + lk][wm + li];
-            float a1 = As[2 * kk + lk][wm + 32 + li];
-            float b0 = Bs[2 * kk + lk][wn + li];
-            float b1 = Bs[2 * kk + lk][wn + 32 + li];
-            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+            float a[WI];
+#pragma unroll
+            for (int i = 0; i < WI; ++i) a[i] = As[2 * kk + lk][wm + 32 * i + li];
+            const float b0 = Bs[2 * kk + lk][wn + li];
+            const float b1 = Bs[2 * kk + lk][wn + 32 + li];
+#pragma unroll
+            for (int i = 0; i < WI; ++i) {
+                acc[i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b0, acc[i][0], 0, 0, 0);
+                acc[i][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b1, acc[i][1], 0, 0, 0);
+            }
         }
     }
     float *C = (float *)g.C + (int64_t)blockIdx.z * g.c_split_stride;
     const float *act = (const float *)g.act;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int col = n0 + wn + j * 32 + li;
@@ -251,10 +258,10 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g0) {
         }
 }
 
-template <bool AK, bool BN_, int EPI>
+template <bool AK, bool BN_, int EPI, int TM>
 static void launch_gemm_t(hipStream_t st, const GemmArgs &g, int splits) {
-    int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
-    hipLaunchKernelGGL((k_gemm_f32<AK, BN_, EPI>), dim3(tiles, 1, splits), dim3(256), 0, st, g);
+    int tiles = ((g.M + TM - 1) / TM) * ((g.N + BN - 1) / BN);
+    hipLaunchKernelGGL((k_gemm_f32<AK, BN_, EPI, TM>), dim3(tiles, 1, splits), dim3(256), 0, st, g);
 }
 
 static int split_chunk(int K, int splits) {
@@ -263,22 +270,29 @@ static int split_chunk(int K, int splits) {
     return chunk > 0 ? chunk : BK;
 }
 
-void launch_gemm_f32(hipStream_t st, const GemmArgs &g0, bool a_kcontig, bool b_ncontig, int epi, int splits) {
+void launch_gemm_f32(hipStream_t st, const GemmArgs &g0, bool a_kcontig, bool b_ncontig, int epi, int splits,
+                     int tm) {
     GemmArgs g = g0;
     if (splits < 1) splits = 1;
     g.k_chunk = split_chunk(g.K, splits);
-#define DISPATCH(AK, BNC)                                                                               \
-    switch (epi) {                                                                                      \
-        case EPI_STORE: launch_gemm_t<AK, BNC, EPI_STORE>(st, g, splits); break;   \
-        case EPI_BIAS: launch_gemm_t<AK, BNC, EPI_BIAS>(st, g, splits); break;     \
-        case EPI_BIAS_TANH: launch_gemm_t<AK, BNC, EPI_BIAS_TANH>(st, g, splits); break; \
-        case EPI_DTANH: launch_gemm_t<AK, BNC, EPI_DTANH>(st, g, splits); break;   \
+#define DISPATCH_TM(AK, BNC, EPI)                                           \
+    if (tm == 64)                                                           \
+        launch_gemm_t<AK, BNC, EPI, 64>(st, g, splits);                     \
+    else                                                                    \
+        launch_gemm_t<AK, BNC, EPI, 128>(st, g, splits);
+#define DISPATCH(AK, BNC)                                                   \
+    switch (epi) {                                                          \
+        case EPI_STORE: DISPATCH_TM(AK, BNC, EPI_STORE) break;              \
+        case EPI_BIAS: DISPATCH_TM(AK, BNC, EPI_BIAS) break;                \
+        case EPI_BIAS_TANH: DISPATCH_TM(AK, BNC, EPI_BIAS_TANH) break;      \
+        case EPI_DTANH: DISPATCH_TM(AK, BNC, EPI_DTANH) break;              \
     }
     if (a_kcontig && b_ncontig) { DISPATCH(true, true) }
     else if (a_kcontig && !b_ncontig) { DISPATCH(true, false) }
     else if (!a_kcontig && b_ncontig) { DISPATCH(false, true) }
     else { DISPATCH(false, false) }
 #undef DISPATCH
+#undef DISPATCH_TM
 }
 
 // out[i] = sum_z part[z*count + i], fixed order
