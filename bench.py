@@ -74,6 +74,89 @@ def cpu_baseline(p, sample_n: int):
 PRECISIONS = {"fp32": "FP32", "mixed": "MIXED", "split_bf16": "SPLIT_BF16"}
 
 
+def bench_curve(args, dnqs, synth, torch):
+    """One optimisation step over G geometries: G sequential energy_and_grad calls, one
+    batched call, and a replayed HIP graph of the batched step + AdamW (same stream)."""
+    wl = synth.WORKLOADS["m20_6a6b_curve"]
+    prec = getattr(dnqs, PRECISIONS[args.precision])
+    print(f"[bench] building {args.curve} geometries", file=sys.stderr, flush=True)
+    curve = synth.make_curve(wl, n_geoms=args.curve, out_scale=args.out_scale)
+    sizes = [p.dets.shape[0] for p in curve]
+    ntot = sum(sizes)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = dnqs.Context(0)
+        ctx.autotune(True)
+        conns = []
+        for g, p in enumerate(curve):
+            ctx.set_integrals(p.h, p.eri, p.e_core, wl.n_alpha, wl.n_beta, slot=g)
+            conns.append(ctx.build_connections(dnqs.dets_to_device(p.dets), slot=g, validate=False))
+        thetas = [torch.from_numpy(p.theta).cuda() for p in curve]
+        batch = ctx.batch(wl.widths, list(range(len(curve))), conns, thetas)
+        np_ = thetas[0].numel()
+        m = torch.zeros(len(curve) * np_, device="cuda")
+        v = torch.zeros(len(curve) * np_, device="cuda")
+        step = torch.zeros(1, dtype=torch.int32, device="cuda")
+        reps = max(args.steps, 3)
+
+        def timed(fn):
+            for _ in range(max(args.warmup, 1)):
+                fn()
+            stream.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            e1.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        t_seq = timed(lambda: [ctx.energy_and_grad(wl.widths, thetas[g], conns[g], precision=prec, keep=False)
+                               for g in range(len(curve))])
+        t_bat = timed(lambda: ctx.energy_and_grad_batched(batch, precision=prec))
+        ctx.energy_and_grad_batched(batch, precision=prec)
+        ctx.capture_begin()
+        ctx.energy_and_grad_batched(batch, precision=prec)
+        ctx.adamw_batched(batch, m, v, step)
+        graph = ctx.capture_end()
+        t_graph = timed(graph.launch)
+        graph.free()
+    line = {
+        "metric": "amps+grads/s over a dissociation curve (one optimisation step over all geometries)",
+        "value": ntot / (t_graph * 1e-3), "unit": "amps+grads/s", "n_gpus": 1, "steps": reps,
+        "warmup": args.warmup, "ms_per_step": t_graph, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if prec == dnqs.FP32 else "bf16x3+f32", "data": "synthetic",
+        "config": {"workload": wl.name, "geometries": len(curve), "total_dets": ntot, "min_dets": min(sizes),
+                   "max_dets": max(sizes), "widths": list(wl.widths), "precision": args.precision},
+        "sequential_ms": t_seq, "batched_ms": t_bat, "graph_step_ms": t_graph,
+        "speedup_batched_vs_sequential": t_seq / t_bat, "speedup_graph_vs_sequential": t_seq / t_graph,
+        "autotune": ctx.tune_export().strip().splitlines(),
+    }
+    print(json.dumps(line))
+
+
+# HBM bytes per launch of a kernel from two rocprofv3 --pmc passes (FETCH_SIZE x 2.0,
+# WRITE_SIZE x 1.0, the factors a 1 GiB device copy gives), valid only for the kernel
+# source they were taken on (profiles/pt2_m28_s1e5_hbm_counters.md).
+MEASURED_TRAFFIC = {
+    ("k_pt2_reduce", "m28_7a7b_s100k"): ("paper_2601_21310_amd/csrc/k_pt2_part.hip",
+                                          "bbec564def08a3fe910c6a7c4c8706c9555defdee9da6c1ab3741f97eecacd66",
+                                          26269499987.5),
+}
+
+
+def measured_traffic(kernel, workload):
+    import hashlib
+    rec = MEASURED_TRAFFIC.get((kernel, workload))
+    if rec is None:
+        return None
+    path, sha, nbytes = rec
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), path), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != sha:
+            return None          # the kernel changed since the counters were taken
+    return nbytes
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,8 +167,13 @@ def main():
     ap.add_argument("--precision", choices=list(PRECISIONS), default="mixed")
     ap.add_argument("--out-scale", type=float, default=1e-2,
                     help="scale of the Glorot output layer (small, as the paper initialises it)")
-    ap.add_argument("--cpu-sample", type=int, default=3000)
+    ap.add_argument("--cpu-sample", type=int, default=50000,
+                    help="dets of S the oracle is timed on (about 10-30 s of host work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--curve", type=int, default=0,
+                    help="instead of the headline run: energy+gradient over a synthetic dissociation curve of "
+                         "this many geometries (M=20, 6a+6b, |S| log-uniform in [2^10, 2^16]), sequential vs "
+                         "batched vs a replayed HIP graph of the batched step with AdamW")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a device copy of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -110,6 +198,9 @@ def main():
 
     import paper_2601_21310_amd as dnqs
     import synth
+
+    if args.curve:
+        return bench_curve(args, dnqs, synth, torch)
 
     wl = synth.WORKLOADS[args.workload]
     print(f"[bench] building inputs for {wl.name}", file=sys.stderr, flush=True)
@@ -176,10 +267,16 @@ def main():
     o = out["out"].cpu().numpy()
     c = out["counts"].cpu().numpy()
     pairs = int(c[0])
-    # PT2 traffic model: an 8-byte descriptor per (x, a) pair is written by L1, read
-    # twice and written once by L2, and read by the reduce: 40 B/pair over the phase.
-    pt2_bytes = 40.0 * pairs
-    achieved = pt2_bytes / (t_p * 1e-3) / 1e9
+    # Roofline of the dominant kernel, the PT2 reduce: it streams one 8-byte pair
+    # descriptor per (x, a) pair (its gathers of dets, psi and integrals hit L2);
+    # duration = its average HIP-event time on the library stream.
+    t_red = avg["pt2_reduce"]
+    red_bytes = 8.0 * pairs
+    achieved = red_bytes / (t_red * 1e-3) / 1e9
+    traffic = measured_traffic("k_pt2_reduce", wl.name)
+    # the whole PT2 phase against the 40 B/pair group-by model (write + read of a
+    # 16-byte key and a 4-byte value per pair)
+    pt2_model = 40.0 * pairs
     line = {
         "metric": "amps+grads/s and H/PT2 elements/s at |S|=1e5; mixed vs FP32 at 1e-5 Ha",
         "value": n / (t_e * 1e-3),
@@ -202,9 +299,12 @@ def main():
         "results": {"E": E, "dE_pt2": float(o[0]), "E_total": E + float(o[0]), "min_denominator": float(o[3])},
         "precisions": compare,
         "autotune": ctx.tune_export().strip().splitlines(),
-        "roofline": {"kernel": "pt2 (L1 + L2 + reduce)", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes_per_launch": pt2_bytes},
+        "roofline": {"kernel": "k_pt2_reduce", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": red_bytes, "launch_ms": t_red},
+        "pt2_phase_roofline": {"model": "40 B/pair group-by", "bytes": pt2_model, "ms": t_p,
+                               "achieved": pt2_model / (t_p * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": pt2_model / (t_p * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
