@@ -304,6 +304,21 @@ void launch_gemm(int engine, hipStream_t st, const GemmArgs &g, bool a_kcontig, 
         launch_gemm_f32(st, g, a_kcontig, b_ncontig, epi, splits, tm);
 }
 
+// BF16 hi / lo planes of a layer's weights W (din x dout, row-major) for the split-BF16
+// engine: [dout][din] for the forward GEMM (transpose), [din][dout] for the data
+// gradient; split once per call, in workspace `name`.
+dnqs_status weight_planes(dnqs_ctx *ctx, const std::string &name, const float *W, int din, int dout, bool transpose,
+                          GemmArgs &g) {
+    void *planes = nullptr;
+    TRY(ws_get(ctx, name, (size_t)din * dout * 2 * sizeof(uint16_t), &planes));
+    launch_split_planes(ctx->stream, W, din, dout, transpose, planes);
+    CHECK_LAUNCH(ctx);
+    g.bsplit = planes;
+    g.ldbs = transpose ? din : dout;
+    g.bs_plane = (int64_t)din * dout;
+    return DNQS_OK;
+}
+
 // Runs launch(cfg) with the configuration of `key`: the tuned one if the table has it;
 // else, with tuning on and no capture in progress, every candidate is timed on the
 // context stream (one warm-up and three timed runs each, HIP events) and the fastest
@@ -400,6 +415,7 @@ dnqs_status forward(dnqs_ctx *ctx, const Slot &sl, const NetView &nv, const floa
         g.bias = theta + nv.offb[l];
         g.ones_row = -1;
         const int eng = gemm_engine(precision, l == L);
+        if (eng == 1) TRY(weight_planes(ctx, "wpT" + std::to_string(l), theta + nv.offW[l], w[l - 1], w[l], true, g));
         const int epi = l < L ? EPI_BIAS_TANH : EPI_BIAS;
         TRY(tuned_launch(ctx, TuneKey{eng, 0, g.M, g.N, g.K}, gemm_candidates(g.M, g.N, g.K, false, false),
                          [&](const GemmCfg &c) -> dnqs_status {
@@ -786,6 +802,7 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
         d.ldact = din;
         d.ones_row = -1;
         const int deng = gemm_engine(precision, l == L);
+        if (deng == 1) TRY(weight_planes(ctx, "wp" + std::to_string(l), theta + nv.offW[l], din, dout, false, d));
         TRY(tuned_launch(ctx, TuneKey{deng, 2, d.M, d.N, d.K}, gemm_candidates(d.M, d.N, d.K, false, false),
                          [&](const GemmCfg &c) -> dnqs_status {
                              launch_gemm(deng, st, d, true, false, EPI_DTANH, 1, c.tm);

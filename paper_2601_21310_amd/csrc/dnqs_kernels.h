@@ -54,6 +54,11 @@ struct GemmArgs {
     const void *const *Bg;
     const float *const *biasg;
     const int2 *ksplit;         // k range [x, y) of each blockIdx.z (split-K over problems)
+    // split-BF16 engine only, optional: B given as BF16 hi / lo planes, both [n][k]
+    // (k-contiguous, leading dimension ldbs); the lo plane starts bs_plane elements
+    // after the hi plane.  Used for weights, split once per call.
+    const void *bsplit;
+    int64_t ldbs, bs_plane;
 };
 
 // One problem of a batched launch (rows off .. off+n-1 of the concatenated layout;
@@ -82,6 +87,9 @@ void launch_gemm_f32(hipStream_t st, const GemmArgs &g, bool a_kcontig, bool b_n
                      int tm = 128);
 void launch_gemm_x3(hipStream_t st, const GemmArgs &g, bool a_kcontig, bool b_ncontig, int epi, int splits,
                     int tm = 128);
+// hi = bf16(W), lo = bf16(W - hi) of a row-major R x C FP32 matrix, written as planes
+// [C][R] (transpose) or [R][C]; lo = hi + R * C
+void launch_split_planes(hipStream_t st, const float *W, int R, int C, bool transpose, void *planes);
 void launch_reduce_splits(hipStream_t st, const float *part, int splits, int64_t count, float *out);
 int orb_lu_group(int ne);
 void launch_orb_lu(hipStream_t st, const uint64_t *dets, int64_t n, int M, int na, int nb, const float *O,

@@ -1,9 +1,9 @@
 // Split-BF16 MFMA GEMM for the mixed-precision form: C = epi(A B) with A, B and C in FP32
 // in HBM, computed on v_mfma_f32_32x32x16_bf16 with FP32 accumulation.
 //
-// Each operand value x is split when it is staged into LDS as x_hi = bf16(x) and
-// x_lo = bf16(x - x_hi), so x = x_hi + x_lo to about 2^-17 relative.  A product is taken
-// as a_lo b_hi + a_hi b_lo + a_hi b_hi (the a_lo b_lo term, ~2^-18 relative, is dropped):
+// Each operand value x is split as x_hi = bf16(x) and x_lo = bf16(x - x_hi), so
+// x = x_hi + x_lo to about 2^-17 relative.  A product is taken as
+// a_lo b_hi + a_hi b_lo + a_hi b_hi (the a_lo b_lo term, ~2^-18 relative, is dropped):
 // three BF16 MFMAs per operand pair, FP32 accumulation.  A single BF16 product (operands
 // rounded to 2^-9) moves the variational energy by a few 1e-5 Ha at the headline size;
 // the split form keeps it near 1e-7 Ha at a sixth of the BF16 MFMA peak, which is still
@@ -12,13 +12,16 @@
 // Tiles: TM x 128 per workgroup (TM = 128 or 64), K step 32; 4 waves as 2 x 2, each
 // (TM/2) x 64 = WI x 2 MFMA tiles.  LDS holds the hi and lo parts of both operands
 // k-contiguous ([row][k], rows padded by 8 bf16 so a wave's 16-byte fragment reads are
-// free of bank conflicts); 40 KB per workgroup at TM = 128.  MFMA lane layout: A[i][k]
-// comes from lane i + 32*(k/8), element k%8; B[k][j] from lane j + 32*(k/8); C/D rows
-// 8*(r/4) + 4*(lane/32) + r%4, column lane%32.
+// free of bank conflicts), double-buffered: 80 KB per workgroup at TM = 128, one
+// barrier per K step; global loads are issued two K steps before their data is staged,
+// so that a step's MFMAs (768 cycles per wave) hide most of the memory latency.
+// MFMA lane layout: A[i][k] comes from lane i + 32*(k/8), element k%8; B[k][j] from lane
+// j + 32*(k/8); C/D rows 8*(r/4) + 4*(lane/32) + r%4, column lane%32.
 //
-// Operands are FP32 in either orientation: "k-contiguous" (row r, k at r*ld + k) or
-// "row-contiguous" (k at k*ld + r).  The epilogues and the split-K / grouped-problem
-// arguments are those of the FP32 MFMA GEMM (GemmArgs).
+// Operands are FP32 in either orientation, "k-contiguous" (row r, k at r*ld + k) or
+// "row-contiguous" (k at k*ld + r), split while staged into LDS; or, for B only, BF16
+// hi / lo planes split once beforehand (weights), staged by plain copies.  The epilogues
+// and the split-K / grouped-problem arguments are those of the FP32 MFMA GEMM.
 #include "dnqs_device.h"
 #include "dnqs_kernels.h"
 
@@ -46,14 +49,16 @@ __device__ __forceinline__ void split_bf16(float x, bf16_t &hi, bf16_t &lo) {
     lo = (bf16_t)(x - (float)hi);
 }
 
-// One operand tile: ROWS rows x 32 k of an FP32 matrix P into registers r[16]; threads
-// t < 2*ROWS take part.
+// One FP32 operand tile: ROWS rows x 32 k of P into registers r[16]; threads t < 2*ROWS
+// take part.
 //   KC (k-contiguous, P[row*ld + k]):   thread = (row t/2, k 16*(t%2) .. +15)
-//   !KC (row-contiguous, P[k*ld + row]): thread = (rows 4*(t%(ROWS/4)) .. +3,
-//                                        k 4*(t/(ROWS/4)) .. +3), r[4*kk + rr] = P[k+kk][row+rr]
+//   !KC (row-contiguous, P[k*ld + row]): thread = (rows 4*(t/8) .. +3, k 4*(t%8) .. +3),
+//                                        r[4*kk + rr] = P[k+kk][row+rr]
+// (in the !KC mapping eight consecutive lanes cover the 32 k of four rows, so their
+// 8-byte LDS writes fall on distinct banks.)
 // Rows >= rows_ld and k >= kend read as 0; row `ones` (if >= 0) reads as 1 for k < kend.
 template <bool KC, int ROWS>
-__device__ __forceinline__ void xload(const float *__restrict__ P, int ld, int r0, int rows_ld, int ones, int k0,
+__device__ __forceinline__ void xload(const float *__restrict__ P, int64_t ld, int r0, int rows_ld, int ones, int k0,
                                       int kend, float (&r)[16]) {
     const int t = threadIdx.x;
     if (t >= 2 * ROWS) return;
@@ -78,7 +83,7 @@ __device__ __forceinline__ void xload(const float *__restrict__ P, int ld, int r
             for (int j = 0; j < 16; ++j) r[j] = (k + j < kend) ? 1.0f : 0.0f;
         }
     } else {
-        const int row = r0 + 4 * (t % (ROWS / 4)), k = k0 + 4 * (t / (ROWS / 4));
+        const int row = r0 + 4 * (t >> 3), k = k0 + 4 * (t & 7);
         const bool vec = row + 4 <= rows_ld && (ld & 3) == 0 && ((((uintptr_t)(P + row)) & 15) == 0);
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
@@ -122,7 +127,7 @@ __device__ __forceinline__ void xstore(bf16_t (*Hs)[XLD], bf16_t (*Ls)[XLD], con
             *(bf16x8_t *)&Ls[row][k + 8 * q] = l;
         }
     } else {
-        const int row = 4 * (t % (ROWS / 4)), k = 4 * (t / (ROWS / 4));
+        const int row = 4 * (t >> 3), k = 4 * (t & 7);
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
             bf16x4_t h, l;
@@ -139,16 +144,56 @@ __device__ __forceinline__ void xstore(bf16_t (*Hs)[XLD], bf16_t (*Ls)[XLD], con
     }
 }
 
+// A pre-split B tile (128 rows n x 32 k of the hi and lo planes): thread = (n t/2,
+// k 16*(t%2) .. +15), 16 hi and 16 lo values.
+struct PreTile {
+    bf16x8_t h0, h1, l0, l1;
+};
+
+__device__ __forceinline__ void pload(const bf16_t *__restrict__ hi, const bf16_t *__restrict__ lo, int64_t ld,
+                                      int n0, int N, int k0, int kend, PreTile &r) {
+    const int t = threadIdx.x;
+    const int n = n0 + (t >> 1), k = k0 + (t & 1) * 16;
+    const int64_t off = (int64_t)n * ld + k;
+    if (n < N && k + 16 <= kend && (ld & 7) == 0 && (((uintptr_t)(hi + off)) & 15) == 0 &&
+        (((uintptr_t)(lo + off)) & 15) == 0) {
+        r.h0 = *(const bf16x8_t *)(hi + off);
+        r.h1 = *(const bf16x8_t *)(hi + off + 8);
+        r.l0 = *(const bf16x8_t *)(lo + off);
+        r.l1 = *(const bf16x8_t *)(lo + off + 8);
+    } else {
+        const bf16_t z = (bf16_t)0.0f;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const bool ok0 = n < N && k + j < kend, ok1 = n < N && k + 8 + j < kend;
+            r.h0[j] = ok0 ? hi[off + j] : z;
+            r.l0[j] = ok0 ? lo[off + j] : z;
+            r.h1[j] = ok1 ? hi[off + 8 + j] : z;
+            r.l1[j] = ok1 ? lo[off + 8 + j] : z;
+        }
+    }
+}
+
+__device__ __forceinline__ void pstore(bf16_t (*Hs)[XLD], bf16_t (*Ls)[XLD], const PreTile &r) {
+    const int t = threadIdx.x;
+    const int n = t >> 1, k = (t & 1) * 16;
+    *(bf16x8_t *)&Hs[n][k] = r.h0;
+    *(bf16x8_t *)&Hs[n][k + 8] = r.h1;
+    *(bf16x8_t *)&Ls[n][k] = r.l0;
+    *(bf16x8_t *)&Ls[n][k + 8] = r.l1;
+}
+
 // AK: A k-contiguous (A[m*lda + k]) else A[k*lda + m].  BNC: B n-contiguous
-// (B[k*ldb + n], i.e. row-contiguous in the [n][k] view) else B[n*ldb + k].
-template <bool AK, bool BNC, int EPI, int TM>
-__global__ __launch_bounds__(256) void k_gemm_x3(GemmArgs g0) {
+// (B[k*ldb + n], i.e. row-contiguous in the [n][k] view) else B[n*ldb + k].  BPRE: B
+// from the pre-split planes g.bsplit (BNC ignored).
+template <bool AK, bool BNC, int EPI, int TM, bool BPRE>
+__global__ __launch_bounds__(256, 2) void k_gemm_x3(GemmArgs g0) {
     constexpr int WI = TM / 64;
     GemmArgs g = g0;
-    __shared__ __attribute__((aligned(16))) bf16_t Ah[TM][XLD];
-    __shared__ __attribute__((aligned(16))) bf16_t Al[TM][XLD];
-    __shared__ __attribute__((aligned(16))) bf16_t Bh[XBN][XLD];
-    __shared__ __attribute__((aligned(16))) bf16_t Bl[XBN][XLD];
+    __shared__ __attribute__((aligned(16))) bf16_t Ah[2][TM][XLD];
+    __shared__ __attribute__((aligned(16))) bf16_t Al[2][TM][XLD];
+    __shared__ __attribute__((aligned(16))) bf16_t Bh[2][XBN][XLD];
+    __shared__ __attribute__((aligned(16))) bf16_t Bl[2][XBN][XLD];
     const int tiles_n = (g.N + XBN - 1) / XBN;
     const int tiles_m = (g.M + TM - 1) / TM;
     const int L = xcd_remap_x(blockIdx.x, tiles_n * tiles_m);
@@ -167,6 +212,8 @@ __global__ __launch_bounds__(256) void k_gemm_x3(GemmArgs g0) {
     if (kend > g.K) kend = g.K;
     const float *A = (const float *)g.A;
     const float *B = (const float *)g.B;
+    const bf16_t *Bhi = (const bf16_t *)g.bsplit;
+    const bf16_t *Blo = BPRE ? Bhi + g.bs_plane : nullptr;
     const int mload = g.ones_row >= 0 ? g.ones_row : g.M;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = (wave >> 1) * (TM / 2), wn = (wave & 1) * 64;
@@ -180,42 +227,83 @@ __global__ __launch_bounds__(256) void k_gemm_x3(GemmArgs g0) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-    float ra[16], rb[16];
-    if (kbeg < kend) {
-        xload<AK, TM>(A, g.lda, m0, mload, g.ones_row, kbeg, kend, ra);
-        xload<!BNC, XBN>(B, g.ldb, n0, g.N, -1, kbeg, kend, rb);
-    }
-    for (int k0 = kbeg; k0 < kend; k0 += XBK) {
-        __syncthreads();
-        xstore<AK, TM>(Ah, Al, ra);
-        xstore<!BNC, XBN>(Bh, Bl, rb);
-        __syncthreads();
-        if (k0 + XBK < kend) {
-            xload<AK, TM>(A, g.lda, m0, mload, g.ones_row, k0 + XBK, kend, ra);
-            xload<!BNC, XBN>(B, g.ldb, n0, g.N, -1, k0 + XBK, kend, rb);
-        }
+    // Global loads run two K steps ahead: register set 0 holds the even steps, set 1
+    // the odd ones; the loop is unrolled by two so that the sets stay static.
+    float ra0[16], rb0[16], ra1[16], rb1[16];
+    PreTile pb0, pb1;
+    auto load = [&](int step, float (&ra)[16], float (&rb)[16], PreTile &pb) {
+        const int k0 = kbeg + step * XBK;
+        xload<AK, TM>(A, g.lda, m0, mload, g.ones_row, k0, kend, ra);
+        if (BPRE)
+            pload(Bhi, Blo, g.ldbs, n0, g.N, k0, kend, pb);
+        else
+            xload<!BNC, XBN>(B, g.ldb, n0, g.N, -1, k0, kend, rb);
+    };
+    auto store = [&](int buf, const float (&ra)[16], const float (&rb)[16], const PreTile &pb) {
+        xstore<AK, TM>(Ah[buf], Al[buf], ra);
+        if (BPRE)
+            pstore(Bh[buf], Bl[buf], pb);
+        else
+            xstore<!BNC, XBN>(Bh[buf], Bl[buf], rb);
+    };
+    auto compute = [&](int cur) {
 #pragma unroll
         for (int ks = 0; ks < XBK; ks += 16) {
             bf16x8_t ah[WI], al[WI], bh[2], bl[2];
 #pragma unroll
             for (int i = 0; i < WI; ++i) {
-                ah[i] = *(const bf16x8_t *)&Ah[wm + 32 * i + li][ks + lk];
-                al[i] = *(const bf16x8_t *)&Al[wm + 32 * i + li][ks + lk];
+                ah[i] = *(const bf16x8_t *)&Ah[cur][wm + 32 * i + li][ks + lk];
+                al[i] = *(const bf16x8_t *)&Al[cur][wm + 32 * i + li][ks + lk];
             }
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                bh[j] = *(const bf16x8_t *)&Bh[wn + 32 * j + li][ks + lk];
-                bl[j] = *(const bf16x8_t *)&Bl[wn + 32 * j + li][ks + lk];
+                bh[j] = *(const bf16x8_t *)&Bh[cur][wn + 32 * j + li][ks + lk];
+                bl[j] = *(const bf16x8_t *)&Bl[cur][wn + 32 * j + li][ks + lk];
             }
+            // three passes over the WI x 2 accumulators, so that consecutive MFMAs never
+            // depend on each other (a dependent MFMA waits for the previous result)
 #pragma unroll
             for (int i = 0; i < WI; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
+                for (int j = 0; j < 2; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < WI; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < WI; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-                }
         }
+    };
+    const int nk = kend > kbeg ? (kend - kbeg + XBK - 1) / XBK : 0;
+    // step s lives in register set s % 2 and LDS buffer s % 2
+    if (nk > 0) {
+        load(0, ra0, rb0, pb0);
+        store(0, ra0, rb0, pb0);
+        if (nk > 1) load(1, ra1, rb1, pb1);
+        if (nk > 2) load(2, ra0, rb0, pb0);
+    }
+    __syncthreads();
+    for (int it = 0; it < nk; it += 2) {
+        // even step it: LDS buffer 0; stage step it+1 (set 1) into buffer 1
+        compute(0);
+        if (it + 1 < nk) {
+            store(1, ra1, rb1, pb1);
+            if (it + 3 < nk) load(it + 3, ra1, rb1, pb1);
+        }
+        __syncthreads();
+        if (it + 1 >= nk) break;
+        // odd step it+1: LDS buffer 1; stage step it+2 (set 0) into buffer 0
+        compute(1);
+        if (it + 2 < nk) {
+            store(0, ra0, rb0, pb0);
+            if (it + 4 < nk) load(it + 4, ra0, rb0, pb0);
+        }
+        __syncthreads();
     }
     float *C = (float *)g.C + (int64_t)blockIdx.z * g.c_split_stride;
     const float *act = (const float *)g.act;
@@ -243,13 +331,11 @@ __global__ __launch_bounds__(256) void k_gemm_x3(GemmArgs g0) {
         }
 }
 
-template <bool AK, bool BNC, int EPI, int TM>
+template <bool AK, bool BNC, int EPI, int TM, bool BPRE>
 static void launch_x(hipStream_t st, GemmArgs g, int splits) {
     const int tiles = ((g.M + TM - 1) / TM) * ((g.N + XBN - 1) / XBN);
-    hipLaunchKernelGGL((k_gemm_x3<AK, BNC, EPI, TM>), dim3(tiles, 1, splits), dim3(256), 0, st, g);
+    hipLaunchKernelGGL((k_gemm_x3<AK, BNC, EPI, TM, BPRE>), dim3(tiles, 1, splits), dim3(256), 0, st, g);
 }
-
-int gemm_x3_kstep() { return XBK; }
 
 void launch_gemm_x3(hipStream_t st, const GemmArgs &g0, bool a_kcontig, bool b_ncontig, int epi, int splits,
                     int tm) {
@@ -258,11 +344,27 @@ void launch_gemm_x3(hipStream_t st, const GemmArgs &g0, bool a_kcontig, bool b_n
     int chunk = (g.K + splits - 1) / splits;
     chunk = (chunk + XBK - 1) / XBK * XBK;
     g.k_chunk = chunk > 0 ? chunk : XBK;
-#define DISPATCH_TM(AK, BNC, EPI)                    \
-    if (tm == 64)                                    \
-        launch_x<AK, BNC, EPI, 64>(st, g, splits);   \
-    else                                             \
-        launch_x<AK, BNC, EPI, 128>(st, g, splits);
+    if (g.bsplit && a_kcontig) {  // weights as B: pre-split planes
+#define DISPATCH_PRE(EPI)                                    \
+    if (tm == 64)                                            \
+        launch_x<true, false, EPI, 64, true>(st, g, splits);  \
+    else                                                     \
+        launch_x<true, false, EPI, 128, true>(st, g, splits);
+        switch (epi) {
+            case EPI_STORE: DISPATCH_PRE(EPI_STORE) break;
+            case EPI_BIAS: DISPATCH_PRE(EPI_BIAS) break;
+            case EPI_BIAS_TANH: DISPATCH_PRE(EPI_BIAS_TANH) break;
+            case EPI_DTANH: DISPATCH_PRE(EPI_DTANH) break;
+        }
+#undef DISPATCH_PRE
+        return;
+    }
+    g.bsplit = nullptr;
+#define DISPATCH_TM(AK, BNC, EPI)                          \
+    if (tm == 64)                                          \
+        launch_x<AK, BNC, EPI, 64, false>(st, g, splits);  \
+    else                                                   \
+        launch_x<AK, BNC, EPI, 128, false>(st, g, splits);
 #define DISPATCH(AK, BNC)                                              \
     switch (epi) {                                                     \
         case EPI_STORE: DISPATCH_TM(AK, BNC, EPI_STORE) break;         \
@@ -276,6 +378,26 @@ void launch_gemm_x3(hipStream_t st, const GemmArgs &g0, bool a_kcontig, bool b_n
     else { DISPATCH(false, false) }
 #undef DISPATCH
 #undef DISPATCH_TM
+}
+
+// hi / lo planes of a row-major R x C FP32 matrix: out[c][r] (transpose) or out[r][c]
+__global__ void k_split_planes(const float *__restrict__ W, int R, int C, bool transpose, bf16_t *__restrict__ hi) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)R * C;
+    if (i >= total) return;
+    const int r = (int)(i / C), c = (int)(i % C);
+    bf16_t h, l;
+    split_bf16(W[i], h, l);
+    const int64_t o = transpose ? (int64_t)c * R + r : i;
+    hi[o] = h;
+    hi[total + o] = l;
+}
+
+void launch_split_planes(hipStream_t st, const float *W, int R, int C, bool transpose, void *planes) {
+    const int64_t total = (int64_t)R * C;
+    if (total == 0) return;
+    hipLaunchKernelGGL(k_split_planes, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, W, R, C, transpose,
+                       (bf16_t *)planes);
 }
 
 }  // namespace dnqs
