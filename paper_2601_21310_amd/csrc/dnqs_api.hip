@@ -874,7 +874,9 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
     // half of the 4096-slot LDS table
     const int64_t nsb_target = std::max<int64_t>(1, pairs / 6000);
     int s1 = 0;
-    while (((int64_t)1 << s1) < nsb_target && (1 << s1) < pt2_max_k1()) ++s1;
+    // K1 <= 512: an L1 round of 8192 descriptors then holds ~16 per bucket (one 128-byte
+    // line per run), and 2^19 sub-buckets leave K2 <= 1024 for the staged L2 pass
+    while (((int64_t)1 << s1) < nsb_target && (1 << s1) < std::min(512, pt2_max_k1())) ++s1;
     int s2 = 0;
     while (((int64_t)1 << (s1 + s2)) < nsb_target && (1 << s2) < pt2_max_k2()) ++s2;
     const int K1 = 1 << s1;

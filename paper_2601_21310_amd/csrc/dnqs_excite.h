@@ -12,16 +12,40 @@ namespace dnqs {
 
 constexpr uint32_t kNoPos = 127u;
 
+// n / d and n % d for 0 <= n, d < 2^24: a float-reciprocal estimate (off by at most a
+// few) corrected to the exact quotient with integer arithmetic.
+struct FastDiv {
+    int d;
+    float r;
+};
+
+__device__ __forceinline__ FastDiv make_fastdiv(int d) { return FastDiv{d, 1.0f / (float)d}; }
+
+__device__ __forceinline__ int fdiv(int n, const FastDiv &f, int &rem) {
+    int q = (int)((float)n * f.r);
+    int r = n - q * f.d;
+    while (r < 0) {
+        --q;
+        r += f.d;
+    }
+    while (r >= f.d) {
+        ++q;
+        r -= f.d;
+    }
+    rem = r;
+    return q;
+}
+
+// Excitation ids are below 2^24 (n_exc of any sector with M <= 64 is ~1.4e6 at most).
 struct ExcLists {
     const uint8_t *oa, *va, *ob, *vb;  // occupied / empty orbitals per spin string
-    int nva, nvb;
-    int64_t pva, pvb, nsb;
-    int64_t c1, c2, c3, c4, total;     // class boundaries
+    FastDiv nva, nvb, pva, pvb, nsb;   // class sizes used as divisors
+    int c1, c2, c3, c4, total;         // class boundaries
 };
 
 // pair index t over n items (i < j), ordered by j then i: t = j(j-1)/2 + i
 __device__ __forceinline__ void unrank_pair(int t, int &i, int &j) {
-    int jj = (int)((1.0 + sqrt(1.0 + 8.0 * (double)t)) * 0.5);
+    int jj = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)t)) * 0.5f);
     while (jj * (jj - 1) / 2 > t) --jj;
     while ((jj + 1) * jj / 2 <= t) ++jj;
     j = jj;
@@ -46,18 +70,21 @@ __device__ inline ExcLists make_exc_lists(const uint8_t (*lists)[64], int M, int
     c.va = lists[1];
     c.ob = lists[2];
     c.vb = lists[3];
-    c.nva = M - na;
-    c.nvb = M - nb;
-    const int64_t nsa = (int64_t)na * c.nva;
-    c.nsb = (int64_t)nb * c.nvb;
-    c.pva = (int64_t)c.nva * (c.nva - 1) / 2;
-    c.pvb = (int64_t)c.nvb * (c.nvb - 1) / 2;
-    const int64_t ndaa = (int64_t)na * (na - 1) / 2 * c.pva, ndbb = (int64_t)nb * (nb - 1) / 2 * c.pvb;
+    const int nva = M - na, nvb = M - nb;
+    const int nsa = na * nva, nsb = nb * nvb;
+    const int pva = nva * (nva - 1) / 2, pvb = nvb * (nvb - 1) / 2;
+    // a size-0 class is never divided by; keep its divisor at 1
+    c.nva = make_fastdiv(nva > 0 ? nva : 1);
+    c.nvb = make_fastdiv(nvb > 0 ? nvb : 1);
+    c.pva = make_fastdiv(pva > 0 ? pva : 1);
+    c.pvb = make_fastdiv(pvb > 0 ? pvb : 1);
+    c.nsb = make_fastdiv(nsb > 0 ? nsb : 1);
+    const int ndaa = na * (na - 1) / 2 * pva, ndbb = nb * (nb - 1) / 2 * pvb;
     c.c1 = nsa;
-    c.c2 = c.c1 + c.nsb;
+    c.c2 = c.c1 + nsb;
     c.c3 = c.c2 + ndaa;
     c.c4 = c.c3 + ndbb;
-    c.total = c.c4 + nsa * c.nsb;
+    c.total = c.c4 + nsa * nsb;
     return c;
 }
 
@@ -65,33 +92,36 @@ __device__ __forceinline__ uint32_t pack_pos(uint32_t p0, uint32_t p1, uint32_t 
     return p0 | (p1 << 7) | (p2 << 14) | (p3 << 21);
 }
 
-// flipped positions of excitation e
-__device__ inline uint32_t excitation_positions(const ExcLists &c, int64_t e) {
+// flipped positions of excitation e (0 <= e < total)
+__device__ inline uint32_t excitation_positions(const ExcLists &c, int e) {
+    int r;
     if (e < c.c1) {
-        const int t = (int)e;
-        return pack_pos(c.oa[t / c.nva], c.va[t % c.nva], kNoPos, kNoPos);
+        const int q = fdiv(e, c.nva, r);
+        return pack_pos(c.oa[q], c.va[r], kNoPos, kNoPos);
     }
     if (e < c.c2) {
-        const int t = (int)(e - c.c1);
-        return pack_pos(64u + c.ob[t / c.nvb], 64u + c.vb[t % c.nvb], kNoPos, kNoPos);
+        const int q = fdiv(e - c.c1, c.nvb, r);
+        return pack_pos(64u + c.ob[q], 64u + c.vb[r], kNoPos, kNoPos);
     }
     if (e < c.c3) {
-        const int64_t t = e - c.c2;
         int i, j, a, b;
-        unrank_pair((int)(t / c.pva), i, j);
-        unrank_pair((int)(t % c.pva), a, b);
+        const int q = fdiv(e - c.c2, c.pva, r);
+        unrank_pair(q, i, j);
+        unrank_pair(r, a, b);
         return pack_pos(c.oa[i], c.oa[j], c.va[a], c.va[b]);
     }
     if (e < c.c4) {
-        const int64_t t = e - c.c3;
         int i, j, a, b;
-        unrank_pair((int)(t / c.pvb), i, j);
-        unrank_pair((int)(t % c.pvb), a, b);
+        const int q = fdiv(e - c.c3, c.pvb, r);
+        unrank_pair(q, i, j);
+        unrank_pair(r, a, b);
         return pack_pos(64u + c.ob[i], 64u + c.ob[j], 64u + c.vb[a], 64u + c.vb[b]);
     }
-    const int64_t t = e - c.c4;
-    const int sa = (int)(t / c.nsb), sb = (int)(t % c.nsb);
-    return pack_pos(c.oa[sa / c.nva], c.va[sa % c.nva], 64u + c.ob[sb / c.nvb], 64u + c.vb[sb % c.nvb]);
+    int sb;
+    const int sa = fdiv(e - c.c4, c.nsb, sb);
+    int ra, rb;
+    const int qa = fdiv(sa, c.nva, ra), qb = fdiv(sb, c.nvb, rb);
+    return pack_pos(c.oa[qa], c.va[ra], 64u + c.ob[qb], 64u + c.vb[rb]);
 }
 
 // target = x with the bits at the packed positions flipped

@@ -1,0 +1,291 @@
+// Epstein-Nesbet PT2 (Eq. 13), external sum: the per-sub-bucket reduce that follows the
+// partition passes of k_pt2_part.hip.
+//
+// One workgroup per sub-bucket (~6000 pairs, ~1700 unique keys at the benchmark size):
+//   1. stage the diagonal table (h_pp, V(p,q) = J_pq - d_s K_pq; M <= 32) in LDS;
+//   2. insert the members of S that hash into this sub-bucket, flagged (S is grouped by
+//      the same hash bits once per call, k_s_sub_*), so no key is probed in the global
+//      hash set of S;
+//   3. decode every pair descriptor (x XOR flipped positions), recompute H_ax exactly in
+//      FP64 from the packed integrals and accumulate w_a = sum_x H_ax psi_x in a 4096-slot
+//      LDS table (64-bit CAS on the key, FP64 add);
+//   4. for every key not in S add w_a^2 / (E - H_aa) in FP64 to the workgroup's partial
+//      sums, H_aa from the LDS table by the diagonal rule.
+// A sub-bucket whose keys do not fit the table raises a flag and the host repeats the L2
+// split and the reduce with twice as many sub-buckets.
+#include "dnqs_device.h"
+#include "dnqs_excite.h"
+#include "dnqs_kernels.h"
+#include "dnqs_pt2.h"
+
+namespace dnqs {
+
+// ------------------------------------------------------------------ reduce
+__device__ inline void red_block(double &s, double &mn, double &np, double &nt) {
+    __shared__ double sh[4][kRedThreads / kWave];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        s += __shfl_xor(s, o, 64);
+        mn = fmin(mn, __shfl_xor(mn, o, 64));
+        np += __shfl_xor(np, o, 64);
+        nt += __shfl_xor(nt, o, 64);
+    }
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    if (lane == 0) {
+        sh[0][wave] = s;
+        sh[1][wave] = mn;
+        sh[2][wave] = np;
+        sh[3][wave] = nt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x / kWave); ++w) {
+            sh[0][0] += sh[0][w];
+            sh[1][0] = fmin(sh[1][0], sh[1][w]);
+            sh[2][0] += sh[2][w];
+            sh[3][0] += sh[3][w];
+        }
+        s = sh[0][0];
+        mn = sh[1][0];
+        np = sh[2][0];
+        nt = sh[3][0];
+    }
+}
+
+// Coulomb minus same-spin exchange between spin-orbitals s, t (alpha s < M, beta M + p)
+__device__ __forceinline__ double v_so(const Ham &H, int s, int t) {
+    const int M = H.M;
+    const bool sa = s < M, ta = t < M;
+    const int i = sa ? s : s - M, j = ta ? t : t - M;
+    double v = H.J[i * M + j];
+    if (sa == ta) v -= H.K[i * M + j];
+    return v;
+}
+
+// Diagonal table for M <= 32: vt[p] = h_pp for the 2M spin-orbitals, then
+// vt[2M + q(q-1)/2 + p] = V(p, q) for p < q, so that
+// H_aa = E_core + sum_{q in a} (vt[q] + sum_{p in a, p < q} vt[2M + q(q-1)/2 + p]).
+// 2M + M(2M-1) doubles: 12.8 KB at M = 28, 16.6 KB at M = 32.
+
+__global__ void k_diag_table(Ham H, double *__restrict__ vt) {
+    const int No = 2 * H.M;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < No) {
+        const int sp = t < H.M ? t : t - H.M;
+        vt[t] = H.h64[sp * H.M + sp];
+        return;
+    }
+    const int u = t - No;
+    if (u >= No * (No - 1) / 2) return;
+    int q = (int)((1.0 + sqrt(1.0 + 8.0 * (double)u)) * 0.5);
+    while (q * (q - 1) / 2 > u) --q;
+    while ((q + 1) * q / 2 <= u) ++q;
+    const int p = u - q * (q - 1) / 2;
+    vt[t] = v_so(H, p, q);
+}
+
+int pt2_diag_table_size(int M) { return 2 * M + (2 * M) * (2 * M - 1) / 2; }
+
+void launch_diag_table(hipStream_t st, const Ham &H, double *vt) {
+    const int total = pt2_diag_table_size(H.M);
+    hipLaunchKernelGGL(k_diag_table, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, H, vt);
+}
+
+// ------------------------------------------------------------------ S by sub-bucket
+// The keys of S grouped by the sub-bucket their hash falls in (top sbits bits, the
+// concatenated L1 and L2 bucket indices), so that each reduce workgroup can mark the
+// members of S among its keys without probing the global hash set.
+template <bool PACKED>
+__device__ __forceinline__ int64_t s_sub(uint64_t a, uint64_t b, int sbits) {
+    return sbits ? (int64_t)(target_hash<PACKED>(a, b) >> (64 - sbits)) : 0;
+}
+
+template <bool PACKED>
+__global__ void k_s_sub_count(const uint64_t *__restrict__ dets, int64_t n, int sbits, int32_t *__restrict__ cnt) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    atomicAdd(&cnt[s_sub<PACKED>(dets[2 * x], dets[2 * x + 1], sbits)], 1);
+}
+
+template <bool PACKED>
+__global__ void k_s_sub_fill(const uint64_t *__restrict__ dets, int64_t n, int sbits, const int64_t *__restrict__ offs,
+                             int32_t *__restrict__ cur, uint64_t *__restrict__ skeys) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const uint64_t a = dets[2 * x], b = dets[2 * x + 1];
+    const int64_t s = s_sub<PACKED>(a, b, sbits);
+    const int64_t pos = offs[s] + atomicAdd(&cur[s], 1);
+    skeys[2 * pos] = a;
+    skeys[2 * pos + 1] = b;
+}
+
+void launch_s_sub(hipStream_t st, const uint64_t *dets, int64_t n, int sbits, bool packed, int32_t *cnt,
+                  const int64_t *offs, uint64_t *skeys, bool fill) {
+    if (n == 0) return;
+    dim3 grid((unsigned)((n + 255) / 256)), blk(256);
+    if (fill) {
+        if (packed)
+            hipLaunchKernelGGL(k_s_sub_fill<true>, grid, blk, 0, st, dets, n, sbits, offs, cnt, skeys);
+        else
+            hipLaunchKernelGGL(k_s_sub_fill<false>, grid, blk, 0, st, dets, n, sbits, offs, cnt, skeys);
+    } else {
+        if (packed)
+            hipLaunchKernelGGL(k_s_sub_count<true>, grid, blk, 0, st, dets, n, sbits, cnt);
+        else
+            hipLaunchKernelGGL(k_s_sub_count<false>, grid, blk, 0, st, dets, n, sbits, cnt);
+    }
+}
+
+// ------------------------------------------------------------------ reduce kernel
+// Insert (a, b) into the LDS table; returns the slot or -1 when the table is full.
+template <bool PACKED>
+__device__ __forceinline__ int red_insert(unsigned long long *ka_t, unsigned long long *kb_t, uint64_t a, uint64_t b) {
+    uint32_t s = (uint32_t)target_hash<PACKED>(a, b) & (kRedTab - 1);
+    for (int p = 0; p < kRedTab; ++p) {
+        if (PACKED) {
+            const unsigned long long k = pack_key(a, b);
+            const unsigned long long prev = atomicCAS(&ka_t[s], (unsigned long long)kEmptyKey, k);
+            if (prev == kEmptyKey || prev == k) return (int)s;
+        } else {
+            const unsigned long long pa = atomicCAS(&ka_t[s], (unsigned long long)kEmptyKey, (unsigned long long)a);
+            if (pa == kEmptyKey || pa == a) {
+                const unsigned long long pb =
+                    atomicCAS(&kb_t[s], (unsigned long long)kEmptyKey, (unsigned long long)b);
+                if (pb == kEmptyKey || pb == b) return (int)s;
+            }
+        }
+        s = (s + 1) & (kRedTab - 1);
+    }
+    return -1;
+}
+
+template <bool PACKED>
+__global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_t *__restrict__ dets,
+                                                            const double *__restrict__ psi,
+                                                            const uint64_t *__restrict__ desc,
+                                                            const int64_t *__restrict__ sb,
+                                                            const uint64_t *__restrict__ skeys,
+                                                            const int64_t *__restrict__ soffs, int64_t n_s,
+                                                            int64_t nsb, const double *__restrict__ vt,
+                                                            const double *__restrict__ energy, uint64_t sample_mask,
+                                                            PT2Export ex, double *__restrict__ part,
+                                                            int *__restrict__ overflow) {
+    __shared__ unsigned long long ka_t[kRedTab];
+    __shared__ unsigned long long kb_t[PACKED ? 1 : kRedTab];
+    __shared__ double w_t[kRedTab];
+    __shared__ uint32_t in_s[kRedTab / 32];
+    extern __shared__ double vt_s[];  // diagonal table (PACKED), sized at launch
+    for (int t = threadIdx.x; t < kRedTab; t += blockDim.x) {
+        ka_t[t] = kEmptyKey;
+        if (!PACKED) kb_t[t] = kEmptyKey;
+        w_t[t] = 0.0;
+    }
+    for (int t = threadIdx.x; t < kRedTab / 32; t += blockDim.x) in_s[t] = 0u;
+    const int No = 2 * H.M;
+    if (PACKED)
+        for (int t = threadIdx.x; t < No + No * (No - 1) / 2; t += blockDim.x) vt_s[t] = vt[t];
+    __syncthreads();
+    bool lost = false;
+    // members of S that hash into this sub-bucket: in the table, marked
+    const int64_t q0 = soffs[blockIdx.x], q1 = blockIdx.x + 1 < nsb ? soffs[blockIdx.x + 1] : n_s;
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+        const int s = red_insert<PACKED>(ka_t, kb_t, skeys[2 * q], skeys[2 * q + 1]);
+        if (s < 0)
+            lost = true;
+        else
+            atomicOr(&in_s[s >> 5], 1u << (s & 31));
+    }
+    __syncthreads();
+    const int64_t s0 = sb[blockIdx.x], s1 = sb[blockIdx.x + 1];
+    for (int64_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
+        const uint64_t d = desc[i];
+        const int64_t x = desc_x(d);
+        const uint64_t xa = dets[2 * x], xb = dets[2 * x + 1];
+        uint64_t a = xa, b = xb;
+        apply_positions(desc_pos(d), a, b);
+        const double v = h_offdiag(H, EriPacked{H.eri_pk}, a, b, xa, xb) * psi[x];
+        const int s = red_insert<PACKED>(ka_t, kb_t, a, b);
+        if (s < 0)
+            lost = true;
+        else
+            atomicAdd(&w_t[s], v);
+    }
+    if (lost) atomicOr(overflow, 1);
+    __syncthreads();
+    const double E = energy[0];
+    double sum = 0.0, mn = INFINITY, np = 0.0, nt = 0.0;
+    for (int t = threadIdx.x; t < kRedTab; t += blockDim.x) {
+        uint64_t a, b;
+        if (PACKED) {
+            const unsigned long long k = ka_t[t];
+            if (k == kEmptyKey) continue;
+            a = k & 0xffffffffull;
+            b = k >> 32;
+        } else {
+            if (kb_t[t] == kEmptyKey) continue;
+            a = ka_t[t];
+            b = kb_t[t];
+        }
+        if ((in_s[t >> 5] >> (t & 31)) & 1u) continue;
+        if (sample_mask && (key_hash(a, b) & sample_mask)) continue;
+        const double w = w_t[t];
+        double haa;
+        if (PACKED) {
+            const uint64_t occ = a | (b << H.M);
+            haa = H.ecore;
+            uint64_t rest = occ;
+            while (rest) {
+                const int qo = ctz64(rest);
+                rest &= rest - 1;
+                double e = vt_s[qo];
+                const double *row = vt_s + No + qo * (qo - 1) / 2;
+                uint64_t below = occ & ((1ull << qo) - 1ull);
+                while (below) {
+                    e += row[ctz64(below)];
+                    below &= below - 1;
+                }
+                haa += e;
+            }
+        } else {
+            haa = h_diag(H, a, b);
+        }
+        const double den = E - haa;
+        np += 1.0;
+        mn = fmin(mn, fabs(den));
+        if (fabs(den) < 1e-8) nt += 1.0;
+        if (w != 0.0) sum += w * w / den;
+        if (ex.cap > 0) {
+            const unsigned long long k = atomicAdd((unsigned long long *)ex.count, 1ull);
+            if ((int64_t)k < ex.cap) {
+                ex.keys[2 * k] = a;
+                ex.keys[2 * k + 1] = b;
+                ex.w[k] = w;
+                ex.haa[k] = haa;
+            }
+        }
+    }
+    red_block(sum, mn, np, nt);
+    if (threadIdx.x == 0) {
+        part[4 * blockIdx.x + 0] = sum;
+        part[4 * blockIdx.x + 1] = mn;
+        part[4 * blockIdx.x + 2] = np;
+        part[4 * blockIdx.x + 3] = nt;
+    }
+}
+
+void launch_pt2_reduce(hipStream_t st, const Ham &H, const uint64_t *dets, const double *psi, const uint64_t *desc,
+                       const int64_t *sb, int64_t nsb, const uint64_t *skeys, const int64_t *soffs, int64_t n_s,
+                       const double *vt, const double *energy, uint64_t sample_mask, const PT2Export &ex, double *part,
+                       int *overflow, bool packed) {
+    dim3 grid((unsigned)nsb), blk(kRedThreads);
+    if (packed)
+        hipLaunchKernelGGL(k_pt2_reduce<true>, grid, blk, sizeof(double) * pt2_diag_table_size(H.M), st, H, dets, psi, desc, sb, skeys, soffs, n_s, nsb, vt,
+                           energy, sample_mask, ex, part, overflow);
+    else
+        hipLaunchKernelGGL(k_pt2_reduce<false>, grid, blk, 0, st, H, dets, psi, desc, sb, skeys, soffs, n_s, nsb, vt,
+                           energy, sample_mask, ex, part, overflow);
+}
+
+int pt2_red_tab() { return kRedTab; }
+
+}  // namespace dnqs
