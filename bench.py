@@ -271,7 +271,9 @@ def main():
     # descriptor per (x, a) pair (its gathers of dets, psi and integrals hit L2);
     # duration = its average HIP-event time on the library stream.
     t_red = avg["pt2_reduce"]
-    red_bytes = 8.0 * pairs
+    # reduce launches per pt2 call (more than one when the key space is sliced)
+    red_per_call = fam["pt2_reduce"][1] / max(fam["pt2"][1], 1)
+    red_bytes = 8.0 * pairs / max(red_per_call, 1.0)
     achieved = red_bytes / (t_red * 1e-3) / 1e9
     traffic = measured_traffic("k_pt2_reduce", wl.name)
     # the whole PT2 phase against the 40 B/pair group-by model (write + read of a

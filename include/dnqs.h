@@ -168,7 +168,13 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
  * opts->export_cap > 0 up to export_cap kept keys are written to export_keys
  * (dev uint64[cap][2]) with export_w (w_a, for psi scaled so that max_x |psi_x| = 1)
  * and export_haa (H_aa) (dev FP64[cap]), and the number of kept keys to export_count
- * (dev int64[1]; may exceed export_cap).  Synchronises the stream. */
+ * (dev int64[1]; may exceed export_cap).
+ * Memory: the external sum materialises an 8-byte descriptor per (x, a) pair twice.
+ * When 16 bytes x pairs exceed opts->max_pair_bytes (0: half of the free device memory
+ * at the call), the key space is cut into 2^k slices by the top k bits of the key hash
+ * and processed one slice after the other (S re-enumerated for each), so that any |S|
+ * fits; the result does not depend on the slicing beyond FP64 summation order.
+ * counts[3] then sums the sub-buckets over slices.  Synchronises the stream. */
 typedef struct {
     uint64_t sample_mask;
     int64_t export_cap;
@@ -176,6 +182,7 @@ typedef struct {
     double *export_w;
     double *export_haa;
     int64_t *export_count;
+    int64_t max_pair_bytes;
 } dnqs_pt2_opts;
 dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const double *log_abs, const int8_t *sign,
                      const double *energy, const dnqs_pt2_opts *opts, double *out, int64_t *counts);

@@ -55,7 +55,8 @@ class AdamwCfg(C.Structure):
 
 class PT2Opts(C.Structure):
     _fields_ = [("sample_mask", C.c_uint64), ("export_cap", C.c_int64), ("export_keys", C.c_void_p),
-                ("export_w", C.c_void_p), ("export_haa", C.c_void_p), ("export_count", C.c_void_p)]
+                ("export_w", C.c_void_p), ("export_haa", C.c_void_p), ("export_count", C.c_void_p),
+                ("max_pair_bytes", C.c_int64)]
 
 
 _lib = None
@@ -254,7 +255,7 @@ class Context:
                                                _ptr(sg)))
         return {"E": E, "stats": stats, "grad": grad, "v": v, "logabs": la, "sign": sg}
 
-    def pt2(self, conn: Connections, logabs, sign, energy, sample_mask=0, export_cap=0):
+    def pt2(self, conn: Connections, logabs, sign, energy, sample_mask=0, export_cap=0, max_pair_bytes=0):
         dev = energy.device
         logabs = _dev_tensor(logabs, torch.float64, "logabs", self.device)
         sign = _dev_tensor(sign, torch.int8, "sign", self.device)
@@ -263,6 +264,7 @@ class Context:
         counts = torch.empty(4, dtype=torch.int64, device=dev)
         opts = PT2Opts()
         opts.sample_mask = int(sample_mask)
+        opts.max_pair_bytes = int(max_pair_bytes)
         ex = None
         if export_cap > 0:
             ex = {"keys": torch.empty((export_cap, 2), dtype=torch.int64, device=dev),

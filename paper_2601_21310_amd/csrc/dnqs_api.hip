@@ -848,8 +848,8 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
     launch_scale_psi(st, log_abs, sign, n, part, stats + 1, psi);
     launch_spmv_energy(st, conn->row_ptr, conn->col, conn->val, conn->diag, psi, n, v, part, part2, stats, e_tmp);
     CHECK_LAUNCH(ctx);
-    double *acc = nullptr;
-    TRY(ws_t(ctx, "pt2_acc", 8, &acc));
+    double *acc = nullptr;  // [internal | external total | current slice attempt]
+    TRY(ws_t(ctx, "pt2_acc", 12, &acc));
     launch_pt2_internal(st, psi, v, conn->diag, n, energy, part, acc);
     launch_pt2_init_acc(st, acc + 4);
     CHECK_LAUNCH(ctx);
@@ -866,13 +866,28 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
     TRY(ws_t(ctx, "pt2_vt", (size_t)pt2_diag_table_size(sl.M), &vt));
     launch_diag_table(st, H, vt);
     CHECK_LAUNCH(ctx);
-    // external sum: partitioned reduce-by-key (k_pt2_part.hip)
+    // external sum: partitioned reduce-by-key (k_pt2_part.hip, k_pt2_reduce.hip)
     const int64_t nexc = n_excitations(sl.M, sl.na, sl.nb);
     const int64_t pairs = n * nexc;
     const bool packed = sl.M <= 32 && !(sl.M == 32 && sl.na == 32 && sl.nb == 32);
+    // key-space slices: 8-byte descriptors are held twice (L1 and L2 order)
+    int64_t budget = o.max_pair_bytes;
+    if (budget <= 0) {
+        size_t fr = 0, tot_mem = 0;
+        HIPCHK(ctx, hipMemGetInfo(&fr, &tot_mem));
+        int64_t held = 0;  // descriptor buffers of an earlier call are reused
+        for (const char *nm : {"pt2_desc1", "pt2_desc2"}) {
+            auto it = ctx->ws.find(nm);
+            if (it != ctx->ws.end()) held += (int64_t)it->second.bytes;
+        }
+        budget = (int64_t)(fr / 2) + held;
+    }
+    int ss = 0;
+    while (ss < 16 && (double)(pairs >> ss) * 16.0 > (double)budget) ++ss;
+    const int64_t slice_pairs = std::max<int64_t>(1, pairs >> ss);
     // sub-buckets of ~6000 pairs: ~2k unique keys at the measured 3.4 pairs per key,
     // half of the 4096-slot LDS table
-    const int64_t nsb_target = std::max<int64_t>(1, pairs / 6000);
+    const int64_t nsb_target = std::max<int64_t>(1, slice_pairs / 6000);
     int s1 = 0;
     // K1 <= 512: an L1 round of 8192 descriptors then holds ~16 per bucket (one 128-byte
     // line per run), and 2^19 sub-buckets leave K2 <= 1024 for the staged L2 pass
@@ -883,127 +898,142 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
     const int64_t nwg = pt2_l1_groups(n);
     uint32_t *c1 = nullptr;
     int32_t *c1t = nullptr;
-    int64_t *offs1 = nullptr, *bsum = nullptr, *tot = nullptr, *bstart_d = nullptr;
+    int64_t *offs1 = nullptr, *bsum = nullptr, *tot = nullptr, *bstart_d = nullptr, *ex_save = nullptr;
     TRY(ws_t(ctx, "pt2_c1", (size_t)nwg * K1, &c1));
     TRY(ws_t(ctx, "pt2_c1t", (size_t)nwg * K1, &c1t));
     TRY(ws_t(ctx, "pt2_offs1", (size_t)nwg * K1, &offs1));
     TRY(ws_t(ctx, "pt2_bsum", (size_t)scan_blocks(nwg * K1) + 1, &bsum));
     TRY(ws_t(ctx, "pt2_tot", 2, &tot));
     TRY(ws_t(ctx, "pt2_bstart", (size_t)K1 + 1, &bstart_d));
-    Timer t1(ctx, "pt2_l1");
-    launch_pt2_l1(st, H, conn->dets, n, psi, s1, nwg, c1, nullptr, nullptr, false, packed);
-    CHECK_LAUNCH(ctx);
-    launch_transpose_u32(st, c1, nwg, K1, c1t);
-    launch_exclusive_scan(st, c1t, nwg * K1, offs1, bsum, tot);
-    CHECK_LAUNCH(ctx);
-    int64_t total1 = 0;
-    HIPCHK(ctx, hipMemcpyAsync(&total1, tot, sizeof total1, hipMemcpyDeviceToHost, st));
-    HIPCHK(ctx, hipStreamSynchronize(st));
-    uint64_t *desc1 = nullptr;
-    TRY(ws_t(ctx, "pt2_desc1", (size_t)std::max<int64_t>(total1, 1), &desc1));
-    Timer t1f(ctx, "pt2_l1_fill");
-    launch_pt2_l1(st, H, conn->dets, n, psi, s1, nwg, nullptr, offs1, desc1, true, packed);
-    CHECK_LAUNCH(ctx);
-    t1f.stop();
-    t1.stop();
-    launch_gather_starts(st, offs1, K1, nwg, tot, bstart_d);
-    CHECK_LAUNCH(ctx);
-    std::vector<int64_t> bstart(K1 + 1);
-    HIPCHK(ctx, hipMemcpyAsync(bstart.data(), bstart_d, sizeof(int64_t) * (K1 + 1), hipMemcpyDeviceToHost, st));
-    HIPCHK(ctx, hipStreamSynchronize(st));
+    TRY(ws_t(ctx, "pt2_exsave", 1, &ex_save));
+    if (o.export_cap > 0) HIPCHK(ctx, hipMemsetAsync(o.export_count, 0, sizeof(int64_t), st));
     int64_t nsb_used = 0;
-    for (int attempt = 0;; ++attempt) {
-        const int K2 = 1 << s2;
-        const uint64_t *desc = desc1;
-        const int64_t *sb = bstart_d;
-        int64_t nsb = K1;
-        if (s2 > 0) {
-            const int64_t CH = 65536;
-            std::vector<PT2Chunk> chunks;
-            std::vector<int64_t> bcb0(K1), bnc(K1);
-            for (int b = 0; b < K1; ++b) {
-                const int64_t size = bstart[b + 1] - bstart[b];
-                const int64_t nc = (size + CH - 1) / CH;
-                bcb0[b] = (int64_t)chunks.size();
-                bnc[b] = nc;
-                for (int64_t c = 0; c < nc; ++c)
-                    chunks.push_back({bstart[b] + c * CH, std::min(CH, size - c * CH), bcb0[b], nc});
-            }
-            const int64_t nchunk = (int64_t)chunks.size();
-            PT2Chunk *chunks_d = nullptr;
-            int64_t *bcb0_d = nullptr, *bnc_d = nullptr, *offs2 = nullptr, *bsum2 = nullptr, *sb_d = nullptr;
-            uint32_t *c2 = nullptr;
-            int32_t *c2t = nullptr;
-            uint64_t *desc2 = nullptr;
-            TRY(ws_t(ctx, "pt2_chunks", (size_t)std::max<int64_t>(nchunk, 1), &chunks_d));
-            TRY(ws_t(ctx, "pt2_bcb0", (size_t)K1, &bcb0_d));
-            TRY(ws_t(ctx, "pt2_bnc", (size_t)K1, &bnc_d));
-            TRY(ws_t(ctx, "pt2_c2", (size_t)std::max<int64_t>(nchunk * K2, 1), &c2));
-            TRY(ws_t(ctx, "pt2_c2t", (size_t)std::max<int64_t>(nchunk * K2, 1), &c2t));
-            TRY(ws_t(ctx, "pt2_offs2", (size_t)std::max<int64_t>(nchunk * K2, 1), &offs2));
-            TRY(ws_t(ctx, "pt2_bsum2", (size_t)scan_blocks(nchunk * K2) + 1, &bsum2));
-            TRY(ws_t(ctx, "pt2_sb", (size_t)K1 * K2 + 1, &sb_d));
-            TRY(ws_t(ctx, "pt2_desc2", (size_t)std::max<int64_t>(total1, 1), &desc2));
-            if (nchunk > 0)
-                HIPCHK(ctx, hipMemcpyAsync(chunks_d, chunks.data(), sizeof(PT2Chunk) * nchunk, hipMemcpyHostToDevice, st));
-            HIPCHK(ctx, hipMemcpyAsync(bcb0_d, bcb0.data(), sizeof(int64_t) * K1, hipMemcpyHostToDevice, st));
-            HIPCHK(ctx, hipMemcpyAsync(bnc_d, bnc.data(), sizeof(int64_t) * K1, hipMemcpyHostToDevice, st));
-            Timer t2(ctx, "pt2_l2");
-            if (nchunk > 0) {
-                launch_pt2_l2(st, desc1, chunks_d, nchunk, s2, c2, nullptr, nullptr, false);
-                CHECK_LAUNCH(ctx);
-                launch_l2_transpose(st, c2, chunks_d, nchunk, K2, c2t);
-                launch_exclusive_scan(st, c2t, nchunk * K2, offs2, bsum2, tot + 1);
-                CHECK_LAUNCH(ctx);
-                launch_pt2_l2(st, desc1, chunks_d, nchunk, s2, nullptr, offs2, desc2, true);
-                CHECK_LAUNCH(ctx);
-            }
-            launch_sub_starts(st, offs2, bstart_d, bcb0_d, bnc_d, K1, K2, sb_d);
-            CHECK_LAUNCH(ctx);
-            t2.stop();
-            // the host vectors are read by the copies above: wait before they go out of scope
-            HIPCHK(ctx, hipStreamSynchronize(st));
-            desc = desc2;
-            sb = sb_d;
-            nsb = (int64_t)K1 * K2;
-        }
-        // S grouped by sub-bucket (same hash bits as the pairs)
-        int32_t *scnt = nullptr;
-        int64_t *soffs = nullptr, *sbsum = nullptr;
-        uint64_t *skeys = nullptr;
-        TRY(ws_t(ctx, "pt2_scnt", (size_t)nsb, &scnt));
-        TRY(ws_t(ctx, "pt2_soffs", (size_t)nsb, &soffs));
-        TRY(ws_t(ctx, "pt2_sbsum", (size_t)scan_blocks(nsb) + 1, &sbsum));
-        TRY(ws_t(ctx, "pt2_skeys", (size_t)2 * std::max<int64_t>(n, 1), &skeys));
-        const int sbits = s1 + (s2 > 0 ? s2 : 0);
-        HIPCHK(ctx, hipMemsetAsync(scnt, 0, sizeof(int32_t) * nsb, st));
-        launch_s_sub(st, conn->dets, n, sbits, packed, scnt, nullptr, nullptr, false);
+    for (uint32_t slice = 0; slice < (1u << ss); ++slice) {
+        Timer t1(ctx, "pt2_l1");
+        launch_pt2_l1(st, H, conn->dets, n, psi, s1, nwg, c1, nullptr, nullptr, false, packed, ss, slice);
         CHECK_LAUNCH(ctx);
-        launch_exclusive_scan(st, scnt, nsb, soffs, sbsum, tot + 1);
+        launch_transpose_u32(st, c1, nwg, K1, c1t);
+        launch_exclusive_scan(st, c1t, nwg * K1, offs1, bsum, tot);
         CHECK_LAUNCH(ctx);
-        HIPCHK(ctx, hipMemsetAsync(scnt, 0, sizeof(int32_t) * nsb, st));
-        launch_s_sub(st, conn->dets, n, sbits, packed, scnt, soffs, skeys, true);
-        CHECK_LAUNCH(ctx);
-        double *part_r = nullptr;
-        TRY(ws_t(ctx, "pt2_part_r", (size_t)nsb * 4, &part_r));
-        launch_pt2_init_acc(st, acc + 4);
-        if (o.export_cap > 0) HIPCHK(ctx, hipMemsetAsync(o.export_count, 0, sizeof(int64_t), st));
-        HIPCHK(ctx, hipMemsetAsync(overflow, 0, sizeof(int), st));
-        Timer tr(ctx, "pt2_reduce");
-        launch_pt2_reduce(st, H, conn->dets, psi, desc, sb, nsb, skeys, soffs, n, vt, energy, o.sample_mask, ex,
-                          part_r, overflow, packed);
-        CHECK_LAUNCH(ctx);
-        tr.stop();
-        launch_pt2_accumulate(st, part_r, nsb, acc + 4);
-        CHECK_LAUNCH(ctx);
-        int ov = 0;
-        HIPCHK(ctx, hipMemcpyAsync(&ov, overflow, sizeof ov, hipMemcpyDeviceToHost, st));
+        int64_t total1 = 0;
+        HIPCHK(ctx, hipMemcpyAsync(&total1, tot, sizeof total1, hipMemcpyDeviceToHost, st));
         HIPCHK(ctx, hipStreamSynchronize(st));
-        nsb_used = nsb;
-        if (!ov) break;
-        if ((1 << s2) >= pt2_max_k2() || attempt > 8)
-            return fail(ctx, DNQS_ECAPACITY, "PT2: a sub-bucket holds more than %d unique keys", pt2_red_tab());
-        ++s2;
+        uint64_t *desc1 = nullptr;
+        TRY(ws_t(ctx, "pt2_desc1", (size_t)std::max<int64_t>(total1, 1), &desc1));
+        Timer t1f(ctx, "pt2_l1_fill");
+        launch_pt2_l1(st, H, conn->dets, n, psi, s1, nwg, nullptr, offs1, desc1, true, packed, ss, slice);
+        CHECK_LAUNCH(ctx);
+        t1f.stop();
+        t1.stop();
+        launch_gather_starts(st, offs1, K1, nwg, tot, bstart_d);
+        CHECK_LAUNCH(ctx);
+        std::vector<int64_t> bstart(K1 + 1);
+        HIPCHK(ctx, hipMemcpyAsync(bstart.data(), bstart_d, sizeof(int64_t) * (K1 + 1), hipMemcpyDeviceToHost, st));
+        if (o.export_cap > 0)
+            HIPCHK(ctx, hipMemcpyAsync(ex_save, o.export_count, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));
+        for (int attempt = 0;; ++attempt) {
+            const int K2 = 1 << s2;
+            const uint64_t *desc = desc1;
+            const int64_t *sb = bstart_d;
+            int64_t nsb = K1;
+            if (s2 > 0) {
+                const int64_t CH = 65536;
+                std::vector<PT2Chunk> chunks;
+                std::vector<int64_t> bcb0(K1), bnc(K1);
+                for (int b = 0; b < K1; ++b) {
+                    const int64_t size = bstart[b + 1] - bstart[b];
+                    const int64_t nc = (size + CH - 1) / CH;
+                    bcb0[b] = (int64_t)chunks.size();
+                    bnc[b] = nc;
+                    for (int64_t c = 0; c < nc; ++c)
+                        chunks.push_back({bstart[b] + c * CH, std::min(CH, size - c * CH), bcb0[b], nc});
+                }
+                const int64_t nchunk = (int64_t)chunks.size();
+                PT2Chunk *chunks_d = nullptr;
+                int64_t *bcb0_d = nullptr, *bnc_d = nullptr, *offs2 = nullptr, *bsum2 = nullptr, *sb_d = nullptr;
+                uint32_t *c2 = nullptr;
+                int32_t *c2t = nullptr;
+                uint64_t *desc2 = nullptr;
+                TRY(ws_t(ctx, "pt2_chunks", (size_t)std::max<int64_t>(nchunk, 1), &chunks_d));
+                TRY(ws_t(ctx, "pt2_bcb0", (size_t)K1, &bcb0_d));
+                TRY(ws_t(ctx, "pt2_bnc", (size_t)K1, &bnc_d));
+                TRY(ws_t(ctx, "pt2_c2", (size_t)std::max<int64_t>(nchunk * K2, 1), &c2));
+                TRY(ws_t(ctx, "pt2_c2t", (size_t)std::max<int64_t>(nchunk * K2, 1), &c2t));
+                TRY(ws_t(ctx, "pt2_offs2", (size_t)std::max<int64_t>(nchunk * K2, 1), &offs2));
+                TRY(ws_t(ctx, "pt2_bsum2", (size_t)scan_blocks(nchunk * K2) + 1, &bsum2));
+                TRY(ws_t(ctx, "pt2_sb", (size_t)K1 * K2 + 1, &sb_d));
+                TRY(ws_t(ctx, "pt2_desc2", (size_t)std::max<int64_t>(total1, 1), &desc2));
+                if (nchunk > 0)
+                    HIPCHK(ctx, hipMemcpyAsync(chunks_d, chunks.data(), sizeof(PT2Chunk) * nchunk,
+                                               hipMemcpyHostToDevice, st));
+                HIPCHK(ctx, hipMemcpyAsync(bcb0_d, bcb0.data(), sizeof(int64_t) * K1, hipMemcpyHostToDevice, st));
+                HIPCHK(ctx, hipMemcpyAsync(bnc_d, bnc.data(), sizeof(int64_t) * K1, hipMemcpyHostToDevice, st));
+                Timer t2(ctx, "pt2_l2");
+                if (nchunk > 0) {
+                    launch_pt2_l2(st, desc1, chunks_d, nchunk, s2, c2, nullptr, nullptr, false);
+                    CHECK_LAUNCH(ctx);
+                    launch_l2_transpose(st, c2, chunks_d, nchunk, K2, c2t);
+                    launch_exclusive_scan(st, c2t, nchunk * K2, offs2, bsum2, tot + 1);
+                    CHECK_LAUNCH(ctx);
+                    launch_pt2_l2(st, desc1, chunks_d, nchunk, s2, nullptr, offs2, desc2, true);
+                    CHECK_LAUNCH(ctx);
+                }
+                launch_sub_starts(st, offs2, bstart_d, bcb0_d, bnc_d, K1, K2, sb_d);
+                CHECK_LAUNCH(ctx);
+                t2.stop();
+                // the host vectors are read by the copies above: wait before they go out of scope
+                HIPCHK(ctx, hipStreamSynchronize(st));
+                desc = desc2;
+                sb = sb_d;
+                nsb = (int64_t)K1 * K2;
+            }
+            // the members of S in this slice, grouped by sub-bucket (same hash bits as the pairs)
+            int32_t *scnt = nullptr;
+            int64_t *soffs = nullptr, *sbsum = nullptr;
+            uint64_t *skeys = nullptr;
+            TRY(ws_t(ctx, "pt2_scnt", (size_t)nsb, &scnt));
+            TRY(ws_t(ctx, "pt2_soffs", (size_t)nsb, &soffs));
+            TRY(ws_t(ctx, "pt2_sbsum", (size_t)scan_blocks(nsb) + 1, &sbsum));
+            TRY(ws_t(ctx, "pt2_skeys", (size_t)2 * std::max<int64_t>(n, 1), &skeys));
+            const int sbits = s1 + (s2 > 0 ? s2 : 0);
+            HIPCHK(ctx, hipMemsetAsync(scnt, 0, sizeof(int32_t) * nsb, st));
+            launch_s_sub(st, conn->dets, n, sbits, packed, scnt, nullptr, nullptr, false, ss, slice);
+            CHECK_LAUNCH(ctx);
+            launch_exclusive_scan(st, scnt, nsb, soffs, sbsum, tot + 1);
+            CHECK_LAUNCH(ctx);
+            int64_t n_s = 0;  // members of S in this slice
+            HIPCHK(ctx, hipMemcpyAsync(&n_s, tot + 1, sizeof n_s, hipMemcpyDeviceToHost, st));
+            HIPCHK(ctx, hipMemsetAsync(scnt, 0, sizeof(int32_t) * nsb, st));
+            launch_s_sub(st, conn->dets, n, sbits, packed, scnt, soffs, skeys, true, ss, slice);
+            CHECK_LAUNCH(ctx);
+            HIPCHK(ctx, hipStreamSynchronize(st));
+            double *part_r = nullptr;
+            TRY(ws_t(ctx, "pt2_part_r", (size_t)nsb * 4, &part_r));
+            launch_pt2_init_acc(st, acc + 8);
+            if (o.export_cap > 0)
+                HIPCHK(ctx, hipMemcpyAsync(o.export_count, ex_save, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+            HIPCHK(ctx, hipMemsetAsync(overflow, 0, sizeof(int), st));
+            Timer tr(ctx, "pt2_reduce");
+            launch_pt2_reduce(st, H, conn->dets, psi, desc, sb, nsb, skeys, soffs, n_s, vt, energy, o.sample_mask,
+                              ex, part_r, overflow, packed);
+            CHECK_LAUNCH(ctx);
+            tr.stop();
+            launch_pt2_accumulate(st, part_r, nsb, acc + 8);
+            CHECK_LAUNCH(ctx);
+            int ov = 0;
+            HIPCHK(ctx, hipMemcpyAsync(&ov, overflow, sizeof ov, hipMemcpyDeviceToHost, st));
+            HIPCHK(ctx, hipStreamSynchronize(st));
+            if (!ov) {
+                launch_pt2_merge(st, acc + 4, acc + 8);
+                CHECK_LAUNCH(ctx);
+                nsb_used += nsb;
+                break;
+            }
+            if ((1 << s2) >= pt2_max_k2() || attempt > 8)
+                return fail(ctx, DNQS_ECAPACITY, "PT2: a sub-bucket holds more than %d unique keys", pt2_red_tab());
+            ++s2;
+        }
     }
     launch_pt2_final(st, acc, acc + 4, stats, out, counts, pairs, nsb_used);
     CHECK_LAUNCH(ctx);

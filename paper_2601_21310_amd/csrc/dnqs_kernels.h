@@ -150,8 +150,10 @@ int64_t pt2_l1_groups(int64_t n);
 int pt2_red_tab();
 int pt2_max_k1();
 int pt2_max_k2();
+// ss > 0: key-space slice `slice` of 2^ss (targets with those top hash bits only)
 void launch_pt2_l1(hipStream_t st, const Ham &H, const uint64_t *dets, int64_t n, const double *psi, int s1,
-                   int64_t nwg, uint32_t *counts, const int64_t *offs, uint64_t *desc, bool fill, bool packed);
+                   int64_t nwg, uint32_t *counts, const int64_t *offs, uint64_t *desc, bool fill, bool packed, int ss,
+                   uint32_t slice);
 void launch_transpose_u32(hipStream_t st, const uint32_t *in, int64_t R, int64_t C, int32_t *out);
 void launch_gather_starts(hipStream_t st, const int64_t *offs, int K, int64_t stride, const int64_t *total,
                           int64_t *starts);
@@ -164,10 +166,11 @@ void launch_sub_starts(hipStream_t st, const int64_t *offs2, const int64_t *bsta
                        const int64_t *bnc, int K1, int K2, int64_t *sb);
 int pt2_diag_table_size(int M);
 void launch_diag_table(hipStream_t st, const Ham &H, double *vt);
-// S grouped by the reduce sub-bucket of its keys (top sbits of the key hash): count into
-// cnt (fill == false), or place into skeys at offs[sub] + cursor (cnt used as cursors)
+// The members of S in key-space slice `slice` grouped by the reduce sub-bucket of their
+// keys (sbits hash bits after the ss slice bits): count into cnt (fill == false), or
+// place into skeys at offs[sub] + cursor (cnt used as cursors)
 void launch_s_sub(hipStream_t st, const uint64_t *dets, int64_t n, int sbits, bool packed, int32_t *cnt,
-                  const int64_t *offs, uint64_t *skeys, bool fill);
+                  const int64_t *offs, uint64_t *skeys, bool fill, int ss, uint32_t slice);
 void launch_pt2_reduce(hipStream_t st, const Ham &H, const uint64_t *dets, const double *psi, const uint64_t *desc,
                        const int64_t *sb, int64_t nsb, const uint64_t *skeys, const int64_t *soffs, int64_t n_s,
                        const double *vt, const double *energy, uint64_t sample_mask, const PT2Export &ex, double *part,
@@ -176,6 +179,8 @@ void launch_pt2_accumulate(hipStream_t st, const double *part, int64_t nb, doubl
 void launch_pt2_internal(hipStream_t st, const double *psi, const double *v, const double *diag, int64_t n,
                          const double *energy, double *part, double *acc_int);
 void launch_pt2_init_acc(hipStream_t st, double *acc);
+// acc += part (sum, min, counts): a finished key-space slice into the external total
+void launch_pt2_merge(hipStream_t st, double *acc, const double *part);
 void launch_pt2_final(hipStream_t st, const double *acc_int, const double *acc_ext, const double *stats,
                       double *out, int64_t *counts, int64_t pairs, int64_t passes);
 

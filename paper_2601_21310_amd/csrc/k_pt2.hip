@@ -110,6 +110,17 @@ void launch_pt2_init_acc(hipStream_t st, double *acc) {
     hipLaunchKernelGGL(k_pt2_init_acc, dim3(1), dim3(1), 0, st, acc);
 }
 
+__global__ void k_pt2_merge(double *acc, const double *part) {
+    acc[0] += part[0];
+    acc[1] = fmin(acc[1], part[1]);
+    acc[2] += part[2];
+    acc[3] += part[3];
+}
+
+void launch_pt2_merge(hipStream_t st, double *acc, const double *part) {
+    hipLaunchKernelGGL(k_pt2_merge, dim3(1), dim3(1), 0, st, acc, part);
+}
+
 // out = {(int + ext)/norm, int, ext, min den}; counts[1] = |P|, counts[2] = tiny
 __global__ void k_pt2_final(const double *__restrict__ acc_int, const double *__restrict__ acc_ext,
                             const double *__restrict__ stats, double *__restrict__ out, int64_t *__restrict__ counts,

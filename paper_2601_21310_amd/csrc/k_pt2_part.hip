@@ -75,11 +75,13 @@ __device__ inline void block_exclusive_scan(const uint32_t *cnt, uint32_t *out, 
 // and written out so that consecutive lanes write consecutive descriptors of one
 // bucket's run: whole lines instead of one 8-byte write per open run.  Pairs of dead
 // determinants (psi = 0) go to bucket K1, which is never written.
+// Key-space slice (ss > 0): only targets whose top ss hash bits equal `slice` are kept,
+// and the bucket bits are taken from the hash shifted past the slice bits.
 template <bool FILL, bool PACKED>
 __global__ __launch_bounds__(kL1Threads) void k_pt2_l1(Ham H, const uint64_t *__restrict__ dets, int64_t n,
                                                        const double *__restrict__ psi, int s1, int64_t nwg,
                                                        uint32_t *__restrict__ counts, const int64_t *__restrict__ offs,
-                                                       uint64_t *__restrict__ desc) {
+                                                       uint64_t *__restrict__ desc, int ss, uint32_t slice) {
     __shared__ uint8_t lists[kL1XPerGroup][4][64];
     __shared__ uint64_t xs[kL1XPerGroup][2];
     __shared__ uint32_t live_s[kL1XPerGroup];
@@ -135,9 +137,13 @@ __global__ __launch_bounds__(kL1Threads) void k_pt2_l1(Ham H, const uint64_t *__
                 const uint32_t pos = excitation_positions(c, e);
                 uint64_t ka = xs[xl][0], kb = xs[xl][1];
                 apply_positions(pos, ka, kb);
-                const uint64_t h = target_hash<PACKED>(ka, kb);
-                bk[j] = l1_bucket(h, s1);
-                d[j] = make_desc(wg * kL1XPerGroup + xl, pos, h, s1);
+                uint64_t h = target_hash<PACKED>(ka, kb);
+                const bool in_slice = ss == 0 || (uint32_t)(h >> (64 - ss)) == slice;
+                if (ss) h <<= ss;
+                if (in_slice) {
+                    bk[j] = l1_bucket(h, s1);
+                    d[j] = make_desc(wg * kL1XPerGroup + xl, pos, h, s1);
+                }
             }
             rk[j] = atomicAdd(&hist[bk[j]], 1u);
             q += blockDim.x;
@@ -177,19 +183,23 @@ __global__ __launch_bounds__(kL1Threads) void k_pt2_l1(Ham H, const uint64_t *__
 }
 
 void launch_pt2_l1(hipStream_t st, const Ham &H, const uint64_t *dets, int64_t n, const double *psi, int s1,
-                   int64_t nwg, uint32_t *counts, const int64_t *offs, uint64_t *desc, bool fill, bool packed) {
+                   int64_t nwg, uint32_t *counts, const int64_t *offs, uint64_t *desc, bool fill, bool packed, int ss,
+                   uint32_t slice) {
     dim3 grid((unsigned)nwg), blk(kL1Threads);
     if (fill) {
         if (packed)
-            hipLaunchKernelGGL((k_pt2_l1<true, true>), grid, blk, 0, st, H, dets, n, psi, s1, nwg, counts, offs, desc);
+            hipLaunchKernelGGL((k_pt2_l1<true, true>), grid, blk, 0, st, H, dets, n, psi, s1, nwg, counts, offs, desc,
+                               ss, slice);
         else
-            hipLaunchKernelGGL((k_pt2_l1<true, false>), grid, blk, 0, st, H, dets, n, psi, s1, nwg, counts, offs, desc);
+            hipLaunchKernelGGL((k_pt2_l1<true, false>), grid, blk, 0, st, H, dets, n, psi, s1, nwg, counts, offs, desc,
+                               ss, slice);
     } else {
         if (packed)
-            hipLaunchKernelGGL((k_pt2_l1<false, true>), grid, blk, 0, st, H, dets, n, psi, s1, nwg, counts, offs, desc);
+            hipLaunchKernelGGL((k_pt2_l1<false, true>), grid, blk, 0, st, H, dets, n, psi, s1, nwg, counts, offs,
+                               desc, ss, slice);
         else
             hipLaunchKernelGGL((k_pt2_l1<false, false>), grid, blk, 0, st, H, dets, n, psi, s1, nwg, counts, offs,
-                               desc);
+                               desc, ss, slice);
     }
 }
 

@@ -95,44 +95,54 @@ void launch_diag_table(hipStream_t st, const Ham &H, double *vt) {
 // The keys of S grouped by the sub-bucket their hash falls in (top sbits bits, the
 // concatenated L1 and L2 bucket indices), so that each reduce workgroup can mark the
 // members of S among its keys without probing the global hash set.
+// sub-bucket of a member of S in key-space slice `slice` (-1: another slice)
 template <bool PACKED>
-__device__ __forceinline__ int64_t s_sub(uint64_t a, uint64_t b, int sbits) {
-    return sbits ? (int64_t)(target_hash<PACKED>(a, b) >> (64 - sbits)) : 0;
+__device__ __forceinline__ int64_t s_sub(uint64_t a, uint64_t b, int sbits, int ss, uint32_t slice) {
+    uint64_t h = target_hash<PACKED>(a, b);
+    if (ss) {
+        if ((uint32_t)(h >> (64 - ss)) != slice) return -1;
+        h <<= ss;
+    }
+    return sbits ? (int64_t)(h >> (64 - sbits)) : 0;
 }
 
 template <bool PACKED>
-__global__ void k_s_sub_count(const uint64_t *__restrict__ dets, int64_t n, int sbits, int32_t *__restrict__ cnt) {
+__global__ void k_s_sub_count(const uint64_t *__restrict__ dets, int64_t n, int sbits, int ss, uint32_t slice,
+                              int32_t *__restrict__ cnt) {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
-    atomicAdd(&cnt[s_sub<PACKED>(dets[2 * x], dets[2 * x + 1], sbits)], 1);
+    const int64_t s = s_sub<PACKED>(dets[2 * x], dets[2 * x + 1], sbits, ss, slice);
+    if (s >= 0) atomicAdd(&cnt[s], 1);
 }
 
 template <bool PACKED>
-__global__ void k_s_sub_fill(const uint64_t *__restrict__ dets, int64_t n, int sbits, const int64_t *__restrict__ offs,
-                             int32_t *__restrict__ cur, uint64_t *__restrict__ skeys) {
+__global__ void k_s_sub_fill(const uint64_t *__restrict__ dets, int64_t n, int sbits, int ss, uint32_t slice,
+                             const int64_t *__restrict__ offs, int32_t *__restrict__ cur,
+                             uint64_t *__restrict__ skeys) {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     const uint64_t a = dets[2 * x], b = dets[2 * x + 1];
-    const int64_t s = s_sub<PACKED>(a, b, sbits);
+    const int64_t s = s_sub<PACKED>(a, b, sbits, ss, slice);
+    if (s < 0) return;
     const int64_t pos = offs[s] + atomicAdd(&cur[s], 1);
     skeys[2 * pos] = a;
     skeys[2 * pos + 1] = b;
 }
 
 void launch_s_sub(hipStream_t st, const uint64_t *dets, int64_t n, int sbits, bool packed, int32_t *cnt,
-                  const int64_t *offs, uint64_t *skeys, bool fill) {
+                  const int64_t *offs, uint64_t *skeys, bool fill, int ss, uint32_t slice) {
     if (n == 0) return;
     dim3 grid((unsigned)((n + 255) / 256)), blk(256);
     if (fill) {
         if (packed)
-            hipLaunchKernelGGL(k_s_sub_fill<true>, grid, blk, 0, st, dets, n, sbits, offs, cnt, skeys);
+            hipLaunchKernelGGL(k_s_sub_fill<true>, grid, blk, 0, st, dets, n, sbits, ss, slice, offs, cnt, skeys);
         else
-            hipLaunchKernelGGL(k_s_sub_fill<false>, grid, blk, 0, st, dets, n, sbits, offs, cnt, skeys);
+            hipLaunchKernelGGL(k_s_sub_fill<false>, grid, blk, 0, st, dets, n, sbits, ss, slice, offs, cnt, skeys);
     } else {
         if (packed)
-            hipLaunchKernelGGL(k_s_sub_count<true>, grid, blk, 0, st, dets, n, sbits, cnt);
+            hipLaunchKernelGGL(k_s_sub_count<true>, grid, blk, 0, st, dets, n, sbits, ss, slice, cnt);
         else
-            hipLaunchKernelGGL(k_s_sub_count<false>, grid, blk, 0, st, dets, n, sbits, cnt);
+            hipLaunchKernelGGL(k_s_sub_count<false>, grid, blk, 0, st, dets, n, sbits, ss, slice, cnt);
     }
 }
 

@@ -124,12 +124,14 @@ PT2_CASES = [("m8_4a4b_full", None), ("m16_5a5b_s16k", 777), ("m16_5a5b_s16k", N
 
 
 @pytest.mark.parametrize("name,n", PT2_CASES)
-def test_pt2_kernel_on_ground_state(dnqs, ctx, name, n):
+@pytest.mark.parametrize("max_pair_bytes", [0, 1 << 24])
+def test_pt2_kernel_on_ground_state(dnqs, ctx, name, n, max_pair_bytes):
     """The paper evaluates PT2 after convergence: psi = lowest eigenvector of H_SS and
     E = its eigenvalue, given to both sides.  Well conditioned (min |E - H_aa| of a few
     Ha here), so the bar is 1e-6 Ha; |P| and the pair count are exact, and sampled
-    w_a agree with the oracle's one-by-one sums."""
-    print(f"[pt2-gs] {name} n={n}", flush=True)
+    w_a agree with the oracle's one-by-one sums.  With a 16 MiB descriptor budget the
+    key space is processed in 2 to 128 slices (same bars; every key of P exported once)."""
+    print(f"[pt2-gs] {name} n={n} max_pair_bytes={max_pair_bytes}", flush=True)
     import scipy.sparse as sp
 
     from oracle import fci
@@ -145,16 +147,19 @@ def test_pt2_kernel_on_ground_state(dnqs, ctx, name, n):
         la = torch.from_numpy(np.log(np.abs(psi))).cuda()
     sg = torch.from_numpy(np.sign(psi).astype(np.int8)).cuda()
     Et = torch.tensor([E0], dtype=torch.float64).cuda()
-    out = ctx.pt2(conn, la, sg, Et, sample_mask=0, export_cap=4096)
+    out = ctx.pt2(conn, la, sg, Et, sample_mask=0, export_cap=4096, max_pair_bytes=max_pair_bytes)
     got = out["out"].cpu().numpy()
     cnt = out["counts"].cpu().numpy()
-    print(f"  dE_PT2 {got[0]:.10f} oracle {o['dE']:.10f} |d| {abs(got[0] - o['dE']):.2e}; |P| {cnt[1]}")
+    print(f"  dE_PT2 {got[0]:.10f} oracle {o['dE']:.10f} |d| {abs(got[0] - o['dE']):.2e}; |P| {cnt[1]}; "
+          f"sub-buckets {cnt[3]}")
     assert abs(got[0] - o["dE"]) <= 1e-6
     assert cnt[1] == o["stats"]["n_p"] and cnt[0] == o["stats"]["pairs"]
     ex = out["export"]
     k = min(int(ex["count"].item()), 4096)
+    assert int(ex["count"].item()) == cnt[1]
     if k:
         keys = dnqs.dets_to_host(ex["keys"][:k])
+        assert len({(int(a), int(b)) for a, b in keys}) == k, "a key was exported twice"
         w_o, haa_o = ham.w_keys(p.wl.M, p.h, p.eri, p.e_core, p.dets, psi, keys)
         # exported w_a are for psi scaled to max |psi_x| = 1
         w_g = ex["w"][:k].cpu().numpy() * np.max(np.abs(psi))
