@@ -74,6 +74,84 @@ def cpu_baseline(p, sample_n: int):
 PRECISIONS = {"fp32": "FP32", "mixed": "MIXED", "split_bf16": "SPLIT_BF16"}
 
 
+def gemm_flops(widths):
+    """FP32-equivalent flops of the network GEMMs per configuration: forward layers 2..L,
+    data gradients of layers L..2, weight gradients (bias row included) of layers L..1."""
+    L = len(widths) - 1
+    fwd = sum(widths[l - 1] * widths[l] for l in range(2, L + 1))
+    dgrad = fwd
+    wgrad = sum((widths[l - 1] + 1) * widths[l] for l in range(1, L + 1))
+    return 2.0 * (fwd + dgrad + wgrad)
+
+
+def bench_sweep(args, dnqs, synth, torch):
+    """|S| sweep on one workload: per size the H_SS build, energy+gradient in FP32 and in
+    the mixed form, and PT2 while the pair count is at most --sweep-pt2-max."""
+    wl = synth.WORKLOADS[args.workload]
+    nexc = n_excitations(wl.M, wl.n_alpha, wl.n_beta)
+    fl = gemm_flops(wl.widths)
+    rows = []
+    for n in [int(float(v)) for v in args.sweep.split(",")]:
+        print(f"[bench] sweep |S| = {n}: building inputs", file=sys.stderr, flush=True)
+        p = synth.make_problem(wl, n_dets=n, out_scale=args.out_scale)
+        ctx = dnqs.Context(0)
+        ctx.autotune(True)
+        ctx.set_integrals(p.h, p.eri, p.e_core, wl.n_alpha, wl.n_beta)
+        dets = dnqs.dets_to_device(p.dets)
+        theta = torch.from_numpy(p.theta).cuda()
+        ctx.timing(True)
+        conn = ctx.build_connections(dets, validate=False)
+        nnz = conn.nnz
+        ctx.timing_reset()
+        conn.free()
+        conn = ctx.build_connections(dets, validate=False)
+        torch.cuda.synchronize()
+        t_h = ctx.timing_get("hss")[0]
+        row = {"n_dets": n, "h_nnz": nnz, "build_connections_ms": t_h,
+               "h_elements_per_s": n * (nexc + 1) / (t_h * 1e-3)}
+        for name in ("fp32", args.precision):
+            pr = getattr(dnqs, PRECISIONS[name])
+            r = ctx.energy_and_grad(wl.widths, theta, conn, precision=pr)   # tunes new shapes
+            r = ctx.energy_and_grad(wl.widths, theta, conn, precision=pr)
+            torch.cuda.synchronize()
+            ctx.timing_reset()
+            for _ in range(max(args.steps, 3)):
+                r = ctx.energy_and_grad(wl.widths, theta, conn, precision=pr)
+            torch.cuda.synchronize()
+            t = ctx.timing_get("egrad")[0] / max(args.steps, 3)
+            peak = FP32_PEAK_TFLOPS if name == "fp32" else BF16_PEAK_TFLOPS / 3.0
+            tf = n * fl / (t * 1e-3) / 1e12
+            row[name] = {"energy_and_grad_ms": t, "amps_grads_per_s": n / (t * 1e-3), "E": r["E"].item(),
+                         "gemm_tflops_fp32_equiv": tf, "gemm_peak_tflops": peak, "gemm_frac_upper": tf / peak}
+        if n * nexc <= args.sweep_pt2_max:
+            r = ctx.energy_and_grad(wl.widths, theta, conn, want_grad=False, precision=getattr(dnqs, PRECISIONS[args.precision]))
+            ctx.timing_reset()
+            out = ctx.pt2(conn, r["logabs"], r["sign"], r["E"])
+            torch.cuda.synchronize()
+            t_p = ctx.timing_get("pt2")[0]
+            c = out["counts"].cpu().numpy()
+            row["pt2"] = {"ms": t_p, "pairs": int(c[0]), "pairs_per_s": int(c[0]) / (t_p * 1e-3),
+                          "unique_P": int(c[1]), "reduce_launches": ctx.timing_get("pt2_reduce")[1],
+                          "dE_pt2": float(out["out"][0].item())}
+        conn.free()
+        ctx.close()
+        rows.append(row)
+        print(f"[bench] sweep |S| = {n}: {json.dumps(row)}", file=sys.stderr, flush=True)
+    big = rows[-1]
+    line = {
+        "metric": "amps+grads/s and H/PT2 elements/s over an |S| sweep",
+        "value": big[args.precision]["amps_grads_per_s"], "unit": "amps+grads/s", "n_gpus": 1,
+        "steps": max(args.steps, 3), "warmup": 2, "ms_per_step": big[args.precision]["energy_and_grad_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16x3+f32", "data": "synthetic",
+        "config": {"workload": wl.name, "M": wl.M, "n_alpha": wl.n_alpha, "n_beta": wl.n_beta,
+                   "widths": list(wl.widths), "precision": args.precision, "n_exc": nexc,
+                   "gemm_flops_per_config": fl},
+        "sweep": rows,
+    }
+    print(json.dumps(line))
+
+
 def bench_curve(args, dnqs, synth, torch):
     """One optimisation step over G geometries: G sequential energy_and_grad calls, one
     batched call, and a replayed HIP graph of the batched step + AdamW (same stream)."""
@@ -170,6 +248,11 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=50000,
                     help="dets of S the oracle is timed on (about 10-30 s of host work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweep", default="",
+                    help="instead of the headline run: comma-separated |S| values on --workload (e.g. "
+                         "m56_12a12b with 1e4,3e4,1e5,3e5,1e6): H_SS, energy+gradient and, up to --sweep-pt2-max "
+                         "pairs, PT2 for each")
+    ap.add_argument("--sweep-pt2-max", type=float, default=2e10)
     ap.add_argument("--curve", type=int, default=0,
                     help="instead of the headline run: energy+gradient over a synthetic dissociation curve of "
                          "this many geometries (M=20, 6a+6b, |S| log-uniform in [2^10, 2^16]), sequential vs "
@@ -201,6 +284,8 @@ def main():
 
     if args.curve:
         return bench_curve(args, dnqs, synth, torch)
+    if args.sweep:
+        return bench_sweep(args, dnqs, synth, torch)
 
     wl = synth.WORKLOADS[args.workload]
     print(f"[bench] building inputs for {wl.name}", file=sys.stderr, flush=True)

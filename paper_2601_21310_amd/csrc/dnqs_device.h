@@ -206,6 +206,27 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Off-diagonal part of row x of H_SS times psi by one wave (sum of the lanes' partial
+// sums; the caller reduces across the wave).  Four independent FP64 partial sums per
+// lane, so that four column loads and psi gathers are in flight at once; fixed order.
+__device__ __forceinline__ double row_dot_lane(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                                               const float *__restrict__ val, const double *__restrict__ psi,
+                                               int64_t x, int lane) {
+    const int64_t b = row_ptr[x], e = row_ptr[x + 1];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int64_t j = b + lane;
+    for (; j + 3 * kWave < e; j += 4 * kWave) {
+        const int32_t c0 = col[j], c1 = col[j + kWave], c2 = col[j + 2 * kWave], c3 = col[j + 3 * kWave];
+        const float v0 = val[j], v1 = val[j + kWave], v2 = val[j + 2 * kWave], v3 = val[j + 3 * kWave];
+        s0 += (double)v0 * psi[c0];
+        s1 += (double)v1 * psi[c1];
+        s2 += (double)v2 * psi[c2];
+        s3 += (double)v3 * psi[c3];
+    }
+    for (; j < e; j += kWave) s0 += (double)val[j] * psi[col[j]];
+    return (s0 + s1) + (s2 + s3);
+}
+
 __device__ __forceinline__ float wave_sum_f(float v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);

@@ -117,10 +117,7 @@ __global__ __launch_bounds__(256) void k_spmv_rows(const int64_t *__restrict__ r
     const int lane = threadIdx.x % kWave;
     const int64_t x = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     if (x >= n) return;
-    const int64_t b = row_ptr[x], e = row_ptr[x + 1];
-    double s = 0.0;
-    for (int64_t j = b + lane; j < e; j += kWave) s += (double)val[j] * psi[col[j]];
-    s = wave_sum(s);
+    const double s = wave_sum(row_dot_lane(row_ptr, col, val, psi, x, lane));
     if (lane == 0) {
         const double px = psi[x];
         const double vx = s + diag[x] * px;

@@ -91,10 +91,7 @@ __global__ __launch_bounds__(kRedBlock) void k_spmv(const int64_t *__restrict__ 
     const int64_t x = (int64_t)blockIdx.x * kSpmvRowsPerBlock + wave;
     double pv = 0.0, pp = 0.0;
     if (x < n) {
-        const int64_t b = row_ptr[x], e = row_ptr[x + 1];
-        double s = 0.0;
-        for (int64_t j = b + lane; j < e; j += kWave) s += (double)val[j] * psi[col[j]];
-        s = wave_sum(s);
+        const double s = wave_sum(row_dot_lane(row_ptr, col, val, psi, x, lane));
         const double px = psi[x];
         const double vx = s + diag[x] * px;
         if (lane == 0) v[x] = vx;

@@ -2,7 +2,7 @@
 // partition passes of k_pt2_part.hip.
 //
 // One workgroup per sub-bucket (~6000 pairs, ~1700 unique keys at the benchmark size):
-//   1. stage the diagonal table (h_pp, V(p,q) = J_pq - d_s K_pq; M <= 32) in LDS;
+//   1. stage the diagonal table (h_pp, V(p,q) = J_pq - d_s K_pq; M <= 62) in LDS;
 //   2. insert the members of S that hash into this sub-bucket, flagged (S is grouped by
 //      the same hash bits once per call, k_s_sub_*), so no key is probed in the global
 //      hash set of S;
@@ -85,6 +85,10 @@ __global__ void k_diag_table(Ham H, double *__restrict__ vt) {
 }
 
 int pt2_diag_table_size(int M) { return 2 * M + (2 * M) * (2 * M - 1) / 2; }
+
+// 128-bit-key reduce: 3 x 32 KB of tables + flags; the diagonal table must fit the
+// remaining LDS of a CU (M <= 62)
+bool pt2_diag_table_fits(int M) { return 3 * 32768 + 1024 + sizeof(double) * pt2_diag_table_size(M) <= 160 * 1024; }
 
 void launch_diag_table(hipStream_t st, const Ham &H, double *vt) {
     const int total = pt2_diag_table_size(H.M);
@@ -184,7 +188,7 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
     __shared__ unsigned long long kb_t[PACKED ? 1 : kRedTab];
     __shared__ double w_t[kRedTab];
     __shared__ uint32_t in_s[kRedTab / 32];
-    extern __shared__ double vt_s[];  // diagonal table (PACKED), sized at launch
+    extern __shared__ double vt_s[];  // diagonal table, sized at launch (empty: global tables)
     for (int t = threadIdx.x; t < kRedTab; t += blockDim.x) {
         ka_t[t] = kEmptyKey;
         if (!PACKED) kb_t[t] = kEmptyKey;
@@ -192,7 +196,8 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
     }
     for (int t = threadIdx.x; t < kRedTab / 32; t += blockDim.x) in_s[t] = 0u;
     const int No = 2 * H.M;
-    if (PACKED)
+    const bool lds_vt = vt != nullptr;  // else (M > 62) H_aa from the global J, K tables
+    if (lds_vt)
         for (int t = threadIdx.x; t < No + No * (No - 1) / 2; t += blockDim.x) vt_s[t] = vt[t];
     __syncthreads();
     bool lost = false;
@@ -256,6 +261,42 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
                 }
                 haa += e;
             }
+        } else if (lds_vt) {
+            // 128-bit keys: alpha p -> p, beta p -> M + p; every pair (p, q) of occupied
+            // spin-orbitals once, from the row of the larger index
+            haa = H.ecore;
+            uint64_t ra = a;
+            while (ra) {
+                const int q = ctz64(ra);
+                ra &= ra - 1;
+                double e = vt_s[q];
+                const double *row = vt_s + No + q * (q - 1) / 2;
+                uint64_t below = a & ((1ull << q) - 1ull);
+                while (below) {
+                    e += row[ctz64(below)];
+                    below &= below - 1;
+                }
+                haa += e;
+            }
+            uint64_t rb = b;
+            while (rb) {
+                const int q = ctz64(rb);
+                rb &= rb - 1;
+                const int qs = H.M + q;
+                double e = vt_s[qs];
+                const double *row = vt_s + No + qs * (qs - 1) / 2;
+                uint64_t al = a;
+                while (al) {
+                    e += row[ctz64(al)];
+                    al &= al - 1;
+                }
+                uint64_t below = b & ((1ull << q) - 1ull);
+                while (below) {
+                    e += row[H.M + ctz64(below)];
+                    below &= below - 1;
+                }
+                haa += e;
+            }
         } else {
             haa = h_diag(H, a, b);
         }
@@ -288,12 +329,16 @@ void launch_pt2_reduce(hipStream_t st, const Ham &H, const uint64_t *dets, const
                        const double *vt, const double *energy, uint64_t sample_mask, const PT2Export &ex, double *part,
                        int *overflow, bool packed) {
     dim3 grid((unsigned)nsb), blk(kRedThreads);
+    const size_t vt_bytes = sizeof(double) * pt2_diag_table_size(H.M);
     if (packed)
-        hipLaunchKernelGGL(k_pt2_reduce<true>, grid, blk, sizeof(double) * pt2_diag_table_size(H.M), st, H, dets, psi, desc, sb, skeys, soffs, n_s, nsb, vt,
+        hipLaunchKernelGGL(k_pt2_reduce<true>, grid, blk, vt_bytes, st, H, dets, psi, desc, sb, skeys, soffs, n_s, nsb, vt,
                            energy, sample_mask, ex, part, overflow);
+    else if (pt2_diag_table_fits(H.M))
+        hipLaunchKernelGGL(k_pt2_reduce<false>, grid, blk, vt_bytes, st, H, dets, psi, desc, sb, skeys, soffs, n_s,
+                           nsb, vt, energy, sample_mask, ex, part, overflow);
     else
-        hipLaunchKernelGGL(k_pt2_reduce<false>, grid, blk, 0, st, H, dets, psi, desc, sb, skeys, soffs, n_s, nsb, vt,
-                           energy, sample_mask, ex, part, overflow);
+        hipLaunchKernelGGL(k_pt2_reduce<false>, grid, blk, 0, st, H, dets, psi, desc, sb, skeys, soffs, n_s, nsb,
+                           (const double *)nullptr, energy, sample_mask, ex, part, overflow);
 }
 
 int pt2_red_tab() { return kRedTab; }
