@@ -217,9 +217,9 @@ def bench_curve(args, dnqs, synth, torch):
 # WRITE_SIZE x 1.0, the factors a 1 GiB device copy gives), valid only for the kernel
 # source they were taken on (profiles/pt2_m28_s1e5_hbm_counters.md).
 MEASURED_TRAFFIC = {
-    ("k_pt2_reduce", "m28_7a7b_s100k"): ("paper_2601_21310_amd/csrc/k_pt2_part.hip",
-                                          "bbec564def08a3fe910c6a7c4c8706c9555defdee9da6c1ab3741f97eecacd66",
-                                          26269499987.5),
+    ("k_pt2_reduce", "m28_7a7b_s100k"): ("paper_2601_21310_amd/csrc/k_pt2_reduce.hip",
+                                          "28f6c412fc2e5f99322845ce8d71b89305926090a9db1e43f86fbed3ccda350f",
+                                          27953532232.1),
 }
 
 
