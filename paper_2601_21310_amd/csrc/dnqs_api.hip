@@ -865,6 +865,9 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
     double *vt = nullptr;
     TRY(ws_t(ctx, "pt2_vt", (size_t)pt2_diag_table_size(sl.M), &vt));
     launch_diag_table(st, H, vt);
+    uint64_t *rec = nullptr;
+    TRY(ws_t(ctx, "pt2_rec", (size_t)4 * std::max<int64_t>(n, 1), &rec));
+    launch_pt2_records(st, conn->dets, psi, n, rec);
     CHECK_LAUNCH(ctx);
     // external sum: partitioned reduce-by-key (k_pt2_part.hip, k_pt2_reduce.hip)
     const int64_t nexc = n_excitations(sl.M, sl.na, sl.nb);
@@ -1015,7 +1018,7 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
                 HIPCHK(ctx, hipMemcpyAsync(o.export_count, ex_save, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
             HIPCHK(ctx, hipMemsetAsync(overflow, 0, sizeof(int), st));
             Timer tr(ctx, "pt2_reduce");
-            launch_pt2_reduce(st, H, conn->dets, psi, desc, sb, nsb, skeys, soffs, n_s, vt, energy, o.sample_mask,
+            launch_pt2_reduce(st, H, rec, desc, sb, nsb, skeys, soffs, n_s, vt, energy, o.sample_mask,
                               ex, part_r, overflow, packed);
             CHECK_LAUNCH(ctx);
             tr.stop();

@@ -121,6 +121,23 @@ void launch_pt2_merge(hipStream_t st, double *acc, const double *part) {
     hipLaunchKernelGGL(k_pt2_merge, dim3(1), dim3(1), 0, st, acc, part);
 }
 
+// rec[x] = {alpha, beta, bits of psi_x, 0}: the reduce's per-pair gather of the source
+// determinant and its amplitude touches one 32-byte record, one cache line
+__global__ void k_pt2_records(const uint64_t *__restrict__ dets, const double *__restrict__ psi, int64_t n,
+                              uint64_t *__restrict__ rec) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    rec[4 * x + 0] = dets[2 * x];
+    rec[4 * x + 1] = dets[2 * x + 1];
+    rec[4 * x + 2] = (uint64_t)__double_as_longlong(psi[x]);
+    rec[4 * x + 3] = 0ull;
+}
+
+void launch_pt2_records(hipStream_t st, const uint64_t *dets, const double *psi, int64_t n, uint64_t *rec) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_pt2_records, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dets, psi, n, rec);
+}
+
 // out = {(int + ext)/norm, int, ext, min den}; counts[1] = |P|, counts[2] = tiny
 __global__ void k_pt2_final(const double *__restrict__ acc_int, const double *__restrict__ acc_ext,
                             const double *__restrict__ stats, double *__restrict__ out, int64_t *__restrict__ counts,

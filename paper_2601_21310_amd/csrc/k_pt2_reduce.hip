@@ -8,9 +8,11 @@
 //      hash set of S;
 //   3. decode every pair descriptor (x XOR flipped positions), recompute H_ax exactly in
 //      FP64 from the packed integrals and accumulate w_a = sum_x H_ax psi_x in a 4096-slot
-//      LDS table (64-bit CAS on the key, FP64 add);
-//   4. for every key not in S add w_a^2 / (E - H_aa) in FP64 to the workgroup's partial
-//      sums, H_aa from the LDS table by the diagonal rule.
+//      LDS table (64-bit CAS on the key, FP64 add); the source determinant and psi_x
+//      come from one 32-byte record, and single excitations are queued and done last;
+//   4. compact the keys not in S to the front of the table, then for each add
+//      w_a^2 / (E - H_aa) in FP64 to the workgroup's partial sums, H_aa from the LDS
+//      table by the diagonal rule.
 // A sub-bucket whose keys do not fit the table raises a flag and the host repeats the L2
 // split and the reduce with twice as many sub-buckets.
 #include "dnqs_device.h"
@@ -86,9 +88,11 @@ __global__ void k_diag_table(Ham H, double *__restrict__ vt) {
 
 int pt2_diag_table_size(int M) { return 2 * M + (2 * M) * (2 * M - 1) / 2; }
 
-// 128-bit-key reduce: 3 x 32 KB of tables + flags; the diagonal table must fit the
+// 128-bit-key reduce: 3 x 32 KB of tables, flags and the singles queue; the diagonal table must fit the
 // remaining LDS of a CU (M <= 62)
-bool pt2_diag_table_fits(int M) { return 3 * 32768 + 1024 + sizeof(double) * pt2_diag_table_size(M) <= 160 * 1024; }
+bool pt2_diag_table_fits(int M) {
+    return 3 * 32768 + 1024 + sizeof(uint64_t) * kRedSingles + sizeof(double) * pt2_diag_table_size(M) <= 160 * 1024;
+}
 
 void launch_diag_table(hipStream_t st, const Ham &H, double *vt) {
     const int total = pt2_diag_table_size(H.M);
@@ -173,9 +177,47 @@ __device__ __forceinline__ int red_insert(unsigned long long *ka_t, unsigned lon
     return -1;
 }
 
+// exclusive scan of one count per thread across the workgroup; total to every thread
+__device__ inline uint32_t red_scan(uint32_t v, uint32_t &total) {
+    __shared__ uint32_t wsum[kRedThreads / kWave];
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    uint32_t inc = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t u = __shfl_up(inc, o, kWave);
+        if (lane >= o) inc += u;
+    }
+    if (lane == kWave - 1) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    total = 0;
+    for (int w = 0; w < kRedThreads / kWave; ++w) {
+        const uint32_t x = wsum[w];
+        if (w < wave) before += x;
+        total += x;
+    }
+    return before + inc - v;
+}
+
+// w_a += H_ax psi_x for one pair descriptor
 template <bool PACKED>
-__global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_t *__restrict__ dets,
-                                                            const double *__restrict__ psi,
+__device__ __forceinline__ bool red_pair(const Ham &H, const uint64_t *__restrict__ rec, uint64_t d,
+                                         unsigned long long *ka_t, unsigned long long *kb_t, double *w_t) {
+    const int64_t x = desc_x(d);
+    const uint4 xr = *reinterpret_cast<const uint4 *>(rec + 4 * x);
+    const uint64_t xa = ((uint64_t)xr.y << 32) | xr.x, xb = ((uint64_t)xr.w << 32) | xr.z;
+    const double px = __longlong_as_double((long long)rec[4 * x + 2]);
+    uint64_t a = xa, b = xb;
+    apply_positions(desc_pos(d), a, b);
+    const double v = h_offdiag(H, EriPacked{H.eri_pk}, a, b, xa, xb) * px;
+    const int s = red_insert<PACKED>(ka_t, kb_t, a, b);
+    if (s < 0) return false;
+    atomicAdd(&w_t[s], v);
+    return true;
+}
+
+template <bool PACKED>
+__global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_t *__restrict__ rec,
                                                             const uint64_t *__restrict__ desc,
                                                             const int64_t *__restrict__ sb,
                                                             const uint64_t *__restrict__ skeys,
@@ -188,6 +230,8 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
     __shared__ unsigned long long kb_t[PACKED ? 1 : kRedTab];
     __shared__ double w_t[kRedTab];
     __shared__ uint32_t in_s[kRedTab / 32];
+    __shared__ uint64_t sq[kRedSingles];  // single excitations, deferred
+    __shared__ int nsq;
     extern __shared__ double vt_s[];  // diagonal table, sized at launch (empty: global tables)
     for (int t = threadIdx.x; t < kRedTab; t += blockDim.x) {
         ka_t[t] = kEmptyKey;
@@ -195,6 +239,7 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
         w_t[t] = 0.0;
     }
     for (int t = threadIdx.x; t < kRedTab / 32; t += blockDim.x) in_s[t] = 0u;
+    if (threadIdx.x == 0) nsq = 0;
     const int No = 2 * H.M;
     const bool lds_vt = vt != nullptr;  // else (M > 62) H_aa from the global J, K tables
     if (lds_vt)
@@ -211,38 +256,71 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
             atomicOr(&in_s[s >> 5], 1u << (s & 31));
     }
     __syncthreads();
+    // Doubles first.  A single excitation's value sums over all occupied orbitals
+    // (~3 N_e integral loads against 1-2 for a double); at ~1% of the pairs in random
+    // order, handled inline they would stall about half of the waves, so they are queued
+    // and done together (inline only if the queue is full).
     const int64_t s0 = sb[blockIdx.x], s1 = sb[blockIdx.x + 1];
     for (int64_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
         const uint64_t d = desc[i];
-        const int64_t x = desc_x(d);
-        const uint64_t xa = dets[2 * x], xb = dets[2 * x + 1];
-        uint64_t a = xa, b = xb;
-        apply_positions(desc_pos(d), a, b);
-        const double v = h_offdiag(H, EriPacked{H.eri_pk}, a, b, xa, xb) * psi[x];
-        const int s = red_insert<PACKED>(ka_t, kb_t, a, b);
-        if (s < 0)
-            lost = true;
-        else
-            atomicAdd(&w_t[s], v);
+        if (((desc_pos(d) >> 14) & 127u) == kNoPos) {
+            const int k = atomicAdd(&nsq, 1);
+            if (k < kRedSingles) {
+                sq[k] = d;
+                continue;
+            }
+        }
+        if (!red_pair<PACKED>(H, rec, d, ka_t, kb_t, w_t)) lost = true;
     }
+    __syncthreads();
+    const int n_sq = min(nsq, kRedSingles);
+    for (int k = threadIdx.x; k < n_sq; k += blockDim.x)
+        if (!red_pair<PACKED>(H, rec, sq[k], ka_t, kb_t, w_t)) lost = true;
     if (lost) atomicOr(overflow, 1);
+    __syncthreads();
+    // compact the keys that enter the sum (not in S, in the sample) to the front of the
+    // table, so that every lane of the H_aa loop below has a key
+    constexpr int kPer = kRedTab / kRedThreads;
+    unsigned long long ck[kPer], cb[kPer];
+    double cw[kPer];
+    uint32_t live = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int t = threadIdx.x + j * kRedThreads;
+        ck[j] = ka_t[t];
+        cb[j] = PACKED ? 0ull : kb_t[t];
+        cw[j] = w_t[t];
+        bool ok = (PACKED ? ck[j] : cb[j]) != kEmptyKey && !((in_s[t >> 5] >> (t & 31)) & 1u);
+        if (ok && sample_mask) {
+            const uint64_t a = PACKED ? (ck[j] & 0xffffffffull) : ck[j], b = PACKED ? (ck[j] >> 32) : cb[j];
+            ok = !(key_hash(a, b) & sample_mask);
+        }
+        live |= (ok ? 1u : 0u) << j;
+    }
+    uint32_t n_live = 0;
+    uint32_t pos = red_scan((uint32_t)__popc(live), n_live);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kPer; ++j)
+        if ((live >> j) & 1u) {
+            ka_t[pos] = ck[j];
+            if (!PACKED) kb_t[pos] = cb[j];
+            w_t[pos] = cw[j];
+            ++pos;
+        }
     __syncthreads();
     const double E = energy[0];
     double sum = 0.0, mn = INFINITY, np = 0.0, nt = 0.0;
-    for (int t = threadIdx.x; t < kRedTab; t += blockDim.x) {
+    for (int t = threadIdx.x; t < (int)n_live; t += blockDim.x) {
         uint64_t a, b;
         if (PACKED) {
             const unsigned long long k = ka_t[t];
-            if (k == kEmptyKey) continue;
             a = k & 0xffffffffull;
             b = k >> 32;
         } else {
-            if (kb_t[t] == kEmptyKey) continue;
             a = ka_t[t];
             b = kb_t[t];
         }
-        if ((in_s[t >> 5] >> (t & 31)) & 1u) continue;
-        if (sample_mask && (key_hash(a, b) & sample_mask)) continue;
         const double w = w_t[t];
         double haa;
         if (PACKED) {
@@ -324,20 +402,20 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
     }
 }
 
-void launch_pt2_reduce(hipStream_t st, const Ham &H, const uint64_t *dets, const double *psi, const uint64_t *desc,
+void launch_pt2_reduce(hipStream_t st, const Ham &H, const uint64_t *rec, const uint64_t *desc,
                        const int64_t *sb, int64_t nsb, const uint64_t *skeys, const int64_t *soffs, int64_t n_s,
                        const double *vt, const double *energy, uint64_t sample_mask, const PT2Export &ex, double *part,
                        int *overflow, bool packed) {
     dim3 grid((unsigned)nsb), blk(kRedThreads);
     const size_t vt_bytes = sizeof(double) * pt2_diag_table_size(H.M);
     if (packed)
-        hipLaunchKernelGGL(k_pt2_reduce<true>, grid, blk, vt_bytes, st, H, dets, psi, desc, sb, skeys, soffs, n_s, nsb, vt,
+        hipLaunchKernelGGL(k_pt2_reduce<true>, grid, blk, vt_bytes, st, H, rec, desc, sb, skeys, soffs, n_s, nsb, vt,
                            energy, sample_mask, ex, part, overflow);
     else if (pt2_diag_table_fits(H.M))
-        hipLaunchKernelGGL(k_pt2_reduce<false>, grid, blk, vt_bytes, st, H, dets, psi, desc, sb, skeys, soffs, n_s,
+        hipLaunchKernelGGL(k_pt2_reduce<false>, grid, blk, vt_bytes, st, H, rec, desc, sb, skeys, soffs, n_s,
                            nsb, vt, energy, sample_mask, ex, part, overflow);
     else
-        hipLaunchKernelGGL(k_pt2_reduce<false>, grid, blk, 0, st, H, dets, psi, desc, sb, skeys, soffs, n_s, nsb,
+        hipLaunchKernelGGL(k_pt2_reduce<false>, grid, blk, 0, st, H, rec, desc, sb, skeys, soffs, n_s, nsb,
                            (const double *)nullptr, energy, sample_mask, ex, part, overflow);
 }
 
