@@ -156,9 +156,24 @@ void launch_s_sub(hipStream_t st, const uint64_t *dets, int64_t n, int sbits, bo
 
 // ------------------------------------------------------------------ reduce kernel
 // Insert (a, b) into the LDS table; returns the slot or -1 when the table is full.
+// Slot of a key in the LDS table: a 32-bit fold of the key through the lowbias32
+// integer hash (C. Wellons, hash-prospector).  Independent of the partition hash, whose
+// top bits chose the sub-bucket, and about a third of its cost.
+template <bool PACKED>
+__device__ __forceinline__ uint32_t red_slot(uint64_t a, uint64_t b) {
+    uint32_t f = (uint32_t)a ^ ((uint32_t)b * 0x9e3779b1u);
+    if (!PACKED) f ^= ((uint32_t)(a >> 32) * 0x85ebca6bu) ^ ((uint32_t)(b >> 32) * 0xc2b2ae35u);
+    f ^= f >> 16;
+    f *= 0x7feb352du;
+    f ^= f >> 15;
+    f *= 0x846ca68bu;
+    f ^= f >> 16;
+    return f & (kRedTab - 1);
+}
+
 template <bool PACKED>
 __device__ __forceinline__ int red_insert(unsigned long long *ka_t, unsigned long long *kb_t, uint64_t a, uint64_t b) {
-    uint32_t s = (uint32_t)target_hash<PACKED>(a, b) & (kRedTab - 1);
+    uint32_t s = red_slot<PACKED>(a, b);
     for (int p = 0; p < kRedTab; ++p) {
         if (PACKED) {
             const unsigned long long k = pack_key(a, b);
@@ -175,6 +190,59 @@ __device__ __forceinline__ int red_insert(unsigned long long *ka_t, unsigned lon
         s = (s + 1) & (kRedTab - 1);
     }
     return -1;
+}
+
+// H_aa by the diagonal rule from the LDS table, with the loops unrolled over at most
+// kHaaOcc electrons per spin.  Every key of the sector has na alpha and nb beta electrons,
+// so the trip counts are the same on every lane and the occupied indices stay in
+// registers.  W: 32-bit strings (M <= 32) or 64-bit.
+constexpr int kHaaOcc = 16;
+
+__device__ __forceinline__ int low_bit(uint32_t m) { return __builtin_ctz(m); }
+__device__ __forceinline__ int low_bit(uint64_t m) { return ctz64(m); }
+
+template <typename W>
+__device__ __forceinline__ double haa_unrolled(const double *vt, int No, int M, int na, int nb, W a, W b,
+                                               double ecore) {
+    int oa[kHaaOcc], ob[kHaaOcc];
+#pragma unroll
+    for (int k = 0; k < kHaaOcc; ++k) {
+        oa[k] = 0;
+        ob[k] = 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kHaaOcc; ++k)
+        if (k < na) {
+            oa[k] = low_bit(a);
+            a &= a - 1;
+        }
+#pragma unroll
+    for (int k = 0; k < kHaaOcc; ++k)
+        if (k < nb) {
+            ob[k] = M + low_bit(b);
+            b &= b - 1;
+        }
+    double e0 = ecore, e1 = 0.0, e2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < kHaaOcc; ++q)
+        if (q < na) {
+            const double *row = vt + No + oa[q] * (oa[q] - 1) / 2;
+            e0 += vt[oa[q]];
+#pragma unroll
+            for (int p = 0; p < q; ++p) e1 += row[oa[p]];
+        }
+#pragma unroll
+    for (int q = 0; q < kHaaOcc; ++q)
+        if (q < nb) {
+            const double *row = vt + No + ob[q] * (ob[q] - 1) / 2;
+            e0 += vt[ob[q]];
+#pragma unroll
+            for (int p = 0; p < kHaaOcc; ++p)
+                if (p < na) e2 += row[oa[p]];
+#pragma unroll
+            for (int p = 0; p < q; ++p) e1 += row[ob[p]];
+        }
+    return e0 + (e1 + e2);
 }
 
 // exclusive scan of one count per thread across the workgroup; total to every thread
@@ -199,7 +267,21 @@ __device__ inline uint32_t red_scan(uint32_t v, uint32_t &total) {
     return before + inc - v;
 }
 
-// w_a += H_ax psi_x for one pair descriptor
+// (-1)^(occupied orbitals of s strictly between p and q); 32-bit strings when M <= 32
+template <bool PACKED>
+__device__ __forceinline__ int red_phase(uint64_t s, int p, int q) {
+    if (PACKED) {
+        const int lo = min(p, q), hi = max(p, q);
+        const uint32_t m = ((1u << hi) - 1u) & ~((2u << lo) - 1u);
+        return (__popc((uint32_t)s & m) & 1) ? -1 : 1;
+    }
+    return phase_between(s, p, q);
+}
+
+// w_a += H_ax psi_x for one pair descriptor.  The descriptor's flipped positions give the
+// excitation directly (holes of x, then particles; ascending within a spin), so the
+// class, the orbitals and the target are read off it; the values and phases are those of
+// the Slater-Condon rules with ascending hole/particle pairing (h_offdiag).
 template <bool PACKED>
 __device__ __forceinline__ bool red_pair(const Ham &H, const uint64_t *__restrict__ rec, uint64_t d,
                                          unsigned long long *ka_t, unsigned long long *kb_t, double *w_t) {
@@ -207,12 +289,45 @@ __device__ __forceinline__ bool red_pair(const Ham &H, const uint64_t *__restric
     const uint4 xr = *reinterpret_cast<const uint4 *>(rec + 4 * x);
     const uint64_t xa = ((uint64_t)xr.y << 32) | xr.x, xb = ((uint64_t)xr.w << 32) | xr.z;
     const double px = __longlong_as_double((long long)rec[4 * x + 2]);
+    const uint32_t pos = desc_pos(d);
+    const int p0 = (int)(pos & 127u), p1 = (int)((pos >> 7) & 127u), p2 = (int)((pos >> 14) & 127u),
+              p3 = (int)((pos >> 21) & 127u);
+    const EriPacked eri{H.eri_pk};
     uint64_t a = xa, b = xb;
-    apply_positions(desc_pos(d), a, b);
-    const double v = h_offdiag(H, EriPacked{H.eri_pk}, a, b, xa, xb) * px;
+    double v;
+    if (p2 == (int)kNoPos) {  // single: hole p0, particle p1
+        const bool beta = p0 >= 64;
+        const int q = p0 & 63, p = p1 & 63;
+        const uint64_t same = beta ? xb : xa, other = beta ? xa : xb;
+        const uint64_t flip = (1ull << q) | (1ull << p);
+        if (beta)
+            b ^= flip;
+        else
+            a ^= flip;
+        v = red_phase<PACKED>(same, p, q) * single_value(H, eri, p, q, same, other);
+    } else if (p0 < 64 && p2 >= 64) {  // alpha-beta double: i -> r (alpha), j -> s (beta)
+        const int i = p0, r = p1, j = p2 - 64, t = p3 - 64;
+        a ^= (1ull << i) | (1ull << r);
+        b ^= (1ull << j) | (1ull << t);
+        v = (red_phase<PACKED>(xa, i, r) * red_phase<PACKED>(xb, j, t)) * eri(r, i, t, j);
+    } else {  // same-spin double: holes i < j, particles r < t
+        const bool beta = p0 >= 64;
+        const int h0 = p0 & 63, h1 = p1 & 63, q0 = p2 & 63, q1 = p3 & 63;
+        const int i = min(h0, h1), j = max(h0, h1), r = min(q0, q1), t = max(q0, q1);
+        const uint64_t s0 = beta ? xb : xa;
+        const uint64_t flip = (1ull << i) | (1ull << j) | (1ull << r) | (1ull << t);
+        if (beta)
+            b ^= flip;
+        else
+            a ^= flip;
+        const int ph1 = red_phase<PACKED>(s0, i, r);
+        const uint64_t s1 = (s0 & ~(1ull << i)) | (1ull << r);
+        const int ph2 = red_phase<PACKED>(s1, j, t);
+        v = (ph1 * ph2) * (eri(r, i, t, j) - eri(r, j, t, i));
+    }
     const int s = red_insert<PACKED>(ka_t, kb_t, a, b);
     if (s < 0) return false;
-    atomicAdd(&w_t[s], v);
+    atomicAdd(&w_t[s], v * px);
     return true;
 }
 
@@ -323,7 +438,11 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
         }
         const double w = w_t[t];
         double haa;
-        if (PACKED) {
+        if (PACKED && H.na <= kHaaOcc && H.nb <= kHaaOcc) {
+            haa = haa_unrolled<uint32_t>(vt_s, No, H.M, H.na, H.nb, (uint32_t)a, (uint32_t)b, H.ecore);
+        } else if (!PACKED && lds_vt && H.na <= kHaaOcc && H.nb <= kHaaOcc) {
+            haa = haa_unrolled<uint64_t>(vt_s, No, H.M, H.na, H.nb, a, b, H.ecore);
+        } else if (PACKED) {
             const uint64_t occ = a | (b << H.M);
             haa = H.ecore;
             uint64_t rest = occ;
