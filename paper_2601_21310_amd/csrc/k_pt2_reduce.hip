@@ -278,56 +278,131 @@ __device__ __forceinline__ int red_phase(uint64_t s, int p, int q) {
     return phase_between(s, p, q);
 }
 
-// w_a += H_ax psi_x for one pair descriptor.  The descriptor's flipped positions give the
+// H_ax psi_x for one pair descriptor.  The descriptor's flipped positions give the
 // excitation directly (holes of x, then particles; ascending within a spin), so the
 // class, the orbitals and the target are read off it; the values and phases are those of
 // the Slater-Condon rules with ascending hole/particle pairing (h_offdiag).
-template <bool PACKED>
-__device__ __forceinline__ bool red_pair(const Ham &H, const uint64_t *__restrict__ rec, uint64_t d,
-                                         unsigned long long *ka_t, unsigned long long *kb_t, double *w_t) {
+// the source record of a pair: x's strings and psi_x
+struct SrcRec {
+    uint4 s;      // alpha (x, y), beta (z, w) as 32-bit halves
+    uint64_t p;   // bits of psi_x
+};
+
+__device__ __forceinline__ SrcRec load_src(const uint64_t *__restrict__ rec, uint64_t d) {
     const int64_t x = desc_x(d);
-    const uint4 xr = *reinterpret_cast<const uint4 *>(rec + 4 * x);
-    const uint64_t xa = ((uint64_t)xr.y << 32) | xr.x, xb = ((uint64_t)xr.w << 32) | xr.z;
-    const double px = __longlong_as_double((long long)rec[4 * x + 2]);
+    return SrcRec{*reinterpret_cast<const uint4 *>(rec + 4 * x), rec[4 * x + 2]};
+}
+
+// A pair's target (a, b) and the factors of H_ax psi_x = ph * (e1 - e2) * psi_x.  The
+// integrals are kept as loaded and combined in red_add, after the loop has issued its
+// prefetches, so that the wait for them does not cover the prefetches.
+struct PairVal {
+    uint64_t a, b;
+    double e1, e2, px;
+    int ph;
+};
+
+__device__ __forceinline__ uint64_t src_alpha(const SrcRec &sr) { return ((uint64_t)sr.s.y << 32) | sr.s.x; }
+__device__ __forceinline__ uint64_t src_beta(const SrcRec &sr) { return ((uint64_t)sr.s.w << 32) | sr.s.z; }
+
+// Double excitations.  The descriptor's flipped positions give the excitation directly
+// (holes of x, then particles; ascending within a spin), so the class, the orbitals and
+// the target are read off it; values and phases are those of the Slater-Condon rules with
+// ascending hole/particle pairing (h_offdiag).  One code path for both classes (a wave
+// nearly always holds both), straight-line so that the loads can be waited for by count:
+//   alpha-beta: i -> r (alpha), j -> t (beta), value (ri|tj)
+//   same-spin:  holes i < j, particles r < t, value (ri|tj) - (rj|ti)
+// For alpha-beta pairs the second load re-reads the first integral and is not used.
+// Called on every descriptor of the sub-bucket, singles included.
+template <bool PACKED>
+__device__ __forceinline__ PairVal double_value(const Ham &H, const SrcRec &sr, uint64_t d) {
+    const uint64_t xa = src_alpha(sr), xb = src_beta(sr);
     const uint32_t pos = desc_pos(d);
-    const int p0 = (int)(pos & 127u), p1 = (int)((pos >> 7) & 127u), p2 = (int)((pos >> 14) & 127u),
-              p3 = (int)((pos >> 21) & 127u);
-    const EriPacked eri{H.eri_pk};
-    uint64_t a = xa, b = xb;
-    double v;
-    if (p2 == (int)kNoPos) {  // single: hole p0, particle p1
-        const bool beta = p0 >= 64;
-        const int q = p0 & 63, p = p1 & 63;
-        const uint64_t same = beta ? xb : xa, other = beta ? xa : xb;
-        const uint64_t flip = (1ull << q) | (1ull << p);
-        if (beta)
-            b ^= flip;
-        else
-            a ^= flip;
-        v = red_phase<PACKED>(same, p, q) * single_value(H, eri, p, q, same, other);
-    } else if (p0 < 64 && p2 >= 64) {  // alpha-beta double: i -> r (alpha), j -> s (beta)
-        const int i = p0, r = p1, j = p2 - 64, t = p3 - 64;
-        a ^= (1ull << i) | (1ull << r);
-        b ^= (1ull << j) | (1ull << t);
-        v = (red_phase<PACKED>(xa, i, r) * red_phase<PACKED>(xb, j, t)) * eri(r, i, t, j);
-    } else {  // same-spin double: holes i < j, particles r < t
-        const bool beta = p0 >= 64;
-        const int h0 = p0 & 63, h1 = p1 & 63, q0 = p2 & 63, q1 = p3 & 63;
-        const int i = min(h0, h1), j = max(h0, h1), r = min(q0, q1), t = max(q0, q1);
-        const uint64_t s0 = beta ? xb : xa;
-        const uint64_t flip = (1ull << i) | (1ull << j) | (1ull << r) | (1ull << t);
-        if (beta)
-            b ^= flip;
-        else
-            a ^= flip;
-        const int ph1 = red_phase<PACKED>(s0, i, r);
-        const uint64_t s1 = (s0 & ~(1ull << i)) | (1ull << r);
-        const int ph2 = red_phase<PACKED>(s1, j, t);
-        v = (ph1 * ph2) * (eri(r, i, t, j) - eri(r, j, t, i));
+    const int p0 = (int)(pos & 127u), p1 = (int)((pos >> 7) & 127u);
+    // A single's last two positions are kNoPos: it is called on singles too (their result
+    // is discarded), so use its two real positions there to keep every index in the table.
+    const bool single = ((pos >> 14) & 127u) == kNoPos;
+    const int p2 = single ? p0 : (int)((pos >> 14) & 127u), p3 = single ? p1 : (int)((pos >> 21) & 127u);
+    const bool ab = p0 < 64 && p2 >= 64, beta = p0 >= 64;
+    const int i = p0 & 63, t = p3 & 63;
+    const int r = ab ? p1 : (p2 & 63), j = ab ? (p2 - 64) : (p1 & 63);
+    const uint64_t f_ir = (1ull << i) | (1ull << r), f_jt = (1ull << j) | (1ull << t);
+    const uint64_t s1 = beta ? xb : xa;                                    // holds i and r
+    const uint64_t s2 = ab ? xb : ((s1 & ~(1ull << i)) | (1ull << r));  // holds j and t
+    const int ri = tri_index(r, i), tj = tri_index(t, j);
+    const int rj = tri_index(r, j), ti = tri_index(t, i);
+    const double *e = H.eri_pk;
+    PairVal pv;
+    pv.a = xa ^ (ab ? f_ir : (beta ? 0ull : (f_ir | f_jt)));
+    pv.b = xb ^ (ab ? f_jt : (beta ? (f_ir | f_jt) : 0ull));
+    pv.e1 = e[tri_index(ri, tj)];
+    pv.e2 = e[ab ? tri_index(ri, tj) : tri_index(rj, ti)];
+    if (ab) pv.e2 = 0.0;
+    pv.px = __longlong_as_double((long long)sr.p);
+    pv.ph = red_phase<PACKED>(s1, i, r) * red_phase<PACKED>(s2, j, t);
+    return pv;
+}
+
+// Single-excitation value (as single_value: h_pq + sum over the occupied r != q of
+// (pq|rr) - [same spin] (pr|rq), same spin first, both in ascending r, so the result is
+// the same to the bit) with the integral loads issued eight orbitals at a time: a single
+// costs a few load latencies instead of one per occupied orbital.
+__device__ __forceinline__ double single_value_grouped(const Ham &H, int p, int q, uint64_t same, uint64_t other) {
+    const double *e = H.eri_pk;
+    const int pq = tri_index(p, q);
+    double v = H.h64[p * H.M + q];
+    uint64_t s = same & ~(1ull << q), o = other;
+    while (s | o) {
+        double c[8], x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            c[k] = 0.0;
+            x[k] = 0.0;
+            if (s) {
+                const int r = ctz64(s);
+                s &= s - 1;
+                c[k] = e[tri_index(pq, tri_index(r, r))];
+                x[k] = e[tri_index(tri_index(p, r), tri_index(r, q))];
+            } else if (o) {
+                const int r = ctz64(o);
+                o &= o - 1;
+                c[k] = e[tri_index(pq, tri_index(r, r))];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v += c[k] - x[k];
     }
-    const int s = red_insert<PACKED>(ka_t, kb_t, a, b);
+    return v;
+}
+
+// Single excitation (hole p0, particle p1): the value sums over the occupied orbitals.
+template <bool PACKED>
+__device__ __forceinline__ PairVal single_pair(const Ham &H, const SrcRec &sr, uint64_t d) {
+    const uint64_t xa = src_alpha(sr), xb = src_beta(sr);
+    const uint32_t pos = desc_pos(d);
+    const int p0 = (int)(pos & 127u), p1 = (int)((pos >> 7) & 127u);
+    const bool beta = p0 >= 64;
+    const int q = p0 & 63, p = p1 & 63;
+    const uint64_t same = beta ? xb : xa, other = beta ? xa : xb;
+    const uint64_t flip = (1ull << q) | (1ull << p);
+    PairVal pv;
+    pv.a = beta ? xa : (xa ^ flip);
+    pv.b = beta ? (xb ^ flip) : xb;
+    pv.e1 = single_value_grouped(H, p, q, same, other);
+    pv.e2 = 0.0;
+    pv.px = __longlong_as_double((long long)sr.p);
+    pv.ph = red_phase<PACKED>(same, p, q);
+    return pv;
+}
+
+__device__ __forceinline__ bool is_single(uint64_t d) { return ((desc_pos(d) >> 14) & 127u) == kNoPos; }
+
+template <bool PACKED>
+__device__ __forceinline__ bool red_add(const PairVal &pv, unsigned long long *ka_t, unsigned long long *kb_t,
+                                        double *w_t) {
+    const int s = red_insert<PACKED>(ka_t, kb_t, pv.a, pv.b);
     if (s < 0) return false;
-    atomicAdd(&w_t[s], v * px);
+    atomicAdd(&w_t[s], (pv.ph * (pv.e1 - pv.e2)) * pv.px);
     return true;
 }
 
@@ -374,23 +449,56 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
     // Doubles first.  A single excitation's value sums over all occupied orbitals
     // (~3 N_e integral loads against 1-2 for a double); at ~1% of the pairs in random
     // order, handled inline they would stall about half of the waves, so they are queued
-    // and done together (inline only if the queue is full).
-    const int64_t s0 = sb[blockIdx.x], s1 = sb[blockIdx.x + 1];
-    for (int64_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
-        const uint64_t d = desc[i];
-        if (((desc_pos(d) >> 14) & 127u) == kNoPos) {
-            const int k = atomicAdd(&nsq, 1);
-            if (k < kRedSingles) {
-                sq[k] = d;
-                continue;
+    // and done together after the doubles.
+    // The per-pair work is a chain of dependent loads (descriptor from HBM, then the source
+    // record, then the integrals, from L2), so the loop is software-pipelined: the
+    // descriptor of pair k + 4 and the source record of pair k + 1 are loaded while pair k
+    // is done.  The loop is unrolled over a ring of four descriptor and two record
+    // registers (no register moves, which would wait for the newest load), the loads are
+    // unconditional (index clamped into the sub-bucket) and come after the current pair's
+    // integral loads, so that every wait is for a count of loads and never for a
+    // prefetch.  Singles go to the LDS queue; if it fills up they are all redone by a
+    // rescan instead.
+    const int64_t s0 = sb[blockIdx.x], s1 = sb[blockIdx.x + 1], step = blockDim.x;
+    if (s1 > s0) {
+        const int64_t base = s0 + threadIdx.x;
+        auto ld_desc = [&](int64_t k) { return desc[min(base + k * step, s1 - 1)]; };
+        uint64_t D0 = ld_desc(0), D1 = ld_desc(1), D2 = ld_desc(2), D3 = ld_desc(3);
+        SrcRec R0 = load_src(rec, D0), R1{};
+        // pair k: descriptor Dk, record Rk; loads the record of pair k + 1 (from Dn) into
+        // Rn and the descriptor of pair k + 4 into Dk
+        auto stage = [&](int64_t k, uint64_t &Dk, const SrcRec &Rk, const uint64_t &Dn, SrcRec &Rn) {
+            const uint64_t d = Dk;
+            const PairVal pv = double_value<PACKED>(H, Rk, d);
+            Rn = load_src(rec, Dn);
+            Dk = ld_desc(k + 4);
+            if (base + k * step < s1) {
+                if (is_single(d)) {
+                    const int q = atomicAdd(&nsq, 1);
+                    if (q < kRedSingles) sq[q] = d;
+                } else if (!red_add<PACKED>(pv, ka_t, kb_t, w_t)) {
+                    lost = true;
+                }
             }
+        };
+        for (int64_t k = 0; base + k * step < s1; k += 4) {
+            stage(k, D0, R0, D1, R1);
+            stage(k + 1, D1, R1, D2, R0);
+            stage(k + 2, D2, R0, D3, R1);
+            stage(k + 3, D3, R1, D0, R0);
         }
-        if (!red_pair<PACKED>(H, rec, d, ka_t, kb_t, w_t)) lost = true;
     }
     __syncthreads();
-    const int n_sq = min(nsq, kRedSingles);
-    for (int k = threadIdx.x; k < n_sq; k += blockDim.x)
-        if (!red_pair<PACKED>(H, rec, sq[k], ka_t, kb_t, w_t)) lost = true;
+    if (nsq <= kRedSingles) {
+        for (int k = threadIdx.x; k < nsq; k += blockDim.x)
+            if (!red_add<PACKED>(single_pair<PACKED>(H, load_src(rec, sq[k]), sq[k]), ka_t, kb_t, w_t)) lost = true;
+    } else {
+        for (int64_t i = s0 + threadIdx.x; i < s1; i += step) {
+            const uint64_t d = desc[i];
+            if (is_single(d) && !red_add<PACKED>(single_pair<PACKED>(H, load_src(rec, d), d), ka_t, kb_t, w_t))
+                lost = true;
+        }
+    }
     if (lost) atomicOr(overflow, 1);
     __syncthreads();
     // compact the keys that enter the sum (not in S, in the sample) to the front of the
