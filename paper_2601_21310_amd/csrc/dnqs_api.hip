@@ -841,7 +841,8 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
     double *psi = nullptr, *v = nullptr, *part = nullptr, *part2 = nullptr, *stats = nullptr, *e_tmp = nullptr;
     TRY(ws_t(ctx, "pt2_psi", (size_t)n, &psi));
     TRY(ws_t(ctx, "pt2_v", (size_t)n, &v));
-    TRY(ws_t(ctx, "pt2_part", (size_t)std::max<int64_t>(spmv_blocks(n), 4 * 2048), &part));
+    TRY(ws_t(ctx, "pt2_part", (size_t)std::max<int64_t>({spmv_blocks(n), 4 * 2048, (int64_t)pt2_accumulate_scratch()}),
+             &part));
     TRY(ws_t(ctx, "pt2_part2", (size_t)spmv_blocks(n), &part2));
     TRY(ws_t(ctx, "pt2_stats", 4, &stats));
     TRY(ws_t(ctx, "pt2_etmp", 1, &e_tmp));
@@ -1022,7 +1023,7 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
                               ex, part_r, overflow, packed);
             CHECK_LAUNCH(ctx);
             tr.stop();
-            launch_pt2_accumulate(st, part_r, nsb, acc + 8);
+            launch_pt2_accumulate(st, part_r, nsb, acc + 8, part);  // the internal-term partials are used up
             CHECK_LAUNCH(ctx);
             int ov = 0;
             HIPCHK(ctx, hipMemcpyAsync(&ov, overflow, sizeof ov, hipMemcpyDeviceToHost, st));

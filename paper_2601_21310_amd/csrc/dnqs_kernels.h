@@ -176,7 +176,10 @@ void launch_pt2_reduce(hipStream_t st, const Ham &H, const uint64_t *rec, const 
                        const int64_t *sb, int64_t nsb, const uint64_t *skeys, const int64_t *soffs, int64_t n_s,
                        const double *vt, const double *energy, uint64_t sample_mask, const PT2Export &ex, double *part,
                        int *overflow, bool packed);
-void launch_pt2_accumulate(hipStream_t st, const double *part, int64_t nb, double *acc);
+// acc += the partials part[4 nb] (sum, min, |P|, tiny), in a fixed order; scratch (if not
+// null) holds pt2_accumulate_scratch() doubles for a two-level sum
+void launch_pt2_accumulate(hipStream_t st, const double *part, int64_t nb, double *acc, double *scratch = nullptr);
+int pt2_accumulate_scratch();
 void launch_pt2_internal(hipStream_t st, const double *psi, const double *v, const double *diag, int64_t n,
                          const double *energy, double *part, double *acc_int);
 void launch_pt2_init_acc(hipStream_t st, double *acc);

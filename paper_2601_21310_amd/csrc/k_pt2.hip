@@ -102,9 +102,41 @@ void launch_pt2_internal(hipStream_t st, const double *psi, const double *v, con
     hipLaunchKernelGGL(k_pt2_accumulate, dim3(1), dim3(kFinBlock), 0, st, part, nb, acc_int);
 }
 
-void launch_pt2_accumulate(hipStream_t st, const double *part, int64_t nb, double *acc) {
-    hipLaunchKernelGGL(k_pt2_accumulate, dim3(1), dim3(kFinBlock), 0, st, part, nb, acc);
+// Contiguous chunks of the partials summed by many workgroups (fixed order within a
+// chunk, then over the chunks), for the ~5e5 partials of the external sum.
+constexpr int kAccBlocks = 1024;
+
+__global__ __launch_bounds__(kFinBlock) void k_pt2_accumulate_chunks(const double *__restrict__ part, int64_t nb,
+                                                                     double *__restrict__ out) {
+    const int64_t chunk = (nb + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * chunk, hi = lo + chunk < nb ? lo + chunk : nb;
+    double s = 0.0, mn = INFINITY;
+    unsigned long long np = 0, nt = 0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        s += part[4 * i];
+        mn = fmin(mn, part[4 * i + 1]);
+        np += (unsigned long long)part[4 * i + 2];
+        nt += (unsigned long long)part[4 * i + 3];
+    }
+    block_sum_min(s, mn, np, nt);
+    if (threadIdx.x == 0) {
+        out[4 * blockIdx.x + 0] = s;
+        out[4 * blockIdx.x + 1] = mn;
+        out[4 * blockIdx.x + 2] = (double)np;
+        out[4 * blockIdx.x + 3] = (double)nt;
+    }
 }
+
+void launch_pt2_accumulate(hipStream_t st, const double *part, int64_t nb, double *acc, double *scratch) {
+    if (scratch && nb > 4 * kAccBlocks) {
+        hipLaunchKernelGGL(k_pt2_accumulate_chunks, dim3(kAccBlocks), dim3(kFinBlock), 0, st, part, nb, scratch);
+        hipLaunchKernelGGL(k_pt2_accumulate, dim3(1), dim3(kFinBlock), 0, st, scratch, (int64_t)kAccBlocks, acc);
+    } else {
+        hipLaunchKernelGGL(k_pt2_accumulate, dim3(1), dim3(kFinBlock), 0, st, part, nb, acc);
+    }
+}
+
+int pt2_accumulate_scratch() { return 4 * kAccBlocks; }
 
 void launch_pt2_init_acc(hipStream_t st, double *acc) {
     hipLaunchKernelGGL(k_pt2_init_acc, dim3(1), dim3(1), 0, st, acc);

@@ -395,6 +395,48 @@ __device__ __forceinline__ PairVal single_pair(const Ham &H, const SrcRec &sr, u
     return pv;
 }
 
+// One lane's share of a single (hole p0, particle p1) spread over eight lanes: lane l
+// sums the terms of the occupied orbitals r != q numbered l, l + 8, ... (same spin first,
+// ascending) into part; the returned e1 holds h_pq, and the caller adds the eight parts.
+template <bool PACKED>
+__device__ __forceinline__ PairVal single_part(const Ham &H, const SrcRec &sr, uint64_t d, int l, double &part) {
+    const uint64_t xa = src_alpha(sr), xb = src_beta(sr);
+    const uint32_t pos = desc_pos(d);
+    const int p0 = (int)(pos & 127u), p1 = (int)((pos >> 7) & 127u);
+    const bool beta = p0 >= 64;
+    const int q = p0 & 63, p = p1 & 63;
+    const uint64_t same = beta ? xb : xa, other = beta ? xa : xb;
+    const uint64_t flip = (1ull << q) | (1ull << p);
+    const double *e = H.eri_pk;
+    const int pq = tri_index(p, q);
+    uint64_t sm = same & ~(1ull << q), om = other;
+    const int ns = popc64(sm);
+    // this lane's orbitals: entries l, l + 8, ... of (same-spin list, other-spin list)
+    for (int idx = 0; ; idx += 8) {
+        const int n = idx + l;
+        if (n >= ns + popc64(om)) break;
+        if (n < ns) {
+            uint64_t m = sm;
+            for (int c = 0; c < n; ++c) m &= m - 1;
+            const int r = ctz64(m);
+            part += e[tri_index(pq, tri_index(r, r))] - e[tri_index(tri_index(p, r), tri_index(r, q))];
+        } else {
+            uint64_t m = om;
+            for (int c = 0; c < n - ns; ++c) m &= m - 1;
+            const int r = ctz64(m);
+            part += e[tri_index(pq, tri_index(r, r))];
+        }
+    }
+    PairVal pv;
+    pv.a = beta ? xa : (xa ^ flip);
+    pv.b = beta ? (xb ^ flip) : xb;
+    pv.e1 = H.h64[p * H.M + q];
+    pv.e2 = 0.0;
+    pv.px = __longlong_as_double((long long)sr.p);
+    pv.ph = red_phase<PACKED>(same, p, q);
+    return pv;
+}
+
 __device__ __forceinline__ bool is_single(uint64_t d) { return ((desc_pos(d) >> 14) & 127u) == kNoPos; }
 
 template <bool PACKED>
@@ -490,8 +532,21 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
     }
     __syncthreads();
     if (nsq <= kRedSingles) {
-        for (int k = threadIdx.x; k < nsq; k += blockDim.x)
-            if (!red_add<PACKED>(single_pair<PACKED>(H, load_src(rec, sq[k]), sq[k]), ka_t, kb_t, w_t)) lost = true;
+        // eight lanes per queued single, each summing every eighth occupied orbital
+        for (int k0 = 0; k0 < nsq; k0 += kRedThreads / 8) {
+            const int k = k0 + (int)(threadIdx.x >> 3), l = (int)(threadIdx.x & 7);
+            const bool have = k < nsq;
+            PairVal pv{};
+            double part_v = 0.0;
+            if (have) pv = single_part<PACKED>(H, load_src(rec, sq[k]), sq[k], l, part_v);
+            part_v += __shfl_xor(part_v, 1, 8);
+            part_v += __shfl_xor(part_v, 2, 8);
+            part_v += __shfl_xor(part_v, 4, 8);
+            if (have && l == 0) {
+                pv.e1 += part_v;
+                if (!red_add<PACKED>(pv, ka_t, kb_t, w_t)) lost = true;
+            }
+        }
     } else {
         for (int64_t i = s0 + threadIdx.x; i < s1; i += step) {
             const uint64_t d = desc[i];
