@@ -866,14 +866,14 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
     double *vt = nullptr;
     TRY(ws_t(ctx, "pt2_vt", (size_t)pt2_diag_table_size(sl.M), &vt));
     launch_diag_table(st, H, vt);
-    uint64_t *rec = nullptr;
-    TRY(ws_t(ctx, "pt2_rec", (size_t)4 * std::max<int64_t>(n, 1), &rec));
-    launch_pt2_records(st, conn->dets, psi, n, rec);
-    CHECK_LAUNCH(ctx);
     // external sum: partitioned reduce-by-key (k_pt2_part.hip, k_pt2_reduce.hip)
     const int64_t nexc = n_excitations(sl.M, sl.na, sl.nb);
     const int64_t pairs = n * nexc;
     const bool packed = sl.M <= 32 && !(sl.M == 32 && sl.na == 32 && sl.nb == 32);
+    uint64_t *rec = nullptr;
+    TRY(ws_t(ctx, "pt2_rec", (size_t)4 * std::max<int64_t>(n, 1), &rec));
+    launch_pt2_records(st, conn->dets, psi, n, packed, rec);
+    CHECK_LAUNCH(ctx);
     // key-space slices: 8-byte descriptors are held twice (L1 and L2 order)
     int64_t budget = o.max_pair_bytes;
     if (budget <= 0) {

@@ -171,7 +171,7 @@ void launch_diag_table(hipStream_t st, const Ham &H, double *vt);
 // place into skeys at offs[sub] + cursor (cnt used as cursors)
 void launch_s_sub(hipStream_t st, const uint64_t *dets, int64_t n, int sbits, bool packed, int32_t *cnt,
                   const int64_t *offs, uint64_t *skeys, bool fill, int ss, uint32_t slice);
-// rec: per determinant of S {alpha, beta, bits of psi_x, 0} (launch_pt2_records)
+// rec: the source records of launch_pt2_records (same packed flag)
 void launch_pt2_reduce(hipStream_t st, const Ham &H, const uint64_t *rec, const uint64_t *desc,
                        const int64_t *sb, int64_t nsb, const uint64_t *skeys, const int64_t *soffs, int64_t n_s,
                        const double *vt, const double *energy, uint64_t sample_mask, const PT2Export &ex, double *part,
@@ -185,7 +185,10 @@ void launch_pt2_internal(hipStream_t st, const double *psi, const double *v, con
 void launch_pt2_init_acc(hipStream_t st, double *acc);
 // acc += part (sum, min, counts): a finished key-space slice into the external total
 void launch_pt2_merge(hipStream_t st, double *acc, const double *part);
-void launch_pt2_records(hipStream_t st, const uint64_t *dets, const double *psi, int64_t n, uint64_t *rec);
+// per determinant of S: {alpha | beta << 32, psi bits} when packed (M <= 32), else
+// {alpha, beta, psi bits, 0}; rec holds 4 n words
+void launch_pt2_records(hipStream_t st, const uint64_t *dets, const double *psi, int64_t n, bool packed,
+                        uint64_t *rec);
 void launch_pt2_final(hipStream_t st, const double *acc_int, const double *acc_ext, const double *stats,
                       double *out, int64_t *counts, int64_t pairs, int64_t passes);
 

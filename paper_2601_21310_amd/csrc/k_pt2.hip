@@ -153,21 +153,31 @@ void launch_pt2_merge(hipStream_t st, double *acc, const double *part) {
     hipLaunchKernelGGL(k_pt2_merge, dim3(1), dim3(1), 0, st, acc, part);
 }
 
-// rec[x] = {alpha, beta, bits of psi_x, 0}: the reduce's per-pair gather of the source
-// determinant and its amplitude touches one 32-byte record, one cache line
+// Source records of the reduce's per-pair gather, one cache line each: for M <= 32
+// (packed) rec[2x .. 2x+1] = {alpha | beta << 32, bits of psi_x} (16 bytes: with the
+// integrals the table stays resident in each XCD's L2), else rec[4x .. 4x+3] = {alpha,
+// beta, bits of psi_x, 0}.
 __global__ void k_pt2_records(const uint64_t *__restrict__ dets, const double *__restrict__ psi, int64_t n,
-                              uint64_t *__restrict__ rec) {
+                              bool packed, uint64_t *__restrict__ rec) {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
-    rec[4 * x + 0] = dets[2 * x];
-    rec[4 * x + 1] = dets[2 * x + 1];
-    rec[4 * x + 2] = (uint64_t)__double_as_longlong(psi[x]);
-    rec[4 * x + 3] = 0ull;
+    const uint64_t pb = (uint64_t)__double_as_longlong(psi[x]);
+    if (packed) {
+        rec[2 * x + 0] = dets[2 * x] | (dets[2 * x + 1] << 32);
+        rec[2 * x + 1] = pb;
+    } else {
+        rec[4 * x + 0] = dets[2 * x];
+        rec[4 * x + 1] = dets[2 * x + 1];
+        rec[4 * x + 2] = pb;
+        rec[4 * x + 3] = 0ull;
+    }
 }
 
-void launch_pt2_records(hipStream_t st, const uint64_t *dets, const double *psi, int64_t n, uint64_t *rec) {
+void launch_pt2_records(hipStream_t st, const uint64_t *dets, const double *psi, int64_t n, bool packed,
+                        uint64_t *rec) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_pt2_records, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dets, psi, n, rec);
+    hipLaunchKernelGGL(k_pt2_records, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dets, psi, n, packed,
+                       rec);
 }
 
 // out = {(int + ext)/norm, int, ext, min den}; counts[1] = |P|, counts[2] = tiny

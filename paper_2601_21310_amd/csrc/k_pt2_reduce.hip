@@ -288,8 +288,16 @@ struct SrcRec {
     uint64_t p;   // bits of psi_x
 };
 
+// Records are 16 bytes when M <= 32 ({alpha | beta << 32, bits of psi_x}: the table stays
+// resident in each XCD's L2 next to the integrals) and 32 bytes otherwise ({alpha, beta,
+// bits of psi_x, 0}); see launch_pt2_records.
+template <bool PACKED>
 __device__ __forceinline__ SrcRec load_src(const uint64_t *__restrict__ rec, uint64_t d) {
     const int64_t x = desc_x(d);
+    if (PACKED) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(rec + 2 * x);
+        return SrcRec{make_uint4(v.x, 0u, v.y, 0u), ((uint64_t)v.w << 32) | v.z};
+    }
     return SrcRec{*reinterpret_cast<const uint4 *>(rec + 4 * x), rec[4 * x + 2]};
 }
 
@@ -506,13 +514,13 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
         const int64_t base = s0 + threadIdx.x;
         auto ld_desc = [&](int64_t k) { return desc[min(base + k * step, s1 - 1)]; };
         uint64_t D0 = ld_desc(0), D1 = ld_desc(1), D2 = ld_desc(2), D3 = ld_desc(3);
-        SrcRec R0 = load_src(rec, D0), R1{};
+        SrcRec R0 = load_src<PACKED>(rec, D0), R1{};
         // pair k: descriptor Dk, record Rk; loads the record of pair k + 1 (from Dn) into
         // Rn and the descriptor of pair k + 4 into Dk
         auto stage = [&](int64_t k, uint64_t &Dk, const SrcRec &Rk, const uint64_t &Dn, SrcRec &Rn) {
             const uint64_t d = Dk;
             const PairVal pv = double_value<PACKED>(H, Rk, d);
-            Rn = load_src(rec, Dn);
+            Rn = load_src<PACKED>(rec, Dn);
             Dk = ld_desc(k + 4);
             if (base + k * step < s1) {
                 if (is_single(d)) {
@@ -538,7 +546,7 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
             const bool have = k < nsq;
             PairVal pv{};
             double part_v = 0.0;
-            if (have) pv = single_part<PACKED>(H, load_src(rec, sq[k]), sq[k], l, part_v);
+            if (have) pv = single_part<PACKED>(H, load_src<PACKED>(rec, sq[k]), sq[k], l, part_v);
             part_v += __shfl_xor(part_v, 1, 8);
             part_v += __shfl_xor(part_v, 2, 8);
             part_v += __shfl_xor(part_v, 4, 8);
@@ -550,7 +558,7 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
     } else {
         for (int64_t i = s0 + threadIdx.x; i < s1; i += step) {
             const uint64_t d = desc[i];
-            if (is_single(d) && !red_add<PACKED>(single_pair<PACKED>(H, load_src(rec, d), d), ka_t, kb_t, w_t))
+            if (is_single(d) && !red_add<PACKED>(single_pair<PACKED>(H, load_src<PACKED>(rec, d), d), ka_t, kb_t, w_t))
                 lost = true;
         }
     }
