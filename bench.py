@@ -218,8 +218,8 @@ def bench_curve(args, dnqs, synth, torch):
 # source they were taken on (profiles/pt2_m28_s1e5_hbm_counters.md).
 MEASURED_TRAFFIC = {
     ("k_pt2_reduce", "m28_7a7b_s100k"): ("paper_2601_21310_amd/csrc/k_pt2_reduce.hip",
-                                          "28f6c412fc2e5f99322845ce8d71b89305926090a9db1e43f86fbed3ccda350f",
-                                          27953532232.1),
+                                          "866a68f21161680241ac03a3bdb1291370fff1f187f1dffff41916bf2c8d4426",
+                                          24871166043.5),
 }
 
 
