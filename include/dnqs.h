@@ -125,6 +125,11 @@ dnqs_status dnqs_build_connections(dnqs_ctx *ctx, int slot, const uint64_t *dets
                                    dnqs_conn **out);
 /* n_dets, nnz (off-diagonal) of a connection object (host outputs, either may be NULL). */
 dnqs_status dnqs_conn_info(const dnqs_conn *conn, int64_t *n_dets, int64_t *nnz);
+/* The occupied-row plan of the output layer kept with the connections (see
+ * dnqs_energy_and_grad): n_dense = orbitals computed densely, or -1 when the full-width
+ * layer is used; n_entries = (configuration, other occupied orbital) rows.  Host
+ * outputs, either may be NULL. */
+dnqs_status dnqs_conn_output_plan(const dnqs_conn *conn, int *n_dense, int64_t *n_entries);
 /* Copy H_SS into caller buffers (dev): row_ptr[n+1], col[nnz], val[nnz], diag[n];
  * any pointer may be NULL to skip it.  Enqueued on the context's stream. */
 dnqs_status dnqs_conn_export(dnqs_ctx *ctx, const dnqs_conn *conn, int64_t *row_ptr, int32_t *col, float *val,
@@ -147,7 +152,14 @@ dnqs_status dnqs_amplitudes(dnqs_ctx *ctx, int slot, const dnqs_net *net, const 
  * Outputs (dev): energy FP64[1]; stats FP64[3] = {psi^T psi, l_max, psi^T v};
  * grad FP32[param_count] (NULL: no backward pass); v_out FP64[n] (NULL: not kept);
  * log_abs FP64[n] and sign int8[n] (NULL: not kept).  E is NaN and the call still
- * succeeds if psi^T psi underflows; grad is then zero.  Enqueued, does not wait. */
+ * succeeds if psi^T psi underflows; grad is then zero.  Enqueued, does not wait.
+ * The orbital output layer is computed for the occupied rows only where that pays:
+ * when S is concentrated on some orbitals (as a set grown around a reference is), the
+ * orbitals occupied in >= 35% of S take a dense GEMM and every other occupied row is
+ * computed per configuration (the plan is built by dnqs_build_connections).  Results
+ * equal the full-width layer up to FP32 summation order.  flags: DNQS_FULL_OUTPUT
+ * forces the full-width layer (as in the batched call). */
+#define DNQS_FULL_OUTPUT 1u
 dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, const float *theta,
                                  const dnqs_conn *conn, int precision, unsigned flags, double *energy,
                                  double *stats, float *grad, double *v_out, double *log_abs, int8_t *sign);

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libdnqs.so")
 MAX_LAYERS = 8
 FP32, MIXED, SPLIT_BF16 = 0, 1, 2
 VALIDATE = 1
+FULL_OUTPUT = 1
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ECAPACITY", -5: "ESTATE", -6: "EDOMAIN"}
 
@@ -82,6 +83,7 @@ def lib():
         L.dnqs_set_integrals.argtypes = [vp, i32, i32, i32, i32, vp, vp, dbl]
         L.dnqs_build_connections.argtypes = [vp, i32, vp, i64, C.c_uint, C.POINTER(vp)]
         L.dnqs_conn_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
+        L.dnqs_conn_output_plan.argtypes = [vp, C.POINTER(i32), C.POINTER(i64)]
         L.dnqs_conn_export.argtypes = [vp, vp, vp, vp, vp, vp]
         L.dnqs_conn_free.argtypes = [vp]
         L.dnqs_conn_free.restype = None
@@ -103,7 +105,7 @@ def lib():
         L.dnqs_tune_export.restype = i64
         L.dnqs_tune_import.argtypes = [vp, C.c_char_p]
         for fn in ("dnqs_create", "dnqs_set_stream", "dnqs_set_integrals", "dnqs_build_connections",
-                   "dnqs_conn_info", "dnqs_conn_export", "dnqs_amplitudes", "dnqs_energy_and_grad", "dnqs_pt2",
+                   "dnqs_conn_info", "dnqs_conn_output_plan", "dnqs_conn_export", "dnqs_amplitudes", "dnqs_energy_and_grad", "dnqs_pt2",
                    "dnqs_energy_and_grad_batched", "dnqs_adamw_batched", "dnqs_capture_begin", "dnqs_capture_end",
                    "dnqs_graph_launch", "dnqs_timing_enable", "dnqs_timing_reset", "dnqs_timing_get",
                    "dnqs_autotune", "dnqs_tune_import"):
@@ -139,6 +141,12 @@ class Connections:
         n, nnz = C.c_int64(), C.c_int64()
         lib().dnqs_conn_info(handle, C.byref(n), C.byref(nnz))
         self.n, self.nnz = n.value, nnz.value
+
+    def output_plan(self):
+        """(dense orbitals or -1 when the full-width output layer is used, sparse rows)."""
+        nd, ne = C.c_int32(), C.c_int64()
+        lib().dnqs_conn_output_plan(self.handle, C.byref(nd), C.byref(ne))
+        return nd.value, ne.value
 
     def export(self):
         """(row_ptr int64, col int32, val float32, diag float64) as CUDA tensors."""
@@ -237,7 +245,8 @@ class Context:
                                           _ptr(la), _ptr(sg)))
         return la, sg
 
-    def energy_and_grad(self, widths, theta, conn: Connections, want_grad=True, precision=FP32, keep=True):
+    def energy_and_grad(self, widths, theta, conn: Connections, want_grad=True, precision=FP32, keep=True,
+                        full_output=False):
         theta = _dev_tensor(theta, torch.float32, "theta", self.device)
         if theta.numel() != self.param_count(widths, conn.slot):
             raise ValueError("theta has the wrong size for this network")
@@ -251,8 +260,8 @@ class Context:
         sg = torch.empty(n, dtype=torch.int8, device=dev) if keep else None
         net = Net.from_widths(widths)
         self._check(lib().dnqs_energy_and_grad(self.handle, conn.slot, C.byref(net), _ptr(theta), conn.handle,
-                                               precision, 0, _ptr(E), _ptr(stats), _ptr(grad), _ptr(v), _ptr(la),
-                                               _ptr(sg)))
+                                               precision, FULL_OUTPUT if full_output else 0, _ptr(E), _ptr(stats),
+                                               _ptr(grad), _ptr(v), _ptr(la), _ptr(sg)))
         return {"E": E, "stats": stats, "grad": grad, "v": v, "logabs": la, "sign": sg}
 
     def pt2(self, conn: Connections, logabs, sign, energy, sample_mask=0, export_cap=0, max_pair_bytes=0):

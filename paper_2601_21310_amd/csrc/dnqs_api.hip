@@ -118,6 +118,12 @@ struct dnqs_conn {
     uint64_t *set_keys = nullptr;
     int32_t *set_idx = nullptr;
     uint64_t set_mask = 0;
+    // occupied-row plan of the orbital output layer (k_outsplit.hip); os_nd < 0: not used
+    int os_nd = -1;
+    int64_t os_ne = 0, os_ntiles = 0, os_nitems = 0;
+    int *os_dpos = nullptr, *os_dorb = nullptr, *os_ifirst = nullptr, *os_icount = nullptr;
+    int32_t *os_ex = nullptr, *os_ej = nullptr, *os_idx = nullptr;
+    int4 *os_tiles = nullptr, *os_items = nullptr;
 };
 
 namespace {
@@ -383,8 +389,11 @@ bool precision_ok(int p) { return p == DNQS_FP32 || p == DNQS_MIXED || p == DNQS
 
 // Forward pass: activations h_1..h_{L-1} kept in workspaces "h1".. (FP32), output layer
 // in "O" (FP32), then orbital rows + LU.  With want_grad also U (occupations) and A^-1.
+// With a connections object that carries an occupied-row plan, the output layer is
+// computed in that form ("O" then holds the dense orbitals' columns, "os_Osp" the entries).
 dnqs_status forward(dnqs_ctx *ctx, const Slot &sl, const NetView &nv, const float *theta, const uint64_t *dets,
-                    int64_t n, int precision, bool want_grad, double *logabs, int8_t *sign, float **Ainv_out) {
+                    int64_t n, int precision, bool want_grad, double *logabs, int8_t *sign, float **Ainv_out,
+                    const dnqs_conn *conn = nullptr) {
     hipStream_t st = ctx->stream;
     const size_t esz = sizeof(float);
     const int M = sl.M, No = 2 * M, Ne = sl.na + sl.nb, L = nv.L;
@@ -396,7 +405,51 @@ dnqs_status forward(dnqs_ctx *ctx, const Slot &sl, const NetView &nv, const floa
     launch_embed(st, dets, n, M, w[1], theta + nv.offW[1], theta + nv.offb[1], (float *)h, (float *)U);
     CHECK_LAUNCH(ctx);
     void *prev = h;
+    OutSplit os{};
+    const bool split = conn && conn->os_nd >= 0 && L >= 2;
     for (int l = 2; l <= L; ++l) {
+        if (l == L && split) {
+            const int nd = conn->os_nd, wd = nd * Ne, din = w[L - 1];
+            float *WD = nullptr, *OD = nullptr, *Osp = nullptr;
+            TRY(ws_t(ctx, "os_WD", (size_t)(din + 1) * std::max(wd, 1), &WD));
+            TRY(ws_t(ctx, "O", (size_t)n * std::max(wd, 1), &OD));
+            TRY(ws_t(ctx, "os_Osp", (size_t)std::max<int64_t>(conn->os_ne, 1) * Ne, &Osp));
+            launch_os_gather_w(st, theta + nv.offW[L], theta + nv.offb[L], din, w[L], Ne, nd, conn->os_dorb, WD);
+            CHECK_LAUNCH(ctx);
+            if (nd > 0) {
+                GemmArgs g{};
+                g.M = (int)n;
+                g.N = wd;
+                g.K = din;
+                g.A = prev;
+                g.lda = din;
+                g.B = WD;
+                g.ldb = wd;
+                g.C = OD;
+                g.ldc = wd;
+                g.bias = WD + (int64_t)din * wd;
+                g.ones_row = -1;
+                const int eng = gemm_engine(precision, true);
+                if (eng == 1) TRY(weight_planes(ctx, "wpTO", WD, din, wd, true, g));
+                TRY(tuned_launch(ctx, TuneKey{eng, 0, g.M, g.N, g.K}, gemm_candidates(g.M, g.N, g.K, false, false),
+                                 [&](const GemmCfg &c) -> dnqs_status {
+                                     launch_gemm(eng, st, g, true, true, EPI_BIAS, 1, c.tm);
+                                     CHECK_LAUNCH(ctx);
+                                     return DNQS_OK;
+                                 }));
+            }
+            launch_os_fwd(st, (const float *)prev, din, theta + nv.offW[L], theta + nv.offb[L], w[L], Ne,
+                          conn->os_tiles, conn->os_ntiles, conn->os_ex, Osp);
+            CHECK_LAUNCH(ctx);
+            os.OD = OD;
+            os.Osp = Osp;
+            os.dpos = conn->os_dpos;
+            os.dorb = conn->os_dorb;
+            os.idx = conn->os_idx;
+            os.nd = nd;
+            prev = nullptr;
+            break;
+        }
         void *out = nullptr;
         if (l < L)
             TRY(ws_get(ctx, "h" + std::to_string(l), (size_t)n * w[l] * esz, &out));
@@ -427,7 +480,8 @@ dnqs_status forward(dnqs_ctx *ctx, const Slot &sl, const NetView &nv, const floa
     }
     float *Ainv = nullptr;
     if (want_grad) TRY(ws_t(ctx, "Ainv", (size_t)n * Ne * Ne, &Ainv));
-    launch_orb_lu(st, dets, n, M, sl.na, sl.nb, (const float *)prev, theta + nv.offPhi0, logabs, sign, Ainv);
+    launch_orb_lu(st, dets, n, M, sl.na, sl.nb, (const float *)prev, theta + nv.offPhi0, logabs, sign, Ainv, {}, 0,
+                  os);
     CHECK_LAUNCH(ctx);
     if (Ainv_out) *Ainv_out = Ainv;
     return DNQS_OK;
@@ -445,6 +499,80 @@ dnqs_status validate_dets_dev(dnqs_ctx *ctx, const Slot &sl, const uint64_t *det
     if (h & 1) return fail(ctx, DNQS_EINVAL, "a determinant has the wrong electron count for the slot's sector");
     if (h & 4) return fail(ctx, DNQS_EINVAL, "a determinant has bits set at or above M");
     if (h & 2) return fail(ctx, DNQS_EINVAL, "determinants are not in strictly ascending canonical order");
+    return DNQS_OK;
+}
+
+// Occupied-row plan of the output layer for the configurations of c: the spin-orbitals
+// occupied in at least 35% of S take the dense GEMM, the others one entry per occupied
+// (configuration, orbital).  Used when it saves at least a fifth of the layer's work
+// (a sparse entry costs about three dense rows); else os_nd stays -1.
+dnqs_status os_plan(dnqs_ctx *ctx, dnqs_conn *c) {
+    hipStream_t st = ctx->stream;
+    const int M = c->M, No = 2 * M, Ne = c->na + c->nb;
+    const int64_t n = c->n;
+    unsigned long long *cnt_d = nullptr;
+    TRY(ws_t(ctx, "os_cnt", (size_t)No, &cnt_d));
+    HIPCHK(ctx, hipMemsetAsync(cnt_d, 0, sizeof(unsigned long long) * No, st));
+    launch_os_count(st, c->dets, n, M, cnt_d);
+    CHECK_LAUNCH(ctx);
+    std::vector<unsigned long long> cnt(No);
+    HIPCHK(ctx, hipMemcpyAsync(cnt.data(), cnt_d, sizeof(unsigned long long) * No, hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    std::vector<int> dpos(No, -1), dorb(No, 0), ifirst(No, 0), icount(No, 0);
+    std::vector<int64_t> eoff(No + 1, 0);
+    int nd = 0;
+    for (int p = 0; p < No; ++p)
+        if ((double)cnt[p] >= 0.35 * (double)n) {
+            dpos[p] = nd;
+            dorb[nd++] = p;
+        }
+    for (int p = 0; p < No; ++p) eoff[p + 1] = eoff[p] + (dpos[p] < 0 ? (int64_t)cnt[p] : 0);
+    const int64_t E = eoff[No];
+    if (nd == No || (double)nd * n + 3.0 * (double)E > 0.8 * (double)No * n) return DNQS_OK;
+    std::vector<int4> tiles, items;
+    for (int p = 0; p < No; ++p) {
+        if (dpos[p] >= 0) continue;
+        for (int64_t e = eoff[p]; e < eoff[p + 1]; e += os_tile())
+            tiles.push_back(make_int4(p, (int)e, (int)std::min<int64_t>(os_tile(), eoff[p + 1] - e), 0));
+        ifirst[p] = (int)items.size();
+        for (int64_t e = eoff[p]; e < eoff[p + 1]; e += os_item())
+            items.push_back(make_int4(p, (int)e, (int)std::min<int64_t>(os_item(), eoff[p + 1] - e), 0));
+        icount[p] = (int)items.size() - ifirst[p];
+    }
+    auto dalloc = [&](void **ptr, size_t bytes) -> dnqs_status {
+        HIPCHK(ctx, hipMalloc(ptr, bytes > 0 ? bytes : 16));
+        return DNQS_OK;
+    };
+    TRY(dalloc((void **)&c->os_dpos, sizeof(int) * No));
+    TRY(dalloc((void **)&c->os_dorb, sizeof(int) * No));
+    TRY(dalloc((void **)&c->os_ifirst, sizeof(int) * No));
+    TRY(dalloc((void **)&c->os_icount, sizeof(int) * No));
+    TRY(dalloc((void **)&c->os_ex, sizeof(int32_t) * E));
+    TRY(dalloc((void **)&c->os_ej, sizeof(int32_t) * E));
+    TRY(dalloc((void **)&c->os_idx, sizeof(int32_t) * n * Ne));
+    TRY(dalloc((void **)&c->os_tiles, sizeof(int4) * tiles.size()));
+    TRY(dalloc((void **)&c->os_items, sizeof(int4) * items.size()));
+    int64_t *eoff_d = nullptr, *boff = nullptr;
+    int *bcnt = nullptr;
+    TRY(ws_t(ctx, "os_eoff", (size_t)No + 1, &eoff_d));
+    TRY(ws_t(ctx, "os_bcnt", (size_t)os_blocks(n) * No, &bcnt));
+    TRY(ws_t(ctx, "os_boff", (size_t)os_blocks(n) * No, &boff));
+    HIPCHK(ctx, hipMemcpyAsync(c->os_dpos, dpos.data(), sizeof(int) * No, hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(c->os_dorb, dorb.data(), sizeof(int) * No, hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(c->os_ifirst, ifirst.data(), sizeof(int) * No, hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(c->os_icount, icount.data(), sizeof(int) * No, hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(eoff_d, eoff.data(), sizeof(int64_t) * (No + 1), hipMemcpyHostToDevice, st));
+    if (!tiles.empty())
+        HIPCHK(ctx, hipMemcpyAsync(c->os_tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, st));
+    if (!items.empty())
+        HIPCHK(ctx, hipMemcpyAsync(c->os_items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, st));
+    launch_os_build(st, c->dets, n, M, c->na, Ne, c->os_dpos, eoff_d, bcnt, boff, c->os_ex, c->os_ej, c->os_idx);
+    CHECK_LAUNCH(ctx);
+    HIPCHK(ctx, hipStreamSynchronize(st));  // the host vectors are read by the copies above
+    c->os_nd = nd;
+    c->os_ne = E;
+    c->os_ntiles = (int64_t)tiles.size();
+    c->os_nitems = (int64_t)items.size();
     return DNQS_OK;
 }
 
@@ -584,6 +712,9 @@ void dnqs_conn_free(dnqs_conn *c) {
     (void)hipFree(c->diag);
     (void)hipFree(c->set_keys);
     (void)hipFree(c->set_idx);
+    for (void *q : {(void *)c->os_dpos, (void *)c->os_dorb, (void *)c->os_ifirst, (void *)c->os_icount,
+                    (void *)c->os_ex, (void *)c->os_ej, (void *)c->os_idx, (void *)c->os_tiles, (void *)c->os_items})
+        if (q) (void)hipFree(q);
     delete c;
 }
 
@@ -658,6 +789,7 @@ dnqs_status dnqs_build_connections(dnqs_ctx *ctx, int slot, const uint64_t *dets
     CHK_C(hipGetLastError());
     launch_row_ptr(st, offs, n, nsub, nnz, c->row_ptr);
     CHK_C(hipGetLastError());
+    if ((s = os_plan(ctx, c)) != DNQS_OK) return cleanup(s);
     tm.stop();
     CHK_C(hipStreamSynchronize(st));
 #undef CHK_C
@@ -669,6 +801,13 @@ dnqs_status dnqs_conn_info(const dnqs_conn *conn, int64_t *n_dets, int64_t *nnz)
     if (!conn) return DNQS_EINVAL;
     if (n_dets) *n_dets = conn->n;
     if (nnz) *nnz = conn->nnz;
+    return DNQS_OK;
+}
+
+dnqs_status dnqs_conn_output_plan(const dnqs_conn *conn, int *n_dense, int64_t *n_entries) {
+    if (!conn) return DNQS_EINVAL;
+    if (n_dense) *n_dense = conn->os_nd;
+    if (n_entries) *n_entries = conn->os_nd >= 0 ? conn->os_ne : 0;
     return DNQS_OK;
 }
 
@@ -706,8 +845,8 @@ dnqs_status dnqs_amplitudes(dnqs_ctx *ctx, int slot, const dnqs_net *net, const 
 dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, const float *theta,
                                  const dnqs_conn *conn, int precision, unsigned flags, double *energy,
                                  double *stats, float *grad, double *v_out, double *log_abs, int8_t *sign) {
-    (void)flags;
     if (!ctx) return DNQS_EINVAL;
+    if (flags & ~DNQS_FULL_OUTPUT) return fail(ctx, DNQS_EINVAL, "unknown flags 0x%x", flags);
     TRY(check_slot(ctx, slot));
     const Slot &sl = ctx->slots[slot];
     NetView nv;
@@ -730,7 +869,8 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
     if (!sg) TRY(ws_t(ctx, "sign", (size_t)n, &sg));
     float *Ainv = nullptr;
     const bool want_grad = grad != nullptr;
-    TRY(forward(ctx, sl, nv, theta, conn->dets, n, precision, want_grad, la, sg, &Ainv));
+    const bool full_out = (flags & DNQS_FULL_OUTPUT) != 0;
+    TRY(forward(ctx, sl, nv, theta, conn->dets, n, precision, want_grad, la, sg, &Ainv, full_out ? nullptr : conn));
     double *psi = nullptr, *v = v_out, *part = nullptr, *part2 = nullptr;
     TRY(ws_t(ctx, "psi", (size_t)n, &psi));
     if (!v) TRY(ws_t(ctx, "v", (size_t)n, &v));
@@ -743,8 +883,26 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
     if (!want_grad) return DNQS_OK;
     // adjoint: dO, then layer by layer
     float *dO = nullptr;
-    TRY(ws_t(ctx, "dO", (size_t)n * w[L], &dO));
-    launch_det_bwd(st, conn->dets, n, M, sl.na, sl.nb, psi, v, energy, stats, Ainv, dO);
+    const bool split = !full_out && conn->os_nd >= 0 && L >= 2;
+    const int nd = split ? conn->os_nd : 0, wd = nd * Ne;
+    OutSplit og{};
+    if (split) {
+        // full-width dO for the data gradient, and the split layout for the weight gradient
+        float *dOsp = nullptr, *dOD = nullptr;
+        TRY(ws_t(ctx, "dO", (size_t)n * w[L], &dO));
+        TRY(ws_t(ctx, "os_dOD", (size_t)n * std::max(wd, 1), &dOD));
+        TRY(ws_t(ctx, "os_dOsp", (size_t)std::max<int64_t>(conn->os_ne, 1) * Ne, &dOsp));
+        og.dOD = dOD;
+        og.dOsp = dOsp;
+        og.dpos = conn->os_dpos;
+        og.dorb = conn->os_dorb;
+        og.idx = conn->os_idx;
+        og.nd = nd;
+        launch_det_bwd(st, conn->dets, n, M, sl.na, sl.nb, psi, v, energy, stats, Ainv, dO, {}, og);
+    } else {
+        TRY(ws_t(ctx, "dO", (size_t)n * w[L], &dO));
+        launch_det_bwd(st, conn->dets, n, M, sl.na, sl.nb, psi, v, energy, stats, Ainv, dO);
+    }
     CHECK_LAUNCH(ctx);
     const size_t esz = sizeof(float);
     int maxw = 0;
@@ -759,31 +917,73 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
         void *hp = nullptr;
         TRY(ws_get(ctx, l == 1 ? std::string("U") : "h" + std::to_string(l - 1), 1, &hp));
         const int din = w[l - 1], dout = w[l];
-        GemmArgs g{};
-        g.M = din + 1;
-        g.N = dout;
-        g.K = (int)n;
-        g.A = hp;
-        g.lda = din;
-        g.B = delta;
-        g.ldb = dout;
-        g.ldc = dout;
-        g.ones_row = din;
-        const int64_t cnt = (int64_t)(din + 1) * dout;
-        const int eng = gemm_engine(precision, l == L);
-        TRY(tuned_launch(ctx, TuneKey{eng, 1, g.M, g.N, g.K}, gemm_candidates(g.M, g.N, g.K, true, false),
-                         [&](const GemmCfg &c) -> dnqs_status {
-                             float *partial = nullptr;
-                             TRY(ws_t(ctx, "splitk", (size_t)cnt * c.splits, &partial));
-                             GemmArgs gs = g;
-                             gs.C = partial;
-                             gs.c_split_stride = cnt;
-                             launch_gemm(eng, st, gs, false, true, EPI_STORE, c.splits, c.tm);
-                             CHECK_LAUNCH(ctx);
-                             launch_reduce_splits(st, partial, c.splits, cnt, grad + nv.offW[l]);
-                             CHECK_LAUNCH(ctx);
-                             return DNQS_OK;
-                         }));
+        if (l == L && split) {
+            // occupied-row output layer, weight gradient: the dense columns by GEMM
+            // (scattered into place), the sparse orbitals over their entries
+            const int eng = gemm_engine(precision, true);
+            if (nd > 0) {
+                float *GD = nullptr;
+                TRY(ws_t(ctx, "os_GD", (size_t)(din + 1) * wd, &GD));
+                GemmArgs g{};
+                g.M = din + 1;
+                g.N = wd;
+                g.K = (int)n;
+                g.A = hp;
+                g.lda = din;
+                g.B = og.dOD;
+                g.ldb = wd;
+                g.ldc = wd;
+                g.ones_row = din;
+                const int64_t cnt = (int64_t)(din + 1) * wd;
+                TRY(tuned_launch(ctx, TuneKey{eng, 1, g.M, g.N, g.K}, gemm_candidates(g.M, g.N, g.K, true, false),
+                                 [&](const GemmCfg &c) -> dnqs_status {
+                                     float *partial = nullptr;
+                                     TRY(ws_t(ctx, "splitk", (size_t)cnt * c.splits, &partial));
+                                     GemmArgs gs = g;
+                                     gs.C = partial;
+                                     gs.c_split_stride = cnt;
+                                     launch_gemm(eng, st, gs, false, true, EPI_STORE, c.splits, c.tm);
+                                     CHECK_LAUNCH(ctx);
+                                     launch_reduce_splits(st, partial, c.splits, cnt, GD);
+                                     CHECK_LAUNCH(ctx);
+                                     return DNQS_OK;
+                                 }));
+                launch_os_scatter(st, GD, din, Ne, nd, dout, conn->os_dorb, grad + nv.offW[l]);
+                CHECK_LAUNCH(ctx);
+            }
+            float *part_w = nullptr;
+            TRY(ws_t(ctx, "os_wpart", (size_t)std::max<int64_t>(conn->os_nitems, 1) * (din + 1) * Ne, &part_w));
+            launch_os_wgrad(st, (const float *)hp, din, Ne, conn->os_items, conn->os_nitems, conn->os_ex, og.dOsp,
+                            part_w, conn->os_dpos, conn->os_ifirst, conn->os_icount, No, grad + nv.offW[l]);
+            CHECK_LAUNCH(ctx);
+        }
+        if (!(l == L && split)) {
+            GemmArgs g{};
+            g.M = din + 1;
+            g.N = dout;
+            g.K = (int)n;
+            g.A = hp;
+            g.lda = din;
+            g.B = delta;
+            g.ldb = dout;
+            g.ldc = dout;
+            g.ones_row = din;
+            const int64_t cnt = (int64_t)(din + 1) * dout;
+            const int eng = gemm_engine(precision, l == L);
+            TRY(tuned_launch(ctx, TuneKey{eng, 1, g.M, g.N, g.K}, gemm_candidates(g.M, g.N, g.K, true, false),
+                             [&](const GemmCfg &c) -> dnqs_status {
+                                 float *partial = nullptr;
+                                 TRY(ws_t(ctx, "splitk", (size_t)cnt * c.splits, &partial));
+                                 GemmArgs gs = g;
+                                 gs.C = partial;
+                                 gs.c_split_stride = cnt;
+                                 launch_gemm(eng, st, gs, false, true, EPI_STORE, c.splits, c.tm);
+                                 CHECK_LAUNCH(ctx);
+                                 launch_reduce_splits(st, partial, c.splits, cnt, grad + nv.offW[l]);
+                                 CHECK_LAUNCH(ctx);
+                                 return DNQS_OK;
+                             }));
+        }
         if (l == 1) break;
         // delta_{l-1} = (delta_l W_l^T) * (1 - h_{l-1}^2)
         void *dnext = dbuf[which];

@@ -92,12 +92,43 @@ void launch_gemm_x3(hipStream_t st, const GemmArgs &g, bool a_kcontig, bool b_nc
 void launch_split_planes(hipStream_t st, const float *W, int R, int C, bool transpose, void *planes);
 void launch_reduce_splits(hipStream_t st, const float *part, int splits, int64_t count, float *out);
 int orb_lu_group(int ne);
+// Output layer in the occupied-row form (k_outsplit.hip): the dense orbitals' column
+// blocks in OD (ldd = nd * Ne per configuration, orbital p at dpos[p] * Ne), every other
+// occupied row j of A(x) as entry e = idx[x * Ne + j] with its Ne values at Osp[e * Ne].
+// In the backward, dOD / dOsp take the same layout (dorb lists the dense orbitals), and
+// the full-width dO is written as well when given (the data gradient uses it).
+struct OutSplit {
+    const float *OD = nullptr;
+    const float *Osp = nullptr;
+    float *dOD = nullptr;
+    float *dOsp = nullptr;
+    const int *dpos = nullptr;
+    const int *dorb = nullptr;
+    const int32_t *idx = nullptr;
+    int nd = 0;
+};
 void launch_orb_lu(hipStream_t st, const uint64_t *dets, int64_t n, int M, int na, int nb, const float *O,
                    const float *Phi0, double *logabs, int8_t *sign, float *Ainv, RowProblems rp = {},
-                   int64_t offPhi0 = 0);
+                   int64_t offPhi0 = 0, OutSplit os = {});
 void launch_det_bwd(hipStream_t st, const uint64_t *dets, int64_t n, int M, int na, int nb, const double *psi,
                     const double *v, const double *energy, const double *stats, const float *Ainv, float *dO,
-                    RowProblems rp = {});
+                    RowProblems rp = {}, OutSplit os = {});
+// occupied-row output layer (k_outsplit.hip)
+void launch_os_count(hipStream_t st, const uint64_t *dets, int64_t n, int M, unsigned long long *cnt);
+int64_t os_blocks(int64_t n);
+void launch_os_build(hipStream_t st, const uint64_t *dets, int64_t n, int M, int na, int Ne, const int *dpos,
+                     const int64_t *eoff, int *bcnt, int64_t *boff, int32_t *ex, int32_t *ej, int32_t *idx);
+void launch_os_gather_w(hipStream_t st, const float *W, const float *bias, int din, int width, int Ne, int nd,
+                        const int *dorb, float *WD);
+int os_tile();
+int os_item();  // entries per weight-gradient work item (at most)
+void launch_os_fwd(hipStream_t st, const float *hL, int din, const float *W, const float *bias, int width, int Ne,
+                   const int4 *tiles, int64_t ntiles, const int32_t *ex, float *Osp);
+void launch_os_wgrad(hipStream_t st, const float *hL, int din, int Ne, const int4 *items, int64_t nitems,
+                     const int32_t *ex, const float *dOsp, float *part, const int *dpos, const int *ifirst,
+                     const int *icount, int No, float *grad);
+void launch_os_scatter(hipStream_t st, const float *GD, int din, int Ne, int nd, int width, const int *dorb,
+                       float *grad);
 void launch_copy_f32(hipStream_t st, const float *x, float *y, int64_t n);
 
 // ---------------------------------------------------------------- batched problems, optimiser

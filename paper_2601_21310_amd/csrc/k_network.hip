@@ -7,6 +7,7 @@
 //               row per lane, log|det| in FP64, sign, and A^-1 for the adjoint
 //   k_det_bwd   dL/dO[x, p*Ne+k] = c_x (A_x^-T)[j,k] for p = i_j, 0 elsewhere,
 //               c_x = 2 (v_x - E psi_x) psi_x / psi^T psi            (Eq. 12)
+//   (both also take the occupied-row layout of the output layer, k_outsplit.hip)
 #include "dnqs_device.h"
 #include "dnqs_kernels.h"
 
@@ -327,7 +328,8 @@ template <int G>
 __global__ __launch_bounds__(256) void k_orb_lu(const uint64_t *__restrict__ dets, int64_t n, int M, int na, int nb,
                                                 const float *__restrict__ O, const float *__restrict__ Phi0g,
                                                 double *__restrict__ logabs, int8_t *__restrict__ sign,
-                                                float *__restrict__ Ainv, RowProblems rp, int64_t offPhi0) {
+                                                float *__restrict__ Ainv, RowProblems rp, int64_t offPhi0,
+                                                OutSplit os) {
     const int Ne = na + nb, No = 2 * M;
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t x = gt / G;
@@ -343,7 +345,14 @@ __global__ __launch_bounds__(256) void k_orb_lu(const uint64_t *__restrict__ det
     if (row_live) {
         const uint64_t da = dets[2 * x], db = dets[2 * x + 1];
         const int p = occupied_so(da, db, M, na, r);
-        const float *orow = O + x * (int64_t)(No * Ne) + (int64_t)p * Ne;
+        const float *orow;
+        if (os.idx) {
+            const int dp = os.dpos[p];
+            orow = dp >= 0 ? os.OD + x * (int64_t)(os.nd * Ne) + (int64_t)dp * Ne
+                           : os.Osp + (int64_t)os.idx[x * Ne + r] * Ne;
+        } else {
+            orow = O + x * (int64_t)(No * Ne) + (int64_t)p * Ne;
+        }
         const float *Phi0 = rp.pid ? rp.P[rp.pid[x]].theta + offPhi0 : Phi0g;
         const float *prow = Phi0 + (int64_t)p * Ne;
 #pragma unroll
@@ -421,19 +430,20 @@ __global__ __launch_bounds__(256) void k_orb_lu(const uint64_t *__restrict__ det
 int orb_lu_group(int ne) { return ne <= 8 ? 8 : ne <= 16 ? 16 : ne <= 32 ? 32 : 0; }
 
 void launch_orb_lu(hipStream_t st, const uint64_t *dets, int64_t n, int M, int na, int nb, const float *O,
-                   const float *Phi0, double *logabs, int8_t *sign, float *Ainv, RowProblems rp, int64_t offPhi0) {
+                   const float *Phi0, double *logabs, int8_t *sign, float *Ainv, RowProblems rp, int64_t offPhi0,
+                   OutSplit os) {
     const int G = orb_lu_group(na + nb);
     const int64_t threads = n * G;
     const unsigned blocks = (unsigned)((threads + 255) / 256);
     if (G == 8)
         hipLaunchKernelGGL(k_orb_lu<8>, dim3(blocks), dim3(256), 0, st, dets, n, M, na, nb, O, Phi0, logabs, sign,
-                           Ainv, rp, offPhi0);
+                           Ainv, rp, offPhi0, os);
     else if (G == 16)
         hipLaunchKernelGGL(k_orb_lu<16>, dim3(blocks), dim3(256), 0, st, dets, n, M, na, nb, O, Phi0, logabs, sign,
-                           Ainv, rp, offPhi0);
+                           Ainv, rp, offPhi0, os);
     else
         hipLaunchKernelGGL(k_orb_lu<32>, dim3(blocks), dim3(256), 0, st, dets, n, M, na, nb, O, Phi0, logabs, sign,
-                           Ainv, rp, offPhi0);
+                           Ainv, rp, offPhi0, os);
 }
 
 // ------------------------------------------------------------------ det backward + scatter
@@ -444,9 +454,9 @@ __global__ __launch_bounds__(256) void k_det_bwd(const uint64_t *__restrict__ de
                                                  int nb, const double *__restrict__ psi,
                                                  const double *__restrict__ v, const double *__restrict__ energy,
                                                  const double *__restrict__ stats, const float *__restrict__ Ainv,
-                                                 float *__restrict__ dO, RowProblems rp) {
+                                                 float *__restrict__ dO, RowProblems rp, OutSplit os) {
     const int Ne = na + nb, No = 2 * M;
-    const int width = No * Ne;
+    const int width = No * Ne, wd = os.nd * Ne;
     for (int i = 0; i < kBwdCfg; ++i) {
         const int64_t x = (int64_t)blockIdx.x * kBwdCfg + i;
         if (x >= n) return;
@@ -466,6 +476,29 @@ __global__ __launch_bounds__(256) void k_det_bwd(const uint64_t *__restrict__ de
         const double px = psi[x];
         const float c = ok ? (float)(2.0 * (v[x] - E * px) * px / norm) : 0.0f;
         const float *ai = Ainv + x * (int64_t)(Ne * Ne);
+        if (os.idx) {
+            // sparse rows: dOsp[e][k] = c Ainv[k][j] for row j held as entry e
+            for (int t = threadIdx.x; t < Ne * Ne; t += blockDim.x) {
+                const int j = t / Ne, k = t % Ne;
+                const int e = os.idx[x * Ne + j];
+                if (e >= 0) os.dOsp[(int64_t)e * Ne + k] = c * ai[k * Ne + j];
+            }
+        }
+        if (os.idx) {
+            // the dense orbitals' columns, compact
+            for (int t = threadIdx.x; t < wd; t += blockDim.x) {
+                const int p = os.dorb[t / Ne], k = t % Ne;
+                float out = 0.0f;
+                const uint64_t s = p < M ? a : b;
+                const int q = p < M ? p : p - M;
+                if ((s >> q) & 1ull) {
+                    const int j = (p < M ? 0 : na) + popc64(s & ((1ull << q) - 1ull));
+                    out = c * ai[k * Ne + j];
+                }
+                os.dOD[x * wd + t] = out;
+            }
+        }
+        if (!dO) continue;
         for (int t = threadIdx.x; t < width; t += blockDim.x) {
             const int p = t / Ne, k = t % Ne;
             float out = 0.0f;
@@ -482,9 +515,9 @@ __global__ __launch_bounds__(256) void k_det_bwd(const uint64_t *__restrict__ de
 
 void launch_det_bwd(hipStream_t st, const uint64_t *dets, int64_t n, int M, int na, int nb, const double *psi,
                     const double *v, const double *energy, const double *stats, const float *Ainv, float *dO,
-                    RowProblems rp) {
+                    RowProblems rp, OutSplit os) {
     hipLaunchKernelGGL(k_det_bwd, dim3((unsigned)((n + kBwdCfg - 1) / kBwdCfg)), dim3(256), 0, st, dets, n, M, na,
-                       nb, psi, v, energy, stats, Ainv, dO, rp);
+                       nb, psi, v, energy, stats, Ainv, dO, rp, os);
 }
 
 // y[i] = x[i]

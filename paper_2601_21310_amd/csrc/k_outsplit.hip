@@ -1,0 +1,348 @@
+// Occupied-row form of the orbital output layer (Eqs. 3-4).
+//
+// The determinant of x reads only the rows of Phi(x) at the occupied spin-orbitals, so
+// only N_e of the N_o row blocks of the output layer are needed per configuration.
+// For a variational set grown around a reference determinant, the reference orbitals
+// are occupied in most of S and every other orbital in a few percent of it.  The output
+// layer is therefore split by orbital:
+//   dense  orbitals (occupied in a large share of S): one GEMM over their N_e-wide
+//          column blocks for every configuration (rows of unoccupied orbitals unused);
+//   sparse orbitals: one "entry" per (configuration, occupied sparse orbital), its N_e
+//          outputs computed from that configuration's last hidden layer.
+// Entries are grouped by orbital, each group in ascending configuration order, built
+// without atomics so that every sum below has a fixed order.  The data gradient stays a
+// full-width GEMM: done per configuration, its sparse rows re-read W_L's column blocks
+// from L2 (~86 KB per configuration), which measured slower than the dense product.
+//
+//   k_os_count      occupancy count of every spin-orbital over S
+//   k_os_bcount     per block of 256 configurations: sparse entries per orbital
+//   k_os_scan       entry offsets per (block, orbital)
+//   k_os_fill       entry -> (configuration, occupied row), and (configuration, row) ->
+//                   entry (-1 for a dense orbital)
+//   k_os_gather_w   the dense orbitals' columns of W_L and b_L, [W_D; b_D]
+//   k_os_fwd        O_sp[e][k] = b_L[p N_e + k] + sum_h h[x_e][h] W_L[h][p N_e + k]
+//   k_os_wgrad      partial dW_L, db_L of the sparse orbitals over chunks of entries
+//   k_os_wgrad_sum  fixed-order sum of the chunk partials into the gradient columns
+//   k_os_scatter    dense orbitals' [dW_D; db_D] into the gradient columns
+#include "dnqs_device.h"
+#include "dnqs_kernels.h"
+
+namespace dnqs {
+
+constexpr int kOsBlock = 256;  // configurations per block in the entry build
+
+__device__ __forceinline__ bool so_occupied(uint64_t a, uint64_t b, int M, int p) {
+    return p < M ? ((a >> p) & 1ull) : ((b >> (p - M)) & 1ull);
+}
+
+// row of spin-orbital p (occupied) in A(x): alpha orbitals first, ascending
+__device__ __forceinline__ int so_row(uint64_t a, uint64_t b, int M, int na, int p) {
+    return p < M ? popc64(a & ((1ull << p) - 1ull)) : na + popc64(b & ((1ull << (p - M)) - 1ull));
+}
+
+__global__ void k_os_count(const uint64_t *__restrict__ dets, int64_t n, int M, unsigned long long *__restrict__ cnt) {
+    __shared__ unsigned int h[128];
+    const int No = 2 * M;
+    for (int p = threadIdx.x; p < No; p += blockDim.x) h[p] = 0u;
+    __syncthreads();
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < n) {
+        uint64_t a = dets[2 * x], b = dets[2 * x + 1];
+        while (a) {
+            atomicAdd(&h[ctz64(a)], 1u);
+            a &= a - 1;
+        }
+        while (b) {
+            atomicAdd(&h[M + ctz64(b)], 1u);
+            b &= b - 1;
+        }
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < No; p += blockDim.x)
+        if (h[p]) atomicAdd(&cnt[p], (unsigned long long)h[p]);
+}
+
+__global__ void k_os_bcount(const uint64_t *__restrict__ dets, int64_t n, int M, const int *__restrict__ dpos,
+                            int *__restrict__ bcnt) {
+    __shared__ unsigned int h[128];
+    const int No = 2 * M;
+    for (int p = threadIdx.x; p < No; p += blockDim.x) h[p] = 0u;
+    __syncthreads();
+    const int64_t x = (int64_t)blockIdx.x * kOsBlock + threadIdx.x;
+    if (x < n) {
+        uint64_t a = dets[2 * x], b = dets[2 * x + 1];
+        while (a) {
+            const int p = ctz64(a);
+            a &= a - 1;
+            if (dpos[p] < 0) atomicAdd(&h[p], 1u);
+        }
+        while (b) {
+            const int p = M + ctz64(b);
+            b &= b - 1;
+            if (dpos[p] < 0) atomicAdd(&h[p], 1u);
+        }
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < No; p += blockDim.x) bcnt[(int64_t)blockIdx.x * No + p] = (int)h[p];
+}
+
+// one thread per orbital: boff[blk][p] = eoff[p] + sum_{b < blk} bcnt[b][p]
+__global__ void k_os_scan(const int *__restrict__ bcnt, int64_t nblk, int No, const int64_t *__restrict__ eoff,
+                          int64_t *__restrict__ boff) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= No) return;
+    int64_t s = eoff[p];
+    for (int64_t b = 0; b < nblk; ++b) {
+        boff[b * No + p] = s;
+        s += bcnt[b * No + p];
+    }
+}
+
+// One thread per configuration, kOsBlock per block.  For every orbital in turn the
+// block ranks its configurations holding that sparse orbital (ascending x).
+__global__ __launch_bounds__(kOsBlock) void k_os_fill(const uint64_t *__restrict__ dets, int64_t n, int M, int na,
+                                                      int Ne, const int *__restrict__ dpos,
+                                                      const int64_t *__restrict__ boff, int32_t *__restrict__ ex,
+                                                      int32_t *__restrict__ ej, int32_t *__restrict__ idx) {
+    __shared__ int wsum[kOsBlock / kWave];
+    const int No = 2 * M;
+    const int64_t x = (int64_t)blockIdx.x * kOsBlock + threadIdx.x;
+    const bool live = x < n;
+    const uint64_t a = live ? dets[2 * x] : 0ull, b = live ? dets[2 * x + 1] : 0ull;
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    for (int p = 0; p < No; ++p) {
+        const bool occ = live && so_occupied(a, b, M, p);
+        const bool sp = occ && dpos[p] < 0;
+        const int j = occ ? so_row(a, b, M, na, p) : 0;
+        const uint64_t bal = __ballot(sp);
+        if (lane == 0) wsum[wave] = __popcll(bal);
+        __syncthreads();
+        int before = 0;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        before += __popcll(bal & ((1ull << lane) - 1ull));
+        if (sp) {
+            const int64_t e = boff[(int64_t)blockIdx.x * No + p] + before;
+            ex[e] = (int32_t)x;
+            ej[e] = j;
+            idx[x * Ne + j] = (int32_t)e;
+        } else if (occ) {
+            idx[x * Ne + j] = -1;
+        }
+        __syncthreads();
+    }
+}
+
+// WD[h][t] = W[h][dorb[t / Ne] Ne + t % Ne] (h < din), WD[din][t] = b[...]
+__global__ void k_os_gather_w(const float *__restrict__ W, const float *__restrict__ bias, int din, int width,
+                              int Ne, int nd, const int *__restrict__ dorb, float *__restrict__ WD) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int wd = nd * Ne;
+    if (i >= (int64_t)(din + 1) * wd) return;
+    const int h = (int)(i / wd), t = (int)(i % wd);
+    const int col = dorb[t / Ne] * Ne + t % Ne;
+    WD[i] = h < din ? W[(int64_t)h * width + col] : bias[col];
+}
+
+// Entry tiles: {orbital, first entry, count <= kOsTile}.  Four lanes per entry split the
+// hidden dimension (lane q takes h = 16 i + 4 q .. + 3, so the four lanes of an entry read
+// 64 contiguous bytes per load), each keeps all NP >= Ne outputs, and the four partial
+// sums are added by two shuffles; W_L's column block of the orbital is staged in LDS as
+// [din][NP].
+constexpr int kOsTile = 64;
+
+template <int NP>
+__global__ __launch_bounds__(256) void k_os_fwd(const float *__restrict__ hL, int din, const float *__restrict__ W,
+                                                const float *__restrict__ bias, int width, int Ne,
+                                                const int4 *__restrict__ tiles, const int32_t *__restrict__ ex,
+                                                float *__restrict__ Osp) {
+    extern __shared__ float Ws[];  // [din][NP]
+    const int4 tl = tiles[blockIdx.x];
+    const int p = tl.x;
+    for (int i = threadIdx.x; i < din * NP; i += blockDim.x) {
+        const int h = i / NP, c = i % NP;
+        Ws[i] = c < Ne ? W[(int64_t)h * width + p * Ne + c] : 0.0f;
+    }
+    __syncthreads();
+    const int le = threadIdx.x / 4, q = threadIdx.x % 4;
+    const bool vec = (din & 3) == 0;
+    for (int e0 = 0; e0 < tl.z; e0 += 64) {
+        const int le2 = e0 + le;
+        const bool have = le2 < tl.z;
+        const int64_t e = (int64_t)tl.y + (have ? le2 : 0);
+        const float *hr = hL + (int64_t)ex[e] * din;
+        float acc[NP];
+#pragma unroll
+        for (int c = 0; c < NP; ++c) acc[c] = 0.0f;
+        if (have) {
+#pragma unroll 4
+            for (int h = 4 * q; h < din; h += 16) {
+                float hv[4];
+                if (vec && h + 4 <= din) {
+                    const float4 v = *reinterpret_cast<const float4 *>(hr + h);
+                    hv[0] = v.x;
+                    hv[1] = v.y;
+                    hv[2] = v.z;
+                    hv[3] = v.w;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) hv[r] = h + r < din ? hr[h + r] : 0.0f;
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (h + r >= din) break;
+                    const float4 *w4 = reinterpret_cast<const float4 *>(Ws + (h + r) * NP);
+#pragma unroll
+                    for (int c4 = 0; c4 < NP / 4; ++c4) {
+                        const float4 w = w4[c4];
+                        acc[4 * c4 + 0] = fmaf(hv[r], w.x, acc[4 * c4 + 0]);
+                        acc[4 * c4 + 1] = fmaf(hv[r], w.y, acc[4 * c4 + 1]);
+                        acc[4 * c4 + 2] = fmaf(hv[r], w.z, acc[4 * c4 + 2]);
+                        acc[4 * c4 + 3] = fmaf(hv[r], w.w, acc[4 * c4 + 3]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NP; ++c) {
+            acc[c] += __shfl_xor(acc[c], 1, 4);
+            acc[c] += __shfl_xor(acc[c], 2, 4);
+        }
+        if (have && q == 0)
+            for (int c = 0; c < Ne; ++c) Osp[e * Ne + c] = bias[p * Ne + c] + acc[c];
+    }
+}
+
+// Partial weight / bias gradients of the sparse orbitals.  Work item {orbital, first
+// entry, count <= kOsItemMax}; its entries' dO (rows padded to NP values) and
+// configurations are staged in LDS; thread h in [0, din] (h = din: the bias row)
+// accumulates the Ne outputs over the item's entries in order into part[item][h][k].
+constexpr int kOsItemMax = 512;
+
+template <int NP>
+__global__ __launch_bounds__(256) void k_os_wgrad(const float *__restrict__ hL, int din, int Ne,
+                                                  const int4 *__restrict__ items, const int32_t *__restrict__ ex,
+                                                  const float *__restrict__ dOsp, float *__restrict__ part) {
+    extern __shared__ float gs[];  // [kOsItemMax][NP], then kOsItemMax configuration indices
+    int *xs = reinterpret_cast<int *>(gs + kOsItemMax * NP);
+    const int4 it = items[blockIdx.x];
+    for (int i = threadIdx.x; i < it.z * NP; i += blockDim.x) {
+        const int e = i / NP, k = i % NP;
+        gs[i] = k < Ne ? dOsp[((int64_t)it.y + e) * Ne + k] : 0.0f;
+    }
+    for (int i = threadIdx.x; i < it.z; i += blockDim.x) xs[i] = ex[(int64_t)it.y + i];
+    __syncthreads();
+    float *out = part + (int64_t)blockIdx.x * (din + 1) * Ne;
+    for (int h = blockIdx.y * blockDim.x + threadIdx.x; h <= din; h += gridDim.y * blockDim.x) {
+        float acc[NP];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) acc[k] = 0.0f;
+#pragma unroll 4
+        for (int i = 0; i < it.z; ++i) {
+            const float hv = h < din ? hL[(int64_t)xs[i] * din + h] : 1.0f;
+            const float4 *g4 = reinterpret_cast<const float4 *>(gs + i * NP);
+#pragma unroll
+            for (int q = 0; q < NP / 4; ++q) {
+                const float4 g = g4[q];
+                acc[4 * q + 0] = fmaf(hv, g.x, acc[4 * q + 0]);
+                acc[4 * q + 1] = fmaf(hv, g.y, acc[4 * q + 1]);
+                acc[4 * q + 2] = fmaf(hv, g.z, acc[4 * q + 2]);
+                acc[4 * q + 3] = fmaf(hv, g.w, acc[4 * q + 3]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+            if (k < Ne) out[(int64_t)h * Ne + k] = acc[k];
+    }
+}
+
+// grad[h][p Ne + k] (h <= din; row din is the bias) = sum over the orbital's items in
+// order; zero for a sparse orbital without entries.  One thread per (h, p, k).
+__global__ void k_os_wgrad_sum(const float *__restrict__ part, int din, int Ne, int No, const int *__restrict__ dpos,
+                               const int *__restrict__ ifirst, const int *__restrict__ icount,
+                               float *__restrict__ grad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int width = No * Ne;
+    if (i >= (int64_t)(din + 1) * width) return;
+    const int h = (int)(i / width), col = (int)(i % width);
+    const int p = col / Ne, k = col % Ne;
+    if (dpos[p] >= 0) return;
+    float s = 0.0f;
+    for (int q = 0; q < icount[p]; ++q) s += part[((int64_t)(ifirst[p] + q) * (din + 1) + h) * Ne + k];
+    grad[i] = s;
+}
+
+// grad[h][dorb[t / Ne] Ne + t % Ne] = GD[h][t] for h <= din
+__global__ void k_os_scatter(const float *__restrict__ GD, int din, int Ne, int nd, int width,
+                             const int *__restrict__ dorb, float *__restrict__ grad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int wd = nd * Ne;
+    if (i >= (int64_t)(din + 1) * wd) return;
+    const int h = (int)(i / wd), t = (int)(i % wd);
+    grad[(int64_t)h * width + dorb[t / Ne] * Ne + t % Ne] = GD[i];
+}
+
+// ------------------------------------------------------------------ launches
+static unsigned g1(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+void launch_os_count(hipStream_t st, const uint64_t *dets, int64_t n, int M, unsigned long long *cnt) {
+    hipLaunchKernelGGL(k_os_count, dim3(g1(n)), dim3(256), 0, st, dets, n, M, cnt);
+}
+
+int64_t os_blocks(int64_t n) { return (n + kOsBlock - 1) / kOsBlock; }
+
+void launch_os_build(hipStream_t st, const uint64_t *dets, int64_t n, int M, int na, int Ne, const int *dpos,
+                     const int64_t *eoff, int *bcnt, int64_t *boff, int32_t *ex, int32_t *ej, int32_t *idx) {
+    const int64_t nb = os_blocks(n);
+    const int No = 2 * M;
+    hipLaunchKernelGGL(k_os_bcount, dim3((unsigned)nb), dim3(kOsBlock), 0, st, dets, n, M, dpos, bcnt);
+    hipLaunchKernelGGL(k_os_scan, dim3(1), dim3(128), 0, st, bcnt, nb, No, eoff, boff);
+    hipLaunchKernelGGL(k_os_fill, dim3((unsigned)nb), dim3(kOsBlock), 0, st, dets, n, M, na, Ne, dpos, boff, ex, ej,
+                       idx);
+}
+
+void launch_os_gather_w(hipStream_t st, const float *W, const float *bias, int din, int width, int Ne, int nd,
+                        const int *dorb, float *WD) {
+    const int64_t tot = (int64_t)(din + 1) * nd * Ne;
+    if (tot == 0) return;
+    hipLaunchKernelGGL(k_os_gather_w, dim3(g1(tot)), dim3(256), 0, st, W, bias, din, width, Ne, nd, dorb, WD);
+}
+
+int os_tile() { return kOsTile; }
+int os_item() { return kOsItemMax; }
+
+void launch_os_fwd(hipStream_t st, const float *hL, int din, const float *W, const float *bias, int width, int Ne,
+                   const int4 *tiles, int64_t ntiles, const int32_t *ex, float *Osp) {
+    if (ntiles == 0) return;
+    if (Ne <= 16)
+        hipLaunchKernelGGL(k_os_fwd<16>, dim3((unsigned)ntiles), dim3(256), sizeof(float) * din * 16, st, hL, din, W,
+                           bias, width, Ne, tiles, ex, Osp);
+    else
+        hipLaunchKernelGGL(k_os_fwd<32>, dim3((unsigned)ntiles), dim3(256), sizeof(float) * din * 32, st, hL, din, W,
+                           bias, width, Ne, tiles, ex, Osp);
+}
+
+void launch_os_wgrad(hipStream_t st, const float *hL, int din, int Ne, const int4 *items, int64_t nitems,
+                     const int32_t *ex, const float *dOsp, float *part, const int *dpos, const int *ifirst,
+                     const int *icount, int No, float *grad) {
+    if (nitems > 0) {
+        const unsigned gy = (unsigned)((din + 1 + 255) / 256);
+        if (Ne <= 16)
+            hipLaunchKernelGGL(k_os_wgrad<16>, dim3((unsigned)nitems, gy), dim3(256),
+                               (sizeof(float) * 16 + sizeof(int)) * kOsItemMax, st, hL, din, Ne, items, ex, dOsp, part);
+        else
+            hipLaunchKernelGGL(k_os_wgrad<32>, dim3((unsigned)nitems, gy), dim3(256),
+                               (sizeof(float) * 32 + sizeof(int)) * kOsItemMax, st, hL, din, Ne, items, ex, dOsp, part);
+    }
+    const int64_t tot = (int64_t)(din + 1) * No * Ne;
+    hipLaunchKernelGGL(k_os_wgrad_sum, dim3(g1(tot)), dim3(256), 0, st, part, din, Ne, No, dpos, ifirst, icount,
+                       grad);
+}
+
+void launch_os_scatter(hipStream_t st, const float *GD, int din, int Ne, int nd, int width, const int *dorb,
+                       float *grad) {
+    const int64_t tot = (int64_t)(din + 1) * nd * Ne;
+    if (tot == 0) return;
+    hipLaunchKernelGGL(k_os_scatter, dim3(g1(tot)), dim3(256), 0, st, GD, din, Ne, nd, width, dorb, grad);
+}
+
+}  // namespace dnqs

@@ -101,7 +101,8 @@ def test_batched_tuned_matches_single(dnqs):
         thetas = [torch.from_numpy(p.theta).cuda() for p in curve]
         batch = ctx.batch(wl.widths, list(range(len(curve))), conns, thetas)
         out = ctx.energy_and_grad_batched(batch, precision=dnqs.MIXED)
-        single = [ctx.energy_and_grad(wl.widths, thetas[g], conns[g], precision=dnqs.MIXED) for g in range(3)]
+        single = [ctx.energy_and_grad(wl.widths, thetas[g], conns[g], precision=dnqs.MIXED, full_output=True)
+                  for g in range(3)]
         stream.synchronize()
     kinds = sorted({int(ln.split()[1]) for ln in ctx.tune_export().strip().splitlines()})
     assert kinds == [0, 1, 2, 3]

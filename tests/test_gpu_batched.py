@@ -1,7 +1,8 @@
 """Batched geometries: one launch per stage over several problems, AdamW, and HIP-graph
 replay of a whole optimisation step.
 
-* batched E and gradient equal the single-problem results for every geometry (which
+* batched E and gradient equal the single-problem results (full-width output layer, as
+  the batched call computes it) for every geometry (which
   the parity tests tie to the oracle), and one geometry is compared with the oracle;
 * the AdamW update equals torch.optim.AdamW (CPU, FP32) with the same cosine schedule;
 * a captured step (energy_and_grad_batched + adamw_batched), replayed several times
@@ -54,7 +55,8 @@ def test_batched_equals_single(dnqs, curve, setup, precision):
         thetas = [torch.from_numpy(p.theta).cuda() for p in curve]
         batch = ctx.batch(WL.widths, list(range(len(curve))), conns, thetas)
         out = ctx.energy_and_grad_batched(batch, precision=prec)
-        single = [ctx.energy_and_grad(WL.widths, thetas[g], conns[g], precision=prec) for g in range(len(curve))]
+        single = [ctx.energy_and_grad(WL.widths, thetas[g], conns[g], precision=prec, full_output=True)
+                  for g in range(len(curve))]
         stream.synchronize()
     for g in range(len(curve)):
         Eb, Es = out[g]["E"].item(), single[g]["E"].item()
