@@ -406,7 +406,7 @@ dnqs_status forward(dnqs_ctx *ctx, const Slot &sl, const NetView &nv, const floa
     CHECK_LAUNCH(ctx);
     void *prev = h;
     OutSplit os{};
-    const bool split = conn && conn->os_nd >= 0 && L >= 2;
+    const bool split = conn && conn->os_nd >= 0 && L >= 2 && os_fwd_fits(w[L - 1], Ne);
     for (int l = 2; l <= L; ++l) {
         if (l == L && split) {
             const int nd = conn->os_nd, wd = nd * Ne, din = w[L - 1];
@@ -529,6 +529,7 @@ dnqs_status os_plan(dnqs_ctx *ctx, dnqs_conn *c) {
     for (int p = 0; p < No; ++p) eoff[p + 1] = eoff[p] + (dpos[p] < 0 ? (int64_t)cnt[p] : 0);
     const int64_t E = eoff[No];
     if (nd == No || (double)nd * n + 3.0 * (double)E > 0.8 * (double)No * n) return DNQS_OK;
+    if (E >= ((int64_t)1 << 31) - 1) return DNQS_OK;  // entry ids are int32
     std::vector<int4> tiles, items;
     for (int p = 0; p < No; ++p) {
         if (dpos[p] >= 0) continue;
@@ -883,13 +884,12 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
     if (!want_grad) return DNQS_OK;
     // adjoint: dO, then layer by layer
     float *dO = nullptr;
-    const bool split = !full_out && conn->os_nd >= 0 && L >= 2;
+    const bool split = !full_out && conn->os_nd >= 0 && L >= 2 && os_fwd_fits(w[L - 1], Ne);
     const int nd = split ? conn->os_nd : 0, wd = nd * Ne;
     OutSplit og{};
     if (split) {
-        // full-width dO for the data gradient, and the split layout for the weight gradient
+        // dO in the occupied-row layout only
         float *dOsp = nullptr, *dOD = nullptr;
-        TRY(ws_t(ctx, "dO", (size_t)n * w[L], &dO));
         TRY(ws_t(ctx, "os_dOD", (size_t)n * std::max(wd, 1), &dOD));
         TRY(ws_t(ctx, "os_dOsp", (size_t)std::max<int64_t>(conn->os_ne, 1) * Ne, &dOsp));
         og.dOD = dOD;
@@ -898,7 +898,7 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
         og.dorb = conn->os_dorb;
         og.idx = conn->os_idx;
         og.nd = nd;
-        launch_det_bwd(st, conn->dets, n, M, sl.na, sl.nb, psi, v, energy, stats, Ainv, dO, {}, og);
+        launch_det_bwd(st, conn->dets, n, M, sl.na, sl.nb, psi, v, energy, stats, Ainv, nullptr, {}, og);
     } else {
         TRY(ws_t(ctx, "dO", (size_t)n * w[L], &dO));
         launch_det_bwd(st, conn->dets, n, M, sl.na, sl.nb, psi, v, energy, stats, Ainv, dO);
@@ -918,8 +918,10 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
         TRY(ws_get(ctx, l == 1 ? std::string("U") : "h" + std::to_string(l - 1), 1, &hp));
         const int din = w[l - 1], dout = w[l];
         if (l == L && split) {
-            // occupied-row output layer, weight gradient: the dense columns by GEMM
-            // (scattered into place), the sparse orbitals over their entries
+            // occupied-row output layer.  Weight gradient: the dense columns by GEMM
+            // (scattered into place), the sparse orbitals over their entries.  Data
+            // gradient: the dense columns by GEMM, the sparse rows by orbital, summed per
+            // configuration in row order with tanh'.
             const int eng = gemm_engine(precision, true);
             if (nd > 0) {
                 float *GD = nullptr;
@@ -956,34 +958,71 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
             launch_os_wgrad(st, (const float *)hp, din, Ne, conn->os_items, conn->os_nitems, conn->os_ex, og.dOsp,
                             part_w, conn->os_dpos, conn->os_ifirst, conn->os_icount, No, grad + nv.offW[l]);
             CHECK_LAUNCH(ctx);
+            float *dD = nullptr;
+            if (nd > 0) {
+                float *WD = nullptr;  // [W_D; b_D] from this call's forward
+                TRY(ws_t(ctx, "os_WD", (size_t)(din + 1) * std::max(wd, 1), &WD));
+                TRY(ws_t(ctx, "os_dD", (size_t)n * din, &dD));
+                GemmArgs d{};
+                d.M = (int)n;
+                d.N = din;
+                d.K = wd;
+                d.A = og.dOD;
+                d.lda = wd;
+                d.B = WD;
+                d.ldb = wd;
+                d.C = dD;
+                d.ldc = din;
+                d.ones_row = -1;
+                // K = n_d N_e is small (196 at the benchmark): the split-BF16 kernel's
+                // two-step prefetch does not amortise over so few K steps, so this product
+                // runs on the FP32 engine in every form (measured 0.22 against 0.36 ms)
+                const int deng = wd < 256 ? 0 : eng;
+                if (deng == 1) TRY(weight_planes(ctx, "wpO", WD, din, wd, false, d));
+                TRY(tuned_launch(ctx, TuneKey{deng, 2, d.M, d.N, d.K}, gemm_candidates(d.M, d.N, d.K, false, false),
+                                 [&](const GemmCfg &c) -> dnqs_status {
+                                     launch_gemm(deng, st, d, true, false, EPI_STORE, 1, c.tm);
+                                     CHECK_LAUNCH(ctx);
+                                     return DNQS_OK;
+                                 }));
+            }
+            float *WT = nullptr, *Cr = nullptr;
+            TRY(ws_t(ctx, "os_WT", (size_t)din * dout, &WT));
+            TRY(ws_t(ctx, "os_C", (size_t)std::max<int64_t>(conn->os_ne, 1) * din, &Cr));
+            launch_os_trans_w(st, theta + nv.offW[l], din, dout, WT);
+            void *dnext = dbuf[which];
+            which ^= 1;
+            launch_os_dgrad(st, n, Ne, din, WT, conn->os_tiles, conn->os_ntiles, og.dOsp, Cr, dD, conn->os_idx,
+                            (const float *)hp, (float *)dnext);
+            CHECK_LAUNCH(ctx);
+            delta = dnext;
+            continue;
         }
-        if (!(l == L && split)) {
-            GemmArgs g{};
-            g.M = din + 1;
-            g.N = dout;
-            g.K = (int)n;
-            g.A = hp;
-            g.lda = din;
-            g.B = delta;
-            g.ldb = dout;
-            g.ldc = dout;
-            g.ones_row = din;
-            const int64_t cnt = (int64_t)(din + 1) * dout;
-            const int eng = gemm_engine(precision, l == L);
-            TRY(tuned_launch(ctx, TuneKey{eng, 1, g.M, g.N, g.K}, gemm_candidates(g.M, g.N, g.K, true, false),
-                             [&](const GemmCfg &c) -> dnqs_status {
-                                 float *partial = nullptr;
-                                 TRY(ws_t(ctx, "splitk", (size_t)cnt * c.splits, &partial));
-                                 GemmArgs gs = g;
-                                 gs.C = partial;
-                                 gs.c_split_stride = cnt;
-                                 launch_gemm(eng, st, gs, false, true, EPI_STORE, c.splits, c.tm);
-                                 CHECK_LAUNCH(ctx);
-                                 launch_reduce_splits(st, partial, c.splits, cnt, grad + nv.offW[l]);
-                                 CHECK_LAUNCH(ctx);
-                                 return DNQS_OK;
-                             }));
-        }
+        GemmArgs g{};
+        g.M = din + 1;
+        g.N = dout;
+        g.K = (int)n;
+        g.A = hp;
+        g.lda = din;
+        g.B = delta;
+        g.ldb = dout;
+        g.ldc = dout;
+        g.ones_row = din;
+        const int64_t cnt = (int64_t)(din + 1) * dout;
+        const int eng = gemm_engine(precision, l == L);
+        TRY(tuned_launch(ctx, TuneKey{eng, 1, g.M, g.N, g.K}, gemm_candidates(g.M, g.N, g.K, true, false),
+                         [&](const GemmCfg &c) -> dnqs_status {
+                             float *partial = nullptr;
+                             TRY(ws_t(ctx, "splitk", (size_t)cnt * c.splits, &partial));
+                             GemmArgs gs = g;
+                             gs.C = partial;
+                             gs.c_split_stride = cnt;
+                             launch_gemm(eng, st, gs, false, true, EPI_STORE, c.splits, c.tm);
+                             CHECK_LAUNCH(ctx);
+                             launch_reduce_splits(st, partial, c.splits, cnt, grad + nv.offW[l]);
+                             CHECK_LAUNCH(ctx);
+                             return DNQS_OK;
+                         }));
         if (l == 1) break;
         // delta_{l-1} = (delta_l W_l^T) * (1 - h_{l-1}^2)
         void *dnext = dbuf[which];

@@ -121,6 +121,13 @@ void launch_os_build(hipStream_t st, const uint64_t *dets, int64_t n, int M, int
 void launch_os_gather_w(hipStream_t st, const float *W, const float *bias, int din, int width, int Ne, int nd,
                         const int *dorb, float *WD);
 int os_tile();
+void launch_os_trans_w(hipStream_t st, const float *W, int din, int width, float *WT);
+// data gradient of the output layer's sparse rows (Cr: entries x din scratch), added to
+// the dense part dD (may be null) per configuration, times (1 - hL^2), into delta
+void launch_os_dgrad(hipStream_t st, int64_t n, int Ne, int din, const float *WT, const int4 *tiles, int64_t ntiles,
+                     const float *dOsp, float *Cr, const float *dD, const int32_t *idx, const float *hL,
+                     float *delta);
+bool os_fwd_fits(int din, int Ne);  // the occupied-row forward fits LDS for this layer
 int os_item();  // entries per weight-gradient work item (at most)
 void launch_os_fwd(hipStream_t st, const float *hL, int din, const float *W, const float *bias, int width, int Ne,
                    const int4 *tiles, int64_t ntiles, const int32_t *ex, float *Osp);

@@ -10,9 +10,9 @@
 //   sparse orbitals: one "entry" per (configuration, occupied sparse orbital), its N_e
 //          outputs computed from that configuration's last hidden layer.
 // Entries are grouped by orbital, each group in ascending configuration order, built
-// without atomics so that every sum below has a fixed order.  The data gradient stays a
-// full-width GEMM: done per configuration, its sparse rows re-read W_L's column blocks
-// from L2 (~86 KB per configuration), which measured slower than the dense product.
+// without atomics so that every sum below has a fixed order.  The data gradient of the
+// sparse rows is formed by orbital (its weight block read once per tile of entries) and
+// then summed per configuration in row order.
 //
 //   k_os_count      occupancy count of every spin-orbital over S
 //   k_os_bcount     per block of 256 configurations: sparse entries per orbital
@@ -21,6 +21,10 @@
 //                   entry (-1 for a dense orbital)
 //   k_os_gather_w   the dense orbitals' columns of W_L and b_L, [W_D; b_D]
 //   k_os_fwd        O_sp[e][k] = b_L[p N_e + k] + sum_h h[x_e][h] W_L[h][p N_e + k]
+//   k_os_trans_w    W_L as [orbital][electron][hidden]
+//   k_os_drows      C[e][h] = sum_k dO_sp[e][k] W_L[h][p_e N_e + k]
+//   k_os_dsum       delta[x][h] = (delta_D[x][h] + sum_{sparse rows e of x} C[e][h])
+//                   (1 - h[x][h]^2)
 //   k_os_wgrad      partial dW_L, db_L of the sparse orbitals over chunks of entries
 //   k_os_wgrad_sum  fixed-order sum of the chunk partials into the gradient columns
 //   k_os_scatter    dense orbitals' [dW_D; db_D] into the gradient columns
@@ -212,6 +216,75 @@ __global__ __launch_bounds__(256) void k_os_fwd(const float *__restrict__ hL, in
     }
 }
 
+// WT[p][k][h] = W[h][p Ne + k]
+__global__ void k_os_trans_w(const float *__restrict__ W, int din, int width, float *__restrict__ WT) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)din * width) return;
+    const int col = (int)(i / din), h = (int)(i % din);
+    WT[i] = W[(int64_t)h * width + col];
+}
+
+// Data gradient of the sparse rows, by orbital: Cr[e][h] = sum_k dO_sp[e][k] W[h][p Ne + k]
+// for the entries e of one tile (orbital p); thread h keeps W's Ne values for its h in
+// registers, the tile's dO rows are staged in LDS.
+template <int NP>
+__global__ __launch_bounds__(256) void k_os_drows(const float *__restrict__ WT, int din, int Ne,
+                                                  const int4 *__restrict__ tiles, const float *__restrict__ dOsp,
+                                                  float *__restrict__ Cr) {
+    __shared__ float gs[kOsTile * NP];
+    const int4 tl = tiles[blockIdx.x];
+    const int p = tl.x;
+    for (int i = threadIdx.x; i < tl.z * NP; i += blockDim.x) {
+        const int e = i / NP, k = i % NP;
+        gs[i] = k < Ne ? dOsp[((int64_t)tl.y + e) * Ne + k] : 0.0f;
+    }
+    __syncthreads();
+    for (int h = threadIdx.x; h < din; h += blockDim.x) {
+        float w[NP];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) w[k] = k < Ne ? WT[((int64_t)p * Ne + k) * din + h] : 0.0f;
+        for (int e = 0; e < tl.z; ++e) {
+            const float4 *g4 = reinterpret_cast<const float4 *>(gs + e * NP);
+            float s = 0.0f;
+#pragma unroll
+            for (int q = 0; q < NP / 4; ++q) {
+                const float4 g = g4[q];
+                s = fmaf(g.x, w[4 * q + 0], s);
+                s = fmaf(g.y, w[4 * q + 1], s);
+                s = fmaf(g.z, w[4 * q + 2], s);
+                s = fmaf(g.w, w[4 * q + 3], s);
+            }
+            Cr[((int64_t)tl.y + e) * din + h] = s;
+        }
+    }
+}
+
+// delta[x][h] = (dD[x][h] + sum of Cr[e][h] over x's sparse rows e in row order)
+//               * (1 - hL[x][h]^2); four configurations per workgroup, one wave each.
+// dD (the dense part) may be null (no dense orbital).
+__global__ __launch_bounds__(256) void k_os_dsum(int64_t n, int Ne, int din, const float *__restrict__ dD,
+                                                 const float *__restrict__ Cr, const int32_t *__restrict__ idx,
+                                                 const float *__restrict__ hL, float *__restrict__ delta) {
+    __shared__ int es[4][32];
+    __shared__ int nes[4];
+    const int sl = threadIdx.x / 64, lt = threadIdx.x % 64;
+    const int64_t x = (int64_t)blockIdx.x * 4 + sl;
+    const bool live = x < n;
+    const int e = (live && lt < Ne) ? idx[x * Ne + lt] : -1;
+    const uint64_t bal = __ballot(e >= 0);
+    if (e >= 0) es[sl][__popcll(bal & ((1ull << lt) - 1ull))] = e;
+    if (lt == 0) nes[sl] = __popcll(bal);
+    __syncthreads();
+    if (!live) return;
+    const int cnt = nes[sl];
+    for (int h = lt; h < din; h += 64) {
+        float s = dD ? dD[x * din + h] : 0.0f;
+        for (int r = 0; r < cnt; ++r) s += Cr[(int64_t)es[sl][r] * din + h];
+        const float hv = hL[x * din + h];
+        delta[x * din + h] = s * (1.0f - hv * hv);
+    }
+}
+
 // Partial weight / bias gradients of the sparse orbitals.  Work item {orbital, first
 // entry, count <= kOsItemMax}; its entries' dO (rows padded to NP values) and
 // configurations are staged in LDS; thread h in [0, din] (h = din: the bias row)
@@ -308,6 +381,9 @@ void launch_os_gather_w(hipStream_t st, const float *W, const float *bias, int d
 }
 
 int os_tile() { return kOsTile; }
+
+// k_os_fwd stages the orbital's din x NP weight block in LDS
+bool os_fwd_fits(int din, int Ne) { return (size_t)din * (Ne <= 16 ? 16 : 32) * sizeof(float) <= 160 * 1024; }
 int os_item() { return kOsItemMax; }
 
 void launch_os_fwd(hipStream_t st, const float *hL, int din, const float *W, const float *bias, int width, int Ne,
@@ -319,6 +395,24 @@ void launch_os_fwd(hipStream_t st, const float *hL, int din, const float *W, con
     else
         hipLaunchKernelGGL(k_os_fwd<32>, dim3((unsigned)ntiles), dim3(256), sizeof(float) * din * 32, st, hL, din, W,
                            bias, width, Ne, tiles, ex, Osp);
+}
+
+void launch_os_trans_w(hipStream_t st, const float *W, int din, int width, float *WT) {
+    const int64_t tot = (int64_t)din * width;
+    hipLaunchKernelGGL(k_os_trans_w, dim3(g1(tot)), dim3(256), 0, st, W, din, width, WT);
+}
+
+void launch_os_dgrad(hipStream_t st, int64_t n, int Ne, int din, const float *WT, const int4 *tiles, int64_t ntiles,
+                     const float *dOsp, float *Cr, const float *dD, const int32_t *idx, const float *hL,
+                     float *delta) {
+    if (ntiles > 0) {
+        if (Ne <= 16)
+            hipLaunchKernelGGL(k_os_drows<16>, dim3((unsigned)ntiles), dim3(256), 0, st, WT, din, Ne, tiles, dOsp, Cr);
+        else
+            hipLaunchKernelGGL(k_os_drows<32>, dim3((unsigned)ntiles), dim3(256), 0, st, WT, din, Ne, tiles, dOsp, Cr);
+    }
+    hipLaunchKernelGGL(k_os_dsum, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, n, Ne, din, dD, Cr, idx, hL,
+                       delta);
 }
 
 void launch_os_wgrad(hipStream_t st, const float *hL, int din, int Ne, const int4 *items, int64_t nitems,
