@@ -158,7 +158,10 @@ dnqs_status dnqs_amplitudes(dnqs_ctx *ctx, int slot, const dnqs_net *net, const 
  * orbitals occupied in >= 35% of S take a dense GEMM and every other occupied row is
  * computed per configuration (the plan is built by dnqs_build_connections).  Results
  * equal the full-width layer up to FP32 summation order.  flags: DNQS_FULL_OUTPUT
- * forces the full-width layer (as in the batched call). */
+ * forces the full-width layer (as in the batched call).  The weight gradients (and the
+ * output layer's per-row products) run on a second stream of the context's device that
+ * is forked from and joined back to the context's stream with events, so the call is
+ * still ordered with that stream as a whole (no fork inside dnqs_capture_begin/end). */
 #define DNQS_FULL_OUTPUT 1u
 dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, const float *theta,
                                  const dnqs_conn *conn, int precision, unsigned flags, double *energy,

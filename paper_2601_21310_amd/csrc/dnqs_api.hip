@@ -97,6 +97,11 @@ struct dnqs_ctx {
     bool capturing = false;
     bool autotune = false;
     std::map<TuneKey, GemmCfg> tuned;
+    // auxiliary stream (default priority) for the weight gradients of the backward pass,
+    // and its fork / join events (per layer: data ready, weight gradient done)
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_ready[16] = {}, ev_wdone[16] = {};
+    hipEvent_t ev_fwd[2] = {};  // forward output layer: input ready, sparse rows done
 };
 
 struct dnqs_graph {
@@ -154,8 +159,9 @@ dnqs_status ws_get(dnqs_ctx *ctx, const std::string &name, size_t bytes, void **
     Buf &b = ctx->ws[name];
     if (b.bytes < bytes) {
         if (b.p) {
-            // queued kernels may still use the old buffer
+            // queued kernels may still use the old buffer (on either stream)
             HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+            if (ctx->aux) HIPCHK(ctx, hipStreamSynchronize(ctx->aux));
             HIPCHK(ctx, hipFree(b.p));
         }
         b.p = nullptr;
@@ -330,7 +336,9 @@ dnqs_status weight_planes(dnqs_ctx *ctx, const std::string &name, const float *W
 // context stream (one warm-up and three timed runs each, HIP events) and the fastest
 // kept; else the first candidate (the default).  launch() must be safe to repeat.
 template <typename F>
-dnqs_status tuned_launch(dnqs_ctx *ctx, const TuneKey &key, const std::vector<GemmCfg> &cands, F launch) {
+dnqs_status tuned_launch(dnqs_ctx *ctx, const TuneKey &key, const std::vector<GemmCfg> &cands, F launch,
+                         hipStream_t ts = nullptr) {
+    if (!ts) ts = ctx->stream;
     auto it = ctx->tuned.find(key);
     if (it != ctx->tuned.end()) return launch(it->second);
     if (!ctx->autotune || ctx->capturing || cands.size() < 2) return launch(cands[0]);
@@ -342,11 +350,11 @@ dnqs_status tuned_launch(dnqs_ctx *ctx, const TuneKey &key, const std::vector<Ge
     dnqs_status st = DNQS_OK;
     for (const GemmCfg &c : cands) {
         if ((st = launch(c)) != DNQS_OK) break;
-        if (hipEventRecord(e0, ctx->stream) != hipSuccess) { st = DNQS_EHIP; break; }
+        if (hipEventRecord(e0, ts) != hipSuccess) { st = DNQS_EHIP; break; }
         for (int r = 0; r < 3 && st == DNQS_OK; ++r) st = launch(c);
         if (st != DNQS_OK) break;
         float ms = 0.0f;
-        if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        if (hipEventRecord(e1, ts) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
             hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
             st = DNQS_EHIP;
             break;
@@ -416,6 +424,22 @@ dnqs_status forward(dnqs_ctx *ctx, const Slot &sl, const NetView &nv, const floa
             TRY(ws_t(ctx, "os_Osp", (size_t)std::max<int64_t>(conn->os_ne, 1) * Ne, &Osp));
             launch_os_gather_w(st, theta + nv.offW[L], theta + nv.offb[L], din, w[L], Ne, nd, conn->os_dorb, WD);
             CHECK_LAUNCH(ctx);
+            // the sparse rows on the auxiliary stream, alongside the dense GEMM (both read
+            // only h_{L-1}); joined before the LU.  Not during capture.
+            const bool fork = !ctx->capturing;
+            hipStream_t ast = st;
+            if (fork) {
+                if (!ctx->aux) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+                for (hipEvent_t &e : ctx->ev_fwd)
+                    if (!e) HIPCHK(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+                ast = ctx->aux;
+                HIPCHK(ctx, hipEventRecord(ctx->ev_fwd[0], st));
+                HIPCHK(ctx, hipStreamWaitEvent(ast, ctx->ev_fwd[0], 0));
+            }
+            launch_os_fwd(ast, (const float *)prev, din, theta + nv.offW[L], theta + nv.offb[L], w[L], Ne,
+                          conn->os_tiles, conn->os_ntiles, conn->os_ex, Osp);
+            CHECK_LAUNCH(ctx);
+            if (fork) HIPCHK(ctx, hipEventRecord(ctx->ev_fwd[1], ast));
             if (nd > 0) {
                 GemmArgs g{};
                 g.M = (int)n;
@@ -438,9 +462,7 @@ dnqs_status forward(dnqs_ctx *ctx, const Slot &sl, const NetView &nv, const floa
                                      return DNQS_OK;
                                  }));
             }
-            launch_os_fwd(st, (const float *)prev, din, theta + nv.offW[L], theta + nv.offb[L], w[L], Ne,
-                          conn->os_tiles, conn->os_ntiles, conn->os_ex, Osp);
-            CHECK_LAUNCH(ctx);
+            if (fork) HIPCHK(ctx, hipStreamWaitEvent(st, ctx->ev_fwd[1], 0));
             os.OD = OD;
             os.Osp = Osp;
             os.dpos = conn->os_dpos;
@@ -621,6 +643,16 @@ void dnqs_destroy(dnqs_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->aux) {
+        (void)hipStreamSynchronize(ctx->aux);
+        (void)hipStreamDestroy(ctx->aux);
+    }
+    for (int i = 0; i < 16; ++i) {
+        if (ctx->ev_ready[i]) (void)hipEventDestroy(ctx->ev_ready[i]);
+        if (ctx->ev_wdone[i]) (void)hipEventDestroy(ctx->ev_wdone[i]);
+    }
+    for (hipEvent_t e : ctx->ev_fwd)
+        if (e) (void)hipEventDestroy(e);
     for (auto &kv : ctx->ws)
         if (kv.second.p) (void)hipFree(kv.second.p);
     for (auto &s : ctx->slots) {
@@ -912,17 +944,34 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
     TRY(ws_get(ctx, "delta1", (size_t)n * maxw * esz, &dbuf[1]));
     const void *delta = dO;  // delta_l, starting at l = L
     int which = 0;
+    // The weight gradient of layer l and the data gradient delta_{l-1} both read only
+    // delta_l: the weight gradients run on the auxiliary stream, overlapping the chain of
+    // data gradients.  A data gradient that overwrites a delta buffer waits for the weight
+    // gradient that read it; the streams join before db_L is copied.  Not during capture.
+    const bool fork = !ctx->capturing && L < 16;
+    hipStream_t ast = st;
+    if (fork) {
+        if (!ctx->aux) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+        for (int l = 1; l <= L; ++l) {
+            if (!ctx->ev_ready[l]) HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_ready[l], hipEventDisableTiming));
+            if (!ctx->ev_wdone[l]) HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_wdone[l], hipEventDisableTiming));
+        }
+        ast = ctx->aux;
+    }
     for (int l = L; l >= 1; --l) {
-        // [h_{l-1}; 1]^T delta_l -> (dW_l, db_l)
         void *hp = nullptr;
         TRY(ws_get(ctx, l == 1 ? std::string("U") : "h" + std::to_string(l - 1), 1, &hp));
         const int din = w[l - 1], dout = w[l];
-        if (l == L && split) {
-            // occupied-row output layer.  Weight gradient: the dense columns by GEMM
-            // (scattered into place), the sparse orbitals over their entries.  Data
-            // gradient: the dense columns by GEMM, the sparse rows by orbital, summed per
-            // configuration in row order with tanh'.
-            const int eng = gemm_engine(precision, true);
+        const bool os_layer = l == L && split;
+        const int eng = gemm_engine(precision, l == L);
+        // ---- [h_{l-1}; 1]^T delta_l -> (dW_l, db_l), on the auxiliary stream
+        if (fork) {
+            HIPCHK(ctx, hipEventRecord(ctx->ev_ready[l], st));
+            HIPCHK(ctx, hipStreamWaitEvent(ast, ctx->ev_ready[l], 0));
+        }
+        if (os_layer) {
+            // occupied-row output layer: the dense columns by GEMM (scattered into place),
+            // the sparse orbitals over their entries
             if (nd > 0) {
                 float *GD = nullptr;
                 TRY(ws_t(ctx, "os_GD", (size_t)(din + 1) * wd, &GD));
@@ -937,27 +986,67 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
                 g.ldc = wd;
                 g.ones_row = din;
                 const int64_t cnt = (int64_t)(din + 1) * wd;
-                TRY(tuned_launch(ctx, TuneKey{eng, 1, g.M, g.N, g.K}, gemm_candidates(g.M, g.N, g.K, true, false),
-                                 [&](const GemmCfg &c) -> dnqs_status {
-                                     float *partial = nullptr;
-                                     TRY(ws_t(ctx, "splitk", (size_t)cnt * c.splits, &partial));
-                                     GemmArgs gs = g;
-                                     gs.C = partial;
-                                     gs.c_split_stride = cnt;
-                                     launch_gemm(eng, st, gs, false, true, EPI_STORE, c.splits, c.tm);
-                                     CHECK_LAUNCH(ctx);
-                                     launch_reduce_splits(st, partial, c.splits, cnt, GD);
-                                     CHECK_LAUNCH(ctx);
-                                     return DNQS_OK;
-                                 }));
-                launch_os_scatter(st, GD, din, Ne, nd, dout, conn->os_dorb, grad + nv.offW[l]);
+                TRY(tuned_launch(
+                    ctx, TuneKey{eng, 1, g.M, g.N, g.K}, gemm_candidates(g.M, g.N, g.K, true, false),
+                    [&](const GemmCfg &c) -> dnqs_status {
+                        float *partial = nullptr;
+                        TRY(ws_t(ctx, "splitk", (size_t)cnt * c.splits, &partial));
+                        GemmArgs gs = g;
+                        gs.C = partial;
+                        gs.c_split_stride = cnt;
+                        launch_gemm(eng, ast, gs, false, true, EPI_STORE, c.splits, c.tm);
+                        CHECK_LAUNCH(ctx);
+                        launch_reduce_splits(ast, partial, c.splits, cnt, GD);
+                        CHECK_LAUNCH(ctx);
+                        return DNQS_OK;
+                    },
+                    ast));
+                launch_os_scatter(ast, GD, din, Ne, nd, dout, conn->os_dorb, grad + nv.offW[l]);
                 CHECK_LAUNCH(ctx);
             }
             float *part_w = nullptr;
             TRY(ws_t(ctx, "os_wpart", (size_t)std::max<int64_t>(conn->os_nitems, 1) * (din + 1) * Ne, &part_w));
-            launch_os_wgrad(st, (const float *)hp, din, Ne, conn->os_items, conn->os_nitems, conn->os_ex, og.dOsp,
+            launch_os_wgrad(ast, (const float *)hp, din, Ne, conn->os_items, conn->os_nitems, conn->os_ex, og.dOsp,
                             part_w, conn->os_dpos, conn->os_ifirst, conn->os_icount, No, grad + nv.offW[l]);
             CHECK_LAUNCH(ctx);
+        } else {
+            GemmArgs g{};
+            g.M = din + 1;
+            g.N = dout;
+            g.K = (int)n;
+            g.A = hp;
+            g.lda = din;
+            g.B = delta;
+            g.ldb = dout;
+            g.ldc = dout;
+            g.ones_row = din;
+            const int64_t cnt = (int64_t)(din + 1) * dout;
+            TRY(tuned_launch(
+                ctx, TuneKey{eng, 1, g.M, g.N, g.K}, gemm_candidates(g.M, g.N, g.K, true, false),
+                [&](const GemmCfg &c) -> dnqs_status {
+                    float *partial = nullptr;
+                    TRY(ws_t(ctx, "splitk", (size_t)cnt * c.splits, &partial));
+                    GemmArgs gs = g;
+                    gs.C = partial;
+                    gs.c_split_stride = cnt;
+                    launch_gemm(eng, ast, gs, false, true, EPI_STORE, c.splits, c.tm);
+                    CHECK_LAUNCH(ctx);
+                    launch_reduce_splits(ast, partial, c.splits, cnt, grad + nv.offW[l]);
+                    CHECK_LAUNCH(ctx);
+                    return DNQS_OK;
+                },
+                ast));
+        }
+        if (fork) HIPCHK(ctx, hipEventRecord(ctx->ev_wdone[l], ast));
+        if (l == 1) break;
+        // ---- delta_{l-1} = (delta_l W_l^T) * (1 - h_{l-1}^2), on the context stream, into
+        // the buffer that held delta_{l+1} (read by the weight gradient of layer l + 1)
+        void *dnext = dbuf[which];
+        which ^= 1;
+        if (fork && l < L) HIPCHK(ctx, hipStreamWaitEvent(st, ctx->ev_wdone[l + 1], 0));
+        if (os_layer) {
+            // occupied-row output layer: the dense columns by GEMM, the sparse rows by
+            // orbital, summed per configuration in row order with tanh'
             float *dD = nullptr;
             if (nd > 0) {
                 float *WD = nullptr;  // [W_D; b_D] from this call's forward
@@ -990,66 +1079,35 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
             TRY(ws_t(ctx, "os_WT", (size_t)din * dout, &WT));
             TRY(ws_t(ctx, "os_C", (size_t)std::max<int64_t>(conn->os_ne, 1) * din, &Cr));
             launch_os_trans_w(st, theta + nv.offW[l], din, dout, WT);
-            void *dnext = dbuf[which];
-            which ^= 1;
             launch_os_dgrad(st, n, Ne, din, WT, conn->os_tiles, conn->os_ntiles, og.dOsp, Cr, dD, conn->os_idx,
                             (const float *)hp, (float *)dnext);
             CHECK_LAUNCH(ctx);
-            delta = dnext;
-            continue;
+        } else {
+            GemmArgs d{};
+            d.M = (int)n;
+            d.N = din;
+            d.K = dout;
+            d.A = delta;
+            d.lda = dout;
+            d.B = theta + nv.offW[l];
+            d.ldb = dout;
+            d.C = dnext;
+            d.ldc = din;
+            d.act = hp;
+            d.ldact = din;
+            d.ones_row = -1;
+            const int deng = gemm_engine(precision, l == L);
+            if (deng == 1) TRY(weight_planes(ctx, "wp" + std::to_string(l), theta + nv.offW[l], din, dout, false, d));
+            TRY(tuned_launch(ctx, TuneKey{deng, 2, d.M, d.N, d.K}, gemm_candidates(d.M, d.N, d.K, false, false),
+                             [&](const GemmCfg &c) -> dnqs_status {
+                                 launch_gemm(deng, st, d, true, false, EPI_DTANH, 1, c.tm);
+                                 CHECK_LAUNCH(ctx);
+                                 return DNQS_OK;
+                             }));
         }
-        GemmArgs g{};
-        g.M = din + 1;
-        g.N = dout;
-        g.K = (int)n;
-        g.A = hp;
-        g.lda = din;
-        g.B = delta;
-        g.ldb = dout;
-        g.ldc = dout;
-        g.ones_row = din;
-        const int64_t cnt = (int64_t)(din + 1) * dout;
-        const int eng = gemm_engine(precision, l == L);
-        TRY(tuned_launch(ctx, TuneKey{eng, 1, g.M, g.N, g.K}, gemm_candidates(g.M, g.N, g.K, true, false),
-                         [&](const GemmCfg &c) -> dnqs_status {
-                             float *partial = nullptr;
-                             TRY(ws_t(ctx, "splitk", (size_t)cnt * c.splits, &partial));
-                             GemmArgs gs = g;
-                             gs.C = partial;
-                             gs.c_split_stride = cnt;
-                             launch_gemm(eng, st, gs, false, true, EPI_STORE, c.splits, c.tm);
-                             CHECK_LAUNCH(ctx);
-                             launch_reduce_splits(st, partial, c.splits, cnt, grad + nv.offW[l]);
-                             CHECK_LAUNCH(ctx);
-                             return DNQS_OK;
-                         }));
-        if (l == 1) break;
-        // delta_{l-1} = (delta_l W_l^T) * (1 - h_{l-1}^2)
-        void *dnext = dbuf[which];
-        which ^= 1;
-        GemmArgs d{};
-        d.M = (int)n;
-        d.N = din;
-        d.K = dout;
-        d.A = delta;
-        d.lda = dout;
-        d.B = theta + nv.offW[l];
-        d.ldb = dout;
-        d.C = dnext;
-        d.ldc = din;
-        d.act = hp;
-        d.ldact = din;
-        d.ones_row = -1;
-        const int deng = gemm_engine(precision, l == L);
-        if (deng == 1) TRY(weight_planes(ctx, "wp" + std::to_string(l), theta + nv.offW[l], din, dout, false, d));
-        TRY(tuned_launch(ctx, TuneKey{deng, 2, d.M, d.N, d.K}, gemm_candidates(d.M, d.N, d.K, false, false),
-                         [&](const GemmCfg &c) -> dnqs_status {
-                             launch_gemm(deng, st, d, true, false, EPI_DTANH, 1, c.tm);
-                             CHECK_LAUNCH(ctx);
-                             return DNQS_OK;
-                         }));
         delta = dnext;
     }
+    if (fork) HIPCHK(ctx, hipStreamWaitEvent(st, ctx->ev_wdone[1], 0));  // join: every weight gradient is done
     // dPhi0 equals db_L (Phi0 and b_L enter A(x) the same way)
     launch_copy_f32(st, grad + nv.offb[L], grad + nv.offPhi0, (int64_t)No * Ne);
     CHECK_LAUNCH(ctx);
