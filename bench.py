@@ -121,8 +121,10 @@ def bench_sweep(args, dnqs, synth, torch):
             t = ctx.timing_get("egrad")[0] / max(args.steps, 3)
             peak = FP32_PEAK_TFLOPS if name == "fp32" else BF16_PEAK_TFLOPS / 3.0
             tf = n * fl / (t * 1e-3) / 1e12
+            # flops of the full-width network (gemm_flops): with the occupied-row output
+            # layer the GEMMs do less work, so this is a dense-equivalent rate
             row[name] = {"energy_and_grad_ms": t, "amps_grads_per_s": n / (t * 1e-3), "E": r["E"].item(),
-                         "gemm_tflops_fp32_equiv": tf, "gemm_peak_tflops": peak, "gemm_frac_upper": tf / peak}
+                         "dense_equiv_gemm_tflops": tf, "gemm_peak_tflops": peak, "dense_equiv_frac": tf / peak}
         if n * nexc <= args.sweep_pt2_max:
             r = ctx.energy_and_grad(wl.widths, theta, conn, want_grad=False, precision=getattr(dnqs, PRECISIONS[args.precision]))
             ctx.timing_reset()
