@@ -164,7 +164,15 @@ __global__ void k_reduce_splits_grouped(const float *__restrict__ part, const in
     const int z0 = zoff[g], z1 = zoff[g + 1];
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
         float s = 0.0f;
-        for (int z = z0; z < z1; ++z) s += part[(int64_t)z * cnt + i];
+        int z = z0;
+        for (; z + 8 <= z1; z += 8) {  // eight reads in flight, added in z order
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(z + u) * cnt + i];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; z < z1; ++z) s += part[(int64_t)z * cnt + i];
         out[i] = s;
     }
 }

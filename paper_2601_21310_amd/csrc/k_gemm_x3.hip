@@ -183,10 +183,177 @@ __device__ __forceinline__ void pstore(bf16_t (*Hs)[XLD], bf16_t (*Ls)[XLD], con
     *(bf16x8_t *)&Ls[n][k + 8] = r.l1;
 }
 
+// ---------------------------------------------------------------- clamped-load form
+// The bounds-checked loads above branch per lane, and the skipped prefetches past the
+// last step branch per workgroup; the compiler then has to wait for every load in flight
+// (vmcnt(0)) before each LDS staging, which takes away the second step of lookahead.  In
+// the clamped form every thread issues the same vector loads for every step: a row past
+// the operand reads a valid row, k past kend reads k = 0, and the staging zeroes what is
+// out of range.  It needs (checked on the host) k0 % 16 == 0, kend % 4 == 0 (% 8 for the
+// pre-split planes), ld % 4 == 0 (% 8), 16-byte aligned operands, and in the
+// row-contiguous form rows_ld % 4 == 0, so that each 16-byte load is either wholly
+// in range or wholly out.  The tile is spread over all 256 threads: PER = ROWS*32/256
+// values each (16 at 128 rows, 8 at 64).
+//   KC:  thread = (row t/(32/PER), k PER*(t%(32/PER)) .. +PER-1), r[j] = P[row][k+j]
+//   !KC: thread = (rows 4*(t/(128/PER)) .. +3, k (PER/4)*(t%(128/PER)) .. +PER/4-1),
+//        r[4*kk + rr] = P[k+kk][row+rr]
+template <bool KC, int ROWS>
+__device__ __forceinline__ void xload_cl(const float *__restrict__ P, int64_t ld, int r0, int rows_ld, int k0,
+                                         int kend, float (&r)[16]) {
+    constexpr int PER = ROWS * XBK / 256;
+    const int t = threadIdx.x;
+    if (KC) {
+        constexpr int TPR = XBK / PER;
+        const int row = r0 + t / TPR, k = k0 + (t % TPR) * PER;
+        const int rc = row < rows_ld ? row : rows_ld - 1;
+        const float *prow = P + (int64_t)rc * ld;
+#pragma unroll
+        for (int q = 0; q < PER / 4; ++q) {
+            const int kq = k + 4 * q;
+            const v4f_x u = *(const v4f_x *)(prow + (kq < kend ? kq : 0));
+            r[4 * q + 0] = u[0];
+            r[4 * q + 1] = u[1];
+            r[4 * q + 2] = u[2];
+            r[4 * q + 3] = u[3];
+        }
+    } else {
+        constexpr int KPT = PER / 4, TPG = XBK / KPT;
+        const int row = r0 + 4 * (t / TPG), k = k0 + KPT * (t % TPG);
+        const int rc = row < rows_ld ? row : 0;
+#pragma unroll
+        for (int kk = 0; kk < KPT; ++kk) {
+            const int kc = k + kk < kend ? k + kk : 0;
+            const v4f_x u = *(const v4f_x *)(P + (int64_t)kc * ld + rc);
+            r[4 * kk + 0] = u[0];
+            r[4 * kk + 1] = u[1];
+            r[4 * kk + 2] = u[2];
+            r[4 * kk + 3] = u[3];
+        }
+    }
+}
+
+// Stage a clamped-form tile: zero what lies past rows_ld or kend, ones in row `ones`,
+// split into the hi / lo LDS arrays.
+template <bool KC, int ROWS>
+__device__ __forceinline__ void xstore_cl(bf16_t (*Hs)[XLD], bf16_t (*Ls)[XLD], const float (&r)[16], int r0,
+                                          int rows_ld, int ones, int k0, int kend) {
+    constexpr int PER = ROWS * XBK / 256;
+    const int t = threadIdx.x;
+    // a tile wholly in range (the common case, uniform over the workgroup) is split as is
+    if (r0 + ROWS <= rows_ld && k0 + XBK <= kend && (ones < r0 || ones >= r0 + ROWS)) {
+        if (KC) {
+            constexpr int TPR = XBK / PER;
+            const int lr = t / TPR, lk = (t % TPR) * PER;
+#pragma unroll
+            for (int q = 0; q < PER / 8; ++q) {
+                bf16x8_t h, l;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    bf16_t a, b;
+                    split_bf16(r[8 * q + j], a, b);
+                    h[j] = a;
+                    l[j] = b;
+                }
+                *(bf16x8_t *)&Hs[lr][lk + 8 * q] = h;
+                *(bf16x8_t *)&Ls[lr][lk + 8 * q] = l;
+            }
+        } else {
+            constexpr int KPT = PER / 4, TPG = XBK / KPT;
+            const int lr = 4 * (t / TPG), lk = KPT * (t % TPG);
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                typedef __bf16 bfk_t __attribute__((ext_vector_type(KPT)));
+                bfk_t h, l;
+#pragma unroll
+                for (int kk = 0; kk < KPT; ++kk) {
+                    bf16_t a, b;
+                    split_bf16(r[4 * kk + rr], a, b);
+                    h[kk] = a;
+                    l[kk] = b;
+                }
+                *(bfk_t *)&Hs[lr + rr][lk] = h;
+                *(bfk_t *)&Ls[lr + rr][lk] = l;
+            }
+        }
+        return;
+    }
+    if (KC) {
+        constexpr int TPR = XBK / PER;
+        const int lr = t / TPR, lk = (t % TPR) * PER;
+        const int row = r0 + lr, k = k0 + lk;
+        const bool rin = row < rows_ld, one = row == ones;
+#pragma unroll
+        for (int q = 0; q < PER / 8; ++q) {
+            bf16x8_t h, l;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const bool kin = k + 8 * q + j < kend;
+                const float v = one ? (kin ? 1.0f : 0.0f) : (rin && kin ? r[8 * q + j] : 0.0f);
+                bf16_t a, b;
+                split_bf16(v, a, b);
+                h[j] = a;
+                l[j] = b;
+            }
+            *(bf16x8_t *)&Hs[lr][lk + 8 * q] = h;
+            *(bf16x8_t *)&Ls[lr][lk + 8 * q] = l;
+        }
+    } else {
+        constexpr int KPT = PER / 4, TPG = XBK / KPT;
+        const int lr = 4 * (t / TPG), lk = KPT * (t % TPG);
+        const int row = r0 + lr, k = k0 + lk;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const bool rin = row + rr < rows_ld, one = row + rr == ones;
+            typedef __bf16 bfk_t __attribute__((ext_vector_type(KPT)));
+            bfk_t h, l;
+#pragma unroll
+            for (int kk = 0; kk < KPT; ++kk) {
+                const bool kin = k + kk < kend;
+                const float v = one ? (kin ? 1.0f : 0.0f) : (rin && kin ? r[4 * kk + rr] : 0.0f);
+                bf16_t a, b;
+                split_bf16(v, a, b);
+                h[kk] = a;
+                l[kk] = b;
+            }
+            *(bfk_t *)&Hs[lr + rr][lk] = h;
+            *(bfk_t *)&Ls[lr + rr][lk] = l;
+        }
+    }
+}
+
+// Clamped form of pload / pstore (conditions as for xload_cl, with ld % 8 == 0).
+__device__ __forceinline__ void pload_cl(const bf16_t *__restrict__ hi, const bf16_t *__restrict__ lo, int64_t ld,
+                                         int n0, int N, int k0, int kend, PreTile &r) {
+    const int t = threadIdx.x;
+    const int n = n0 + (t >> 1), k = k0 + (t & 1) * 16;
+    const int64_t nrow = (int64_t)(n < N ? n : N - 1) * ld;
+    const int64_t o0 = nrow + (k < kend ? k : 0), o1 = nrow + (k + 8 < kend ? k + 8 : 0);
+    r.h0 = *(const bf16x8_t *)(hi + o0);
+    r.h1 = *(const bf16x8_t *)(hi + o1);
+    r.l0 = *(const bf16x8_t *)(lo + o0);
+    r.l1 = *(const bf16x8_t *)(lo + o1);
+}
+
+__device__ __forceinline__ void pstore_cl(bf16_t (*Hs)[XLD], bf16_t (*Ls)[XLD], const PreTile &r, int n0, int N,
+                                          int k0, int kend) {
+    const int t = threadIdx.x;
+    const int n = t >> 1, k = (t & 1) * 16;
+    if (n0 + XBN <= N && k0 + XBK <= kend) {
+        pstore(Hs, Ls, r);
+        return;
+    }
+    const bool in0 = n0 + n < N && k0 + k < kend, in1 = n0 + n < N && k0 + k + 8 < kend;
+    const bf16x8_t z = {};
+    *(bf16x8_t *)&Hs[n][k] = in0 ? r.h0 : z;
+    *(bf16x8_t *)&Hs[n][k + 8] = in1 ? r.h1 : z;
+    *(bf16x8_t *)&Ls[n][k] = in0 ? r.l0 : z;
+    *(bf16x8_t *)&Ls[n][k + 8] = in1 ? r.l1 : z;
+}
+
 // AK: A k-contiguous (A[m*lda + k]) else A[k*lda + m].  BNC: B n-contiguous
 // (B[k*ldb + n], i.e. row-contiguous in the [n][k] view) else B[n*ldb + k].  BPRE: B
-// from the pre-split planes g.bsplit (BNC ignored).
-template <bool AK, bool BNC, int EPI, int TM, bool BPRE>
+// from the pre-split planes g.bsplit (BNC ignored).  CL: the clamped-load form.
+template <bool AK, bool BNC, int EPI, int TM, bool BPRE, bool CL>
 __global__ __launch_bounds__(256, 2) void k_gemm_x3(GemmArgs g0) {
     constexpr int WI = TM / 64;
     GemmArgs g = g0;
@@ -211,7 +378,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_x3(GemmArgs g0) {
     }
     if (kend > g.K) kend = g.K;
     const float *A = (const float *)g.A;
-    const float *B = (const float *)g.B;
+    // the clamped form has no per-tile B: the kernel argument keeps it a global pointer
+    const float *B = (const float *)(CL ? g0.B : g.B);
     const bf16_t *Bhi = (const bf16_t *)g.bsplit;
     const bf16_t *Blo = BPRE ? Bhi + g.bs_plane : nullptr;
     const int mload = g.ones_row >= 0 ? g.ones_row : g.M;
@@ -233,13 +401,36 @@ __global__ __launch_bounds__(256, 2) void k_gemm_x3(GemmArgs g0) {
     PreTile pb0, pb1;
     auto load = [&](int step, float (&ra)[16], float (&rb)[16], PreTile &pb) {
         const int k0 = kbeg + step * XBK;
+        if (CL) {
+            __builtin_amdgcn_sched_barrier(0);
+            xload_cl<AK, TM>(A, g.lda, m0, mload, k0, kend, ra);
+            if (BPRE)
+                pload_cl(Bhi, Blo, g.ldbs, n0, g.N, k0, kend, pb);
+            else
+                xload_cl<!BNC, XBN>(B, g.ldb, n0, g.N, k0, kend, rb);
+            // keep each step's loads together and in program order, so that the wait
+            // before a staging covers only the older step
+            __builtin_amdgcn_sched_barrier(0);
+            return;
+        }
         xload<AK, TM>(A, g.lda, m0, mload, g.ones_row, k0, kend, ra);
         if (BPRE)
             pload(Bhi, Blo, g.ldbs, n0, g.N, k0, kend, pb);
         else
             xload<!BNC, XBN>(B, g.ldb, n0, g.N, -1, k0, kend, rb);
     };
-    auto store = [&](int buf, const float (&ra)[16], const float (&rb)[16], const PreTile &pb) {
+    auto store = [&](int buf, int step, const float (&ra)[16], const float (&rb)[16], const PreTile &pb) {
+        if (CL) {
+            __builtin_amdgcn_sched_barrier(0);
+            const int k0 = kbeg + step * XBK;
+            xstore_cl<AK, TM>(Ah[buf], Al[buf], ra, m0, mload, g.ones_row, k0, kend);
+            if (BPRE)
+                pstore_cl(Bh[buf], Bl[buf], pb, n0, g.N, k0, kend);
+            else
+                xstore_cl<!BNC, XBN>(Bh[buf], Bl[buf], rb, n0, g.N, -1, k0, kend);
+            __builtin_amdgcn_sched_barrier(0);
+            return;
+        }
         xstore<AK, TM>(Ah[buf], Al[buf], ra);
         if (BPRE)
             pstore(Bh[buf], Bl[buf], pb);
@@ -280,28 +471,32 @@ __global__ __launch_bounds__(256, 2) void k_gemm_x3(GemmArgs g0) {
         }
     };
     const int nk = kend > kbeg ? (kend - kbeg + XBK - 1) / XBK : 0;
-    // step s lives in register set s % 2 and LDS buffer s % 2
+    // step s lives in register set s % 2 and LDS buffer s % 2.  In the clamped form the
+    // loads and stagings past the last step run too (they read valid addresses and stage
+    // zeros), so that every path through the loop issues the same loads.
     if (nk > 0) {
         load(0, ra0, rb0, pb0);
-        store(0, ra0, rb0, pb0);
-        if (nk > 1) load(1, ra1, rb1, pb1);
-        if (nk > 2) load(2, ra0, rb0, pb0);
+        store(0, 0, ra0, rb0, pb0);
+        if (CL || nk > 1) load(1, ra1, rb1, pb1);
+        if (CL || nk > 2) load(2, ra0, rb0, pb0);
     }
     __syncthreads();
     for (int it = 0; it < nk; it += 2) {
         // even step it: LDS buffer 0; stage step it+1 (set 1) into buffer 1
         compute(0);
-        if (it + 1 < nk) {
-            store(1, ra1, rb1, pb1);
-            if (it + 3 < nk) load(it + 3, ra1, rb1, pb1);
+        if (CL || it + 1 < nk) {
+            store(1, it + 1, ra1, rb1, pb1);
+            if (CL || it + 3 < nk) load(it + 3, ra1, rb1, pb1);
         }
         __syncthreads();
-        if (it + 1 >= nk) break;
+        // the clamped form runs an odd nk's last pair through: the step past the end was
+        // staged as zeros and adds exact zeros, and the loop body stays one block
+        if (!CL && it + 1 >= nk) break;
         // odd step it+1: LDS buffer 1; stage step it+2 (set 0) into buffer 0
         compute(1);
-        if (it + 2 < nk) {
-            store(0, ra0, rb0, pb0);
-            if (it + 4 < nk) load(it + 4, ra0, rb0, pb0);
+        if (CL || it + 2 < nk) {
+            store(0, it + 2, ra0, rb0, pb0);
+            if (CL || it + 4 < nk) load(it + 4, ra0, rb0, pb0);
         }
         __syncthreads();
     }
@@ -313,6 +508,18 @@ __global__ __launch_bounds__(256, 2) void k_gemm_x3(GemmArgs g0) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int col = n0 + wn + j * 32 + li;
+            // tanh' factors first, as one batch of in-range loads (clamped indices), so
+            // that the 16 reads overlap instead of each waiting before its store
+            float fac[16];
+            if (EPI == EPI_DTANH) {
+                const int cc = col < g.N ? col : g.N - 1;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int row = m0 + wm + i * 32 + 8 * (r >> 2) + lrow + (r & 3);
+                    const float hv = act[(int64_t)(row < g.M ? row : g.M - 1) * g.ldact + cc];
+                    fac[r] = 1.0f - hv * hv;
+                }
+            }
             if (col >= g.N) continue;
             const float bias = (EPI == EPI_BIAS || EPI == EPI_BIAS_TANH) ? g.bias[col] : 0.0f;
 #pragma unroll
@@ -322,19 +529,35 @@ __global__ __launch_bounds__(256, 2) void k_gemm_x3(GemmArgs g0) {
                 float v = acc[i][j][r];
                 if (EPI == EPI_BIAS) v += bias;
                 if (EPI == EPI_BIAS_TANH) v = tanhf(v + bias);
-                if (EPI == EPI_DTANH) {
-                    const float hv = act[(int64_t)row * g.ldact + col];
-                    v *= (1.0f - hv * hv);
-                }
+                if (EPI == EPI_DTANH) v *= fac[r];
                 C[(int64_t)row * g.ldc + col] = v;
             }
         }
 }
 
+static bool al16(const void *p) { return (((uintptr_t)p) & 15) == 0; }
+
+// Whether the clamped-load form applies (its conditions are stated above xload_cl).
+template <bool AK, bool BNC, bool BPRE>
+static bool clamped_ok(const GemmArgs &g) {
+    if (g.ksplit || g.tile_pid || g.k_chunk % XBK) return false;
+    const int mload = g.ones_row >= 0 ? g.ones_row : g.M;
+    if (mload < 1 || g.N < 1 || g.K < 1) return false;
+    // k-contiguous operands need kend % 4 == 0 (pre-split planes % 8); chunks are whole steps
+    if ((AK || (!BPRE && !BNC)) && g.K % 4) return false;
+    if (BPRE && g.K % 8) return false;
+    if (g.lda % 4 || !al16(g.A) || (!AK && mload % 4)) return false;
+    if (BPRE) return g.ldbs % 8 == 0 && g.bs_plane % 8 == 0 && al16(g.bsplit);
+    return g.ldb % 4 == 0 && al16(g.B) && (!BNC || g.N % 4 == 0);
+}
+
 template <bool AK, bool BNC, int EPI, int TM, bool BPRE>
 static void launch_x(hipStream_t st, GemmArgs g, int splits) {
     const int tiles = ((g.M + TM - 1) / TM) * ((g.N + XBN - 1) / XBN);
-    hipLaunchKernelGGL((k_gemm_x3<AK, BNC, EPI, TM, BPRE>), dim3(tiles, 1, splits), dim3(256), 0, st, g);
+    if (clamped_ok<AK, BNC, BPRE>(g))
+        hipLaunchKernelGGL((k_gemm_x3<AK, BNC, EPI, TM, BPRE, true>), dim3(tiles, 1, splits), dim3(256), 0, st, g);
+    else
+        hipLaunchKernelGGL((k_gemm_x3<AK, BNC, EPI, TM, BPRE, false>), dim3(tiles, 1, splits), dim3(256), 0, st, g);
 }
 
 void launch_gemm_x3(hipStream_t st, const GemmArgs &g0, bool a_kcontig, bool b_ncontig, int epi, int splits,

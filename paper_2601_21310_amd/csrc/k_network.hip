@@ -241,6 +241,18 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g0) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int col = n0 + wn + j * 32 + li;
+            // tanh' factors first, as one batch of in-range loads (clamped indices), so
+            // that the 16 reads overlap instead of each waiting before its store
+            float fac[16];
+            if (EPI == EPI_DTANH) {
+                const int cc = col < g.N ? col : g.N - 1;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int row = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * lk + (r & 3);
+                    const float hv = act[(int64_t)(row < g.M ? row : g.M - 1) * g.ldact + cc];
+                    fac[r] = 1.0f - hv * hv;
+                }
+            }
             if (col >= g.N) continue;
             float bias = (EPI == EPI_BIAS || EPI == EPI_BIAS_TANH) ? g.bias[col] : 0.0f;
 #pragma unroll
@@ -250,10 +262,7 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g0) {
                 float v = acc[i][j][r];
                 if (EPI == EPI_BIAS) v += bias;
                 if (EPI == EPI_BIAS_TANH) v = tanhf(v + bias);
-                if (EPI == EPI_DTANH) {
-                    float hv = act[(int64_t)row * g.ldact + col];
-                    v *= (1.0f - hv * hv);
-                }
+                if (EPI == EPI_DTANH) v *= fac[r];
                 C[(int64_t)row * g.ldc + col] = v;
             }
         }
@@ -301,8 +310,18 @@ __global__ void k_reduce_splits(const float *__restrict__ part, int splits, int6
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; i < count; i += stride) {
+        // eight partials read together, then added in split order (the same sum as a
+        // plain loop over z, without one memory round trip per split)
         float s = 0.0f;
-        for (int z = 0; z < splits; ++z) s += part[(int64_t)z * count + i];
+        int z = 0;
+        for (; z + 8 <= splits; z += 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(z + u) * count + i];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; z < splits; ++z) s += part[(int64_t)z * count + i];
         out[i] = s;
     }
 }
