@@ -207,24 +207,33 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Off-diagonal part of row x of H_SS times psi by one wave (sum of the lanes' partial
-// sums; the caller reduces across the wave).  Four independent FP64 partial sums per
-// lane, so that four column loads and psi gathers are in flight at once; fixed order.
+// sums; the caller reduces across the wave).  Eight independent FP64 partial sums per
+// lane, combined in a fixed order.
 __device__ __forceinline__ double row_dot_lane(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                                                const float *__restrict__ val, const double *__restrict__ psi,
                                                int64_t x, int lane) {
+    // Eight elements per lane and step: the 16 index/value reads go out together, then the
+    // 8 psi gathers, so a row of a few hundred elements costs a few memory round trips.
+    // Slots past the row end read the row's first element and add 0.
     const int64_t b = row_ptr[x], e = row_ptr[x + 1];
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int64_t j = b + lane;
-    for (; j + 3 * kWave < e; j += 4 * kWave) {
-        const int32_t c0 = col[j], c1 = col[j + kWave], c2 = col[j + 2 * kWave], c3 = col[j + 3 * kWave];
-        const float v0 = val[j], v1 = val[j + kWave], v2 = val[j + 2 * kWave], v3 = val[j + 3 * kWave];
-        s0 += (double)v0 * psi[c0];
-        s1 += (double)v1 * psi[c1];
-        s2 += (double)v2 * psi[c2];
-        s3 += (double)v3 * psi[c3];
+    double s[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] = 0.0;
+    for (int64_t j0 = b + lane; j0 < e; j0 += 8 * kWave) {
+        int32_t c[8];
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t j = j0 + u * kWave;
+            const int64_t jj = j < e ? j : b;
+            c[u] = col[jj];
+            v[u] = val[jj];
+            if (j >= e) v[u] = 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s[u] += (double)v[u] * psi[c[u]];
     }
-    for (; j < e; j += kWave) s0 += (double)val[j] * psi[col[j]];
-    return (s0 + s1) + (s2 + s3);
+    return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
 __device__ __forceinline__ float wave_sum_f(float v) {

@@ -44,6 +44,15 @@ __device__ __forceinline__ int xcd_remap_x(int L, int total) {
     return (L % nx) * per + (L / nx);
 }
 
+// tanh for the mixed form's hidden layers: tanh x = sign(x) (1 - e) / (1 + e) with
+// e = exp(-2|x|) = 2^(-2 log2(e) |x|) in (0, 1], on the hardware exp2 and reciprocal
+// (about 1 ulp each), so the absolute error stays near 1e-7, well below the 2^-17
+// relative error of the split products that consume it.
+__device__ __forceinline__ float tanh_mixed(float x) {
+    const float e = __builtin_amdgcn_exp2f(-2.8853900817779268f * fabsf(x));
+    return copysignf((1.0f - e) * __builtin_amdgcn_rcpf(1.0f + e), x);
+}
+
 __device__ __forceinline__ void split_bf16(float x, bf16_t &hi, bf16_t &lo) {
     hi = (bf16_t)x;
     lo = (bf16_t)(x - (float)hi);
@@ -528,7 +537,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_x3(GemmArgs g0) {
                 if (row >= g.M) continue;
                 float v = acc[i][j][r];
                 if (EPI == EPI_BIAS) v += bias;
-                if (EPI == EPI_BIAS_TANH) v = tanhf(v + bias);
+                if (EPI == EPI_BIAS_TANH) v = tanh_mixed(v + bias);
                 if (EPI == EPI_DTANH) v *= fac[r];
                 C[(int64_t)row * g.ldc + col] = v;
             }

@@ -35,18 +35,30 @@ __global__ __launch_bounds__(256) void k_embed(const uint64_t *__restrict__ dets
         }
         const uint64_t a = dets[2 * x], b = dets[2 * x + 1];
         for (int c = threadIdx.x; c < d1; c += blockDim.x) {
+            // rows of the occupied spin-orbitals, ascending (alpha, then beta), eight
+            // reads in flight at a time (an exhausted slot reads row 0 and is not added)
             float s = b1[c];
             uint64_t t = a;
-            while (t) {
-                int p = ctz64(t);
-                t &= t - 1;
-                s += W1[(size_t)p * d1 + c];
-            }
-            t = b;
-            while (t) {
-                int p = ctz64(t);
-                t &= t - 1;
-                s += W1[(size_t)(M + p) * d1 + c];
+            int base = 0;
+            for (int half = 0; half < 2; ++half) {
+                while (t) {
+                    int pp[8];
+                    bool ok[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        ok[u] = t != 0;
+                        pp[u] = ok[u] ? base + ctz64(t) : 0;
+                        t &= t - 1;
+                    }
+                    float v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) v[u] = W1[(size_t)pp[u] * d1 + c];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (ok[u]) s += v[u];
+                }
+                t = b;
+                base = M;
             }
             h1[x * d1 + c] = tanhf(s);
         }

@@ -147,72 +147,109 @@ __global__ void k_os_gather_w(const float *__restrict__ W, const float *__restri
     WD[i] = h < din ? W[(int64_t)h * width + col] : bias[col];
 }
 
-// Entry tiles: {orbital, first entry, count <= kOsTile}.  Four lanes per entry split the
-// hidden dimension (lane q takes h = 16 i + 4 q .. + 3, so the four lanes of an entry read
-// 64 contiguous bytes per load), each keeps all NP >= Ne outputs, and the four partial
-// sums are added by two shuffles; W_L's column block of the orbital is staged in LDS as
-// [din][NP].
-constexpr int kOsTile = 64;
+// Entry tiles: {orbital, first entry, count <= kOsTile}.  A tile is a small dense product,
+// [entries x din] (the entries' h_{L-1} rows) times the orbital's [din x Ne] column block
+// of W_L, done on v_mfma_f32_16x16x4f32: each wave takes 16 entries, NP/16 output blocks
+// of 16 columns.  A workgroup takes kOsFwdTiles consecutive tiles (the tiles of one
+// orbital are consecutive) and stages the column block in LDS once per orbital run, as
+// [din][NP + 4] (the padding puts the four k rows one B fragment reads on distinct banks).
+// MFMA 16x16x4 lane layout: A[i][k] at lane i + 16 k, B[k][j] at lane j + 16 k, D[i][j] at
+// lane j + 16 (i / 4), element i % 4.  Each lane loads four consecutive h values of its
+// entry (64 contiguous bytes per entry and K step of 16), so MFMA m of a step takes
+// k = k0 + 4 (lane / 16) + m: the k order within a dot product is permuted, which only
+// reorders the FP32 sum.
+constexpr int kOsTile = 64, kOsFwdTiles = 4;
+
+typedef float v4f_os __attribute__((ext_vector_type(4)));
+
+template <int NP>
+__device__ __forceinline__ void os_stage_w(float *Ws, const float *__restrict__ W, int din, int width, int Ne, int p) {
+    // eight reads in flight per thread (clamped to valid addresses, padding columns zeroed)
+    constexpr int S = NP + 4;
+    const int tot = din * NP;
+    for (int i0 = threadIdx.x; i0 < tot; i0 += 8 * blockDim.x) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * blockDim.x;
+            const int h = i / NP, c = i % NP;
+            v[u] = W[(int64_t)(h < din ? h : 0) * width + p * Ne + (c < Ne ? c : 0)];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * blockDim.x;
+            if (i < tot) Ws[(i / NP) * S + i % NP] = i % NP < Ne ? v[u] : 0.0f;
+        }
+    }
+}
 
 template <int NP>
 __global__ __launch_bounds__(256) void k_os_fwd(const float *__restrict__ hL, int din, const float *__restrict__ W,
                                                 const float *__restrict__ bias, int width, int Ne,
-                                                const int4 *__restrict__ tiles, const int32_t *__restrict__ ex,
-                                                float *__restrict__ Osp) {
-    extern __shared__ float Ws[];  // [din][NP]
-    const int4 tl = tiles[blockIdx.x];
-    const int p = tl.x;
-    for (int i = threadIdx.x; i < din * NP; i += blockDim.x) {
-        const int h = i / NP, c = i % NP;
-        Ws[i] = c < Ne ? W[(int64_t)h * width + p * Ne + c] : 0.0f;
-    }
-    __syncthreads();
-    const int le = threadIdx.x / 4, q = threadIdx.x % 4;
-    const bool vec = (din & 3) == 0;
-    for (int e0 = 0; e0 < tl.z; e0 += 64) {
-        const int le2 = e0 + le;
-        const bool have = le2 < tl.z;
-        const int64_t e = (int64_t)tl.y + (have ? le2 : 0);
-        const float *hr = hL + (int64_t)ex[e] * din;
-        float acc[NP];
+                                                const int4 *__restrict__ tiles, int64_t ntiles,
+                                                const int32_t *__restrict__ ex, float *__restrict__ Osp) {
+    constexpr int S = NP + 4, JB = NP / 16;
+    extern __shared__ float Ws[];  // [din][S]
+    const int64_t t0 = (int64_t)blockIdx.x * kOsFwdTiles;
+    const int64_t t1 = t0 + kOsFwdTiles < ntiles ? t0 + kOsFwdTiles : ntiles;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, kg = lane >> 4;
+    int staged = -1;
+    for (int64_t t = t0; t < t1; ++t) {
+        const int4 tl = tiles[t];
+        const int p = tl.x;
+        if (p != staged) {  // uniform over the workgroup
+            __syncthreads();
+            os_stage_w<NP>(Ws, W, din, width, Ne, p);
+            __syncthreads();
+            staged = p;
+        }
+        const int le = 16 * wave + li;  // this lane's A row (entry) within the tile
+        // a row past the tile reads the tile's first entry; its outputs are not stored
+        const int64_t e = (int64_t)tl.y + (le < tl.z ? le : 0);
+        const float *hr = hL + (int64_t)ex[e] * din + 4 * kg;
+        v4f_os acc[JB];
 #pragma unroll
-        for (int c = 0; c < NP; ++c) acc[c] = 0.0f;
-        if (have) {
-#pragma unroll 4
-            for (int h = 4 * q; h < din; h += 16) {
-                float hv[4];
-                if (vec && h + 4 <= din) {
-                    const float4 v = *reinterpret_cast<const float4 *>(hr + h);
-                    hv[0] = v.x;
-                    hv[1] = v.y;
-                    hv[2] = v.z;
-                    hv[3] = v.w;
-                } else {
+        for (int jb = 0; jb < JB; ++jb) acc[jb] = v4f_os{0.0f, 0.0f, 0.0f, 0.0f};
+        if (16 * wave < tl.z) {  // uniform per wave
+            int k0 = 0;
+            for (; k0 + 128 <= din; k0 += 128) {
+                v4f_os a[8];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) hv[r] = h + r < din ? hr[h + r] : 0.0f;
-                }
+                for (int u = 0; u < 8; ++u) a[u] = *reinterpret_cast<const v4f_os *>(hr + k0 + 16 * u);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    if (h + r >= din) break;
-                    const float4 *w4 = reinterpret_cast<const float4 *>(Ws + (h + r) * NP);
+                for (int u = 0; u < 8; ++u)
 #pragma unroll
-                    for (int c4 = 0; c4 < NP / 4; ++c4) {
-                        const float4 w = w4[c4];
-                        acc[4 * c4 + 0] = fmaf(hv[r], w.x, acc[4 * c4 + 0]);
-                        acc[4 * c4 + 1] = fmaf(hv[r], w.y, acc[4 * c4 + 1]);
-                        acc[4 * c4 + 2] = fmaf(hv[r], w.z, acc[4 * c4 + 2]);
-                        acc[4 * c4 + 3] = fmaf(hv[r], w.w, acc[4 * c4 + 3]);
+                    for (int m = 0; m < 4; ++m) {
+                        const float *wr = Ws + (k0 + 16 * u + 4 * kg + m) * S + li;
+#pragma unroll
+                        for (int jb = 0; jb < JB; ++jb)
+                            acc[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][m], wr[16 * jb], acc[jb], 0, 0, 0);
                     }
+            }
+            for (; k0 < din; k0 += 16) {
+                const v4f_os av = *reinterpret_cast<const v4f_os *>(hr + k0);
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const float *wr = Ws + (k0 + 4 * kg + m) * S + li;
+#pragma unroll
+                    for (int jb = 0; jb < JB; ++jb)
+                        acc[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[m], wr[16 * jb], acc[jb], 0, 0, 0);
                 }
             }
         }
 #pragma unroll
-        for (int c = 0; c < NP; ++c) {
-            acc[c] += __shfl_xor(acc[c], 1, 4);
-            acc[c] += __shfl_xor(acc[c], 2, 4);
+        for (int jb = 0; jb < JB; ++jb) {
+            const int col = 16 * jb + li;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int er = 16 * wave + 4 * kg + r;
+                if (er < tl.z && col < Ne) {
+                    const int64_t ee = (int64_t)tl.y + er;
+                    Osp[ee * Ne + col] = bias[p * Ne + col] + acc[jb][r];
+                }
+            }
         }
-        if (have && q == 0)
-            for (int c = 0; c < Ne; ++c) Osp[e * Ne + c] = bias[p * Ne + c] + acc[c];
     }
 }
 
@@ -383,18 +420,22 @@ void launch_os_gather_w(hipStream_t st, const float *W, const float *bias, int d
 int os_tile() { return kOsTile; }
 
 // k_os_fwd stages the orbital's din x NP weight block in LDS
-bool os_fwd_fits(int din, int Ne) { return (size_t)din * (Ne <= 16 ? 16 : 32) * sizeof(float) <= 160 * 1024; }
+// (and reads h_{L-1} rows as 16-byte vectors, whole K steps of 16)
+bool os_fwd_fits(int din, int Ne) {
+    return din % 16 == 0 && (size_t)din * (Ne <= 16 ? 20 : 36) * sizeof(float) <= 160 * 1024;
+}
 int os_item() { return kOsItemMax; }
 
 void launch_os_fwd(hipStream_t st, const float *hL, int din, const float *W, const float *bias, int width, int Ne,
                    const int4 *tiles, int64_t ntiles, const int32_t *ex, float *Osp) {
     if (ntiles == 0) return;
+    const unsigned blocks = (unsigned)((ntiles + kOsFwdTiles - 1) / kOsFwdTiles);
     if (Ne <= 16)
-        hipLaunchKernelGGL(k_os_fwd<16>, dim3((unsigned)ntiles), dim3(256), sizeof(float) * din * 16, st, hL, din, W,
-                           bias, width, Ne, tiles, ex, Osp);
+        hipLaunchKernelGGL(k_os_fwd<16>, dim3(blocks), dim3(256), sizeof(float) * din * 20, st, hL, din, W, bias,
+                           width, Ne, tiles, ntiles, ex, Osp);
     else
-        hipLaunchKernelGGL(k_os_fwd<32>, dim3((unsigned)ntiles), dim3(256), sizeof(float) * din * 32, st, hL, din, W,
-                           bias, width, Ne, tiles, ex, Osp);
+        hipLaunchKernelGGL(k_os_fwd<32>, dim3(blocks), dim3(256), sizeof(float) * din * 36, st, hL, din, W, bias,
+                           width, Ne, tiles, ntiles, ex, Osp);
 }
 
 void launch_os_trans_w(hipStream_t st, const float *W, int din, int width, float *WT) {
