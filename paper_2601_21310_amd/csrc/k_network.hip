@@ -72,8 +72,96 @@ __global__ __launch_bounds__(256) void k_embed(const uint64_t *__restrict__ dets
     }
 }
 
+// One weight set: a workgroup takes 64 columns of h1 for kEmbedTileCfg configurations and
+// stages those columns of W1 (N_o x 64) in LDS once, so that W1 is read from L2 once per
+// workgroup rather than once per configuration; each wave takes one configuration at a
+// time (its occupied orbitals are uniform over the wave).  Same sums, same order as
+// k_embed.
+constexpr int kEmbedTileCols = 64, kEmbedTileCfg = 64;
+
+__global__ __launch_bounds__(256) void k_embed_tiled(const uint64_t *__restrict__ dets, int64_t n, int M, int d1,
+                                                     const float *__restrict__ W1, const float *__restrict__ b1,
+                                                     float *__restrict__ h1, float *__restrict__ U) {
+    extern __shared__ float Ws[];  // [N_o][64]
+    __shared__ uint64_t Ds[2 * kEmbedTileCfg];
+    const int No = 2 * M;
+    const int c0 = blockIdx.y * kEmbedTileCols;
+    const int64_t x0 = (int64_t)blockIdx.x * kEmbedTileCfg;
+    // the tile's configurations and W1 columns, eight reads in flight per thread
+    for (int i = threadIdx.x; i < 2 * kEmbedTileCfg; i += blockDim.x)
+        Ds[i] = x0 + i / 2 < n ? dets[2 * x0 + i] : 0ull;
+    const int tot = No * kEmbedTileCols;
+    for (int i0 = threadIdx.x; i0 < tot; i0 += 8 * blockDim.x) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * blockDim.x;
+            const int p = i / kEmbedTileCols, c = c0 + i % kEmbedTileCols;
+            v[u] = W1[(size_t)(i < tot ? p : 0) * d1 + (c < d1 ? c : 0)];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * blockDim.x;
+            if (i < tot) Ws[i] = c0 + i % kEmbedTileCols < d1 ? v[u] : 0.0f;
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x % kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int c = c0 + lane;
+    const float bc = c < d1 ? b1[c] : 0.0f;
+    for (int j = wave; j < kEmbedTileCfg; j += blockDim.x / kWave) {
+        const int64_t x = x0 + j;
+        if (x >= n) break;
+        // the configuration is uniform over the wave: its bit strings in scalar registers
+        const uint64_t a = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(Ds[2 * j] >> 32)) << 32) |
+                           (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)Ds[2 * j]);
+        const uint64_t b = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(Ds[2 * j + 1] >> 32)) << 32) |
+                           (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)Ds[2 * j + 1]);
+        // occupied rows ascending (alpha, then beta), eight LDS reads in flight at a time
+        float s = bc;
+        uint64_t t = a;
+        int base = 0;
+        for (int half = 0; half < 2; ++half) {
+            while (t) {
+                int pp[8];
+                bool ok[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    ok[u] = t != 0;
+                    pp[u] = ok[u] ? base + ctz64(t) : 0;
+                    t &= t - 1;
+                }
+                float v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = Ws[pp[u] * kEmbedTileCols + lane];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (ok[u]) s += v[u];
+            }
+            t = b;
+            base = M;
+        }
+        if (c < d1) h1[x * d1 + c] = tanhf(s);
+        if (U && blockIdx.y == 0)
+            for (int p = lane; p < No; p += kWave) {
+                const uint64_t w = p < M ? a : b;
+                const int q = p < M ? p : p - M;
+                U[x * No + p] = (float)((w >> q) & 1ull);
+            }
+    }
+}
+
 void launch_embed(hipStream_t st, const uint64_t *dets, int64_t n, int M, int d1, const float *W1, const float *b1,
                   float *h1, float *U, RowProblems rp, int64_t offW1, int64_t offb1) {
+    if (n <= 0) return;
+    if (!rp.pid) {
+        dim3 grid((unsigned)((n + kEmbedTileCfg - 1) / kEmbedTileCfg),
+                  (unsigned)((d1 + kEmbedTileCols - 1) / kEmbedTileCols));
+        hipLaunchKernelGGL(k_embed_tiled, grid, dim3(256), sizeof(float) * 2 * M * kEmbedTileCols, st, dets, n, M, d1,
+                           W1, b1, h1, U);
+        return;
+    }
     dim3 grid((unsigned)((n + kEmbedCfg - 1) / kEmbedCfg));
     hipLaunchKernelGGL(k_embed, grid, dim3(256), 0, st, dets, n, M, d1, W1, b1, h1, U, rp, offW1, offb1);
 }
