@@ -84,6 +84,7 @@ __global__ __launch_bounds__(256) void k_embed_tiled(const uint64_t *__restrict_
                                                      float *__restrict__ h1, float *__restrict__ U) {
     extern __shared__ float Ws[];  // [N_o][64]
     __shared__ uint64_t Ds[2 * kEmbedTileCfg];
+    __shared__ unsigned char Ps[kEmbedTileCfg][128];  // occupied spin-orbitals, ascending
     const int No = 2 * M;
     const int c0 = blockIdx.y * kEmbedTileCols;
     const int64_t x0 = (int64_t)blockIdx.x * kEmbedTileCfg;
@@ -106,49 +107,42 @@ __global__ __launch_bounds__(256) void k_embed_tiled(const uint64_t *__restrict_
         }
     }
     __syncthreads();
-    const int lane = threadIdx.x % kWave;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    // occupied lists by rank, one (configuration, spin-orbital) pair per thread (vector
+    // work: a scalar bit loop per configuration would queue on the CU's one scalar unit);
+    // the occupation vector U is written here too
+    for (int i = threadIdx.x; i < kEmbedTileCfg * No; i += blockDim.x) {
+        const int j = i / No, p = i % No;
+        if (x0 + j >= n) continue;
+        const uint64_t a = Ds[2 * j], b = Ds[2 * j + 1];
+        const uint64_t w = p < M ? a : b;
+        const int q = p < M ? p : p - M;
+        const bool occ = (w >> q) & 1ull;
+        if (occ) {
+            const uint64_t below = (1ull << q) - 1ull;
+            const int rank = p < M ? popc64(a & below) : popc64(a) + popc64(b & below);
+            Ps[j][rank] = (unsigned char)p;
+        }
+        if (U && blockIdx.y == 0) U[(x0 + j) * No + p] = occ ? 1.0f : 0.0f;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const int c = c0 + lane;
     const float bc = c < d1 ? b1[c] : 0.0f;
     for (int j = wave; j < kEmbedTileCfg; j += blockDim.x / kWave) {
         const int64_t x = x0 + j;
         if (x >= n) break;
-        // the configuration is uniform over the wave: its bit strings in scalar registers
-        const uint64_t a = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(Ds[2 * j] >> 32)) << 32) |
-                           (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)Ds[2 * j]);
-        const uint64_t b = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(Ds[2 * j + 1] >> 32)) << 32) |
-                           (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)Ds[2 * j + 1]);
+        const int ne = popc64(Ds[2 * j]) + popc64(Ds[2 * j + 1]);
         // occupied rows ascending (alpha, then beta), eight LDS reads in flight at a time
         float s = bc;
-        uint64_t t = a;
-        int base = 0;
-        for (int half = 0; half < 2; ++half) {
-            while (t) {
-                int pp[8];
-                bool ok[8];
+        for (int r0 = 0; r0 < ne; r0 += 8) {
+            float v[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    ok[u] = t != 0;
-                    pp[u] = ok[u] ? base + ctz64(t) : 0;
-                    t &= t - 1;
-                }
-                float v[8];
+            for (int u = 0; u < 8; ++u) v[u] = Ws[(r0 + u < ne ? Ps[j][r0 + u] : 0) * kEmbedTileCols + lane];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = Ws[pp[u] * kEmbedTileCols + lane];
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (ok[u]) s += v[u];
-            }
-            t = b;
-            base = M;
+            for (int u = 0; u < 8; ++u)
+                if (r0 + u < ne) s += v[u];
         }
         if (c < d1) h1[x * d1 + c] = tanhf(s);
-        if (U && blockIdx.y == 0)
-            for (int p = lane; p < No; p += kWave) {
-                const uint64_t w = p < M ? a : b;
-                const int q = p < M ? p : p - M;
-                U[x * No + p] = (float)((w >> q) & 1ull);
-            }
     }
 }
 
@@ -478,15 +472,23 @@ __global__ __launch_bounds__(256) void k_orb_lu(const uint64_t *__restrict__ det
         for (int c = 0; c < G; ++c)
             if (c < Ne) a[c] = prow[c] + orow[c];
     }
-    double lsum = 0.0;
+    // Rows stay in their lanes: vpos is the row position a lane would hold after the
+    // partial-pivoting row exchanges, and only vpos is exchanged (the pivot row is
+    // broadcast from wherever it lives).  Same pivots, same arithmetic as exchanging the
+    // rows; half the cross-lane traffic.  |det| is kept as an FP64 mantissa and binary
+    // exponent (one log at the end).
+    int vpos = r;
+    double mant = 1.0;
+    int expo = 0;
     int sgn = 1;
     bool singular = false;
 #pragma unroll
     for (int k = 0; k < G; ++k) {
         if (k >= Ne) continue;  // uniform; keeps the loop fully unrolled
-        // partial pivoting: largest |a[k]| among rows >= k, lowest row on ties
-        float cand = (r >= k && r < Ne) ? fabsf(a[k]) : -1.0f;
-        int ci = r;
+        // partial pivoting: largest |a[k]| among rows at positions >= k, lowest position on
+        // ties; key = position * 64 + lane
+        float cand = (vpos >= k && vpos < Ne) ? fabsf(a[k]) : -1.0f;
+        int ci = vpos * 64 + r;
 #pragma unroll
         for (int o = G / 2; o >= 1; o >>= 1) {
             float oc = __shfl_xor(cand, o, G);
@@ -496,30 +498,29 @@ __global__ __launch_bounds__(256) void k_orb_lu(const uint64_t *__restrict__ det
                 ci = oi;
             }
         }
-        const int piv = ci;
-        if (piv != k) sgn = -sgn;
-        const int src = (r == k) ? piv : ((r == piv) ? k : r);
-#pragma unroll
-        for (int c = 0; c < G; ++c) {
-            a[c] = __shfl(a[c], src, G);
-            inv[c] = __shfl(inv[c], src, G);
-        }
+        const int pv = ci >> 6, plane = ci & 63;  // pivot row's position and lane
+        if (pv != k) sgn = -sgn;
+        if (r == plane) vpos = k;
+        else if (vpos == k) vpos = pv;
         float pa[G], pi[G];
 #pragma unroll
         for (int c = 0; c < G; ++c) {
-            pa[c] = __shfl(a[c], k, G);
-            pi[c] = __shfl(inv[c], k, G);
+            pa[c] = __shfl(a[c], plane, G);
+            pi[c] = __shfl(inv[c], plane, G);
         }
         float d = pa[k];
         if (d == 0.0f) {
             singular = true;
             d = 1.0f;
         } else {
-            lsum += log(fabs((double)d));
+            mant *= fabs((double)d);
+            int e;
+            mant = frexp(mant, &e);
+            expo += e;
             if (d < 0.0f) sgn = -sgn;
         }
         const float rd = 1.0f / d;
-        if (r == k) {
+        if (r == plane) {
 #pragma unroll
             for (int c = 0; c < G; ++c) {
                 a[c] = pa[c] * rd;
@@ -535,11 +536,11 @@ __global__ __launch_bounds__(256) void k_orb_lu(const uint64_t *__restrict__ det
         }
     }
     if (live && r == 0) {
-        logabs[x] = singular ? -INFINITY : lsum;
+        logabs[x] = singular ? -INFINITY : log(mant) + (double)expo * 0.69314718055994530942;
         sign[x] = singular ? (int8_t)0 : (int8_t)sgn;
     }
-    if (Ainv && row_live) {
-        float *out = Ainv + x * (int64_t)(Ne * Ne) + (int64_t)r * Ne;
+    if (Ainv && row_live) {  // row vpos of A^-1
+        float *out = Ainv + x * (int64_t)(Ne * Ne) + (int64_t)vpos * Ne;
 #pragma unroll
         for (int c = 0; c < G; ++c)
             if (c < Ne) out[c] = singular ? 0.0f : inv[c];
