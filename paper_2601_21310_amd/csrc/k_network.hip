@@ -577,6 +577,20 @@ __global__ __launch_bounds__(256) void k_det_bwd(const uint64_t *__restrict__ de
                                                  float *__restrict__ dO, RowProblems rp, OutSplit os) {
     const int Ne = na + nb, No = 2 * M;
     const int width = No * Ne, wd = os.nd * Ne;
+    // the block's configurations' bit strings, psi and v read together up front (index
+    // clamped to the last configuration), rather than one round trip per configuration
+    uint64_t da[kBwdCfg], db[kBwdCfg];
+    double pxs[kBwdCfg], vs[kBwdCfg];
+#pragma unroll
+    for (int i = 0; i < kBwdCfg; ++i) {
+        const int64_t x = (int64_t)blockIdx.x * kBwdCfg + i;
+        const int64_t xc = x < n ? x : n - 1;
+        da[i] = dets[2 * xc];
+        db[i] = dets[2 * xc + 1];
+        pxs[i] = psi[xc];
+        vs[i] = v[xc];
+    }
+#pragma unroll
     for (int i = 0; i < kBwdCfg; ++i) {
         const int64_t x = (int64_t)blockIdx.x * kBwdCfg + i;
         if (x >= n) return;
@@ -592,9 +606,9 @@ __global__ __launch_bounds__(256) void k_det_bwd(const uint64_t *__restrict__ de
             norm = stats[0];
         }
         const bool ok = norm > 0.0 && isfinite(E) && !pad;
-        const uint64_t a = dets[2 * x], b = dets[2 * x + 1];
-        const double px = psi[x];
-        const float c = ok ? (float)(2.0 * (v[x] - E * px) * px / norm) : 0.0f;
+        const uint64_t a = da[i], b = db[i];
+        const double px = pxs[i];
+        const float c = ok ? (float)(2.0 * (vs[i] - E * px) * px / norm) : 0.0f;
         const float *ai = Ainv + x * (int64_t)(Ne * Ne);
         if (os.idx) {
             // sparse rows: dOsp[e][k] = c Ainv[k][j] for row j held as entry e

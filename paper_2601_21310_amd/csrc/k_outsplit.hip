@@ -314,11 +314,34 @@ __global__ __launch_bounds__(256) void k_os_dsum(int64_t n, int Ne, int din, con
     __syncthreads();
     if (!live) return;
     const int cnt = nes[sl];
-    for (int h = lt; h < din; h += 64) {
-        float s = dD ? dD[x * din + h] : 0.0f;
-        for (int r = 0; r < cnt; ++r) s += Cr[(int64_t)es[sl][r] * din + h];
-        const float hv = hL[x * din + h];
-        delta[x * din + h] = s * (1.0f - hv * hv);
+    // four h per lane and four sparse rows at a time, all reads of a batch in flight
+    // together (clamped to valid addresses); each sum in the order dD, then the rows
+    for (int h0 = lt; h0 < din; h0 += 256) {
+        int hh[4];
+        float s[4], hv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            hh[u] = h0 + 64 * u < din ? h0 + 64 * u : h0;
+            s[u] = dD ? dD[x * din + hh[u]] : 0.0f;
+            hv[u] = hL[x * din + hh[u]];
+        }
+        for (int r0 = 0; r0 < cnt; r0 += 4) {
+            float c[4][4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float *cr = Cr + (int64_t)es[sl][r0 + q < cnt ? r0 + q : r0] * din;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) c[q][u] = cr[hh[u]];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (r0 + q < cnt) s[u] += c[q][u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (h0 + 64 * u < din) delta[x * din + h0 + 64 * u] = s[u] * (1.0f - hv[u] * hv[u]);
     }
 }
 
