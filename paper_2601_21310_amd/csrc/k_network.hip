@@ -330,6 +330,38 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g0) {
     }
     float *C = (float *)g.C + (int64_t)blockIdx.z * g.c_split_stride;
     const float *act = (const float *)g.act;
+    if (m0 + TM <= g.M && n0 + BN <= g.N) {
+        // interior tile (uniform): no bounds tests; each lane's 16 rows of a block sit at
+        // fixed multiples of ld from its first row, so only one 64-bit address per block
+        const int64_t ldc = g.ldc, lda_ = g.ldact;
+#pragma unroll
+        for (int i = 0; i < WI; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int col = n0 + wn + j * 32 + li;
+                const int64_t row0 = m0 + wm + i * 32 + 4 * lk;
+                float fac[16];
+                if (EPI == EPI_DTANH) {
+                    const float *ap = act + row0 * lda_ + col;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const float hv = ap[(int64_t)(8 * (r >> 2) + (r & 3)) * lda_];
+                        fac[r] = 1.0f - hv * hv;
+                    }
+                }
+                const float bias = (EPI == EPI_BIAS || EPI == EPI_BIAS_TANH) ? g.bias[col] : 0.0f;
+                float *cp = C + row0 * ldc + col;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    float v = acc[i][j][r];
+                    if (EPI == EPI_BIAS) v += bias;
+                    if (EPI == EPI_BIAS_TANH) v = tanhf(v + bias);
+                    if (EPI == EPI_DTANH) v *= fac[r];
+                    cp[(int64_t)(8 * (r >> 2) + (r & 3)) * ldc] = v;
+                }
+            }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < WI; ++i)
 #pragma unroll
