@@ -358,9 +358,21 @@ __global__ __launch_bounds__(256) void k_os_wgrad(const float *__restrict__ hL, 
     extern __shared__ float gs[];  // [kOsItemMax][NP], then kOsItemMax configuration indices
     int *xs = reinterpret_cast<int *>(gs + kOsItemMax * NP);
     const int4 it = items[blockIdx.x];
-    for (int i = threadIdx.x; i < it.z * NP; i += blockDim.x) {
-        const int e = i / NP, k = i % NP;
-        gs[i] = k < Ne ? dOsp[((int64_t)it.y + e) * Ne + k] : 0.0f;
+    // staging with eight reads in flight per thread (clamped addresses, padding zeroed)
+    const int tot = it.z * NP;
+    for (int i0 = threadIdx.x; i0 < tot; i0 += 8 * blockDim.x) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * blockDim.x;
+            const int e = i < tot ? i / NP : 0, k = i % NP;
+            v[u] = dOsp[((int64_t)it.y + e) * Ne + (k < Ne ? k : 0)];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * blockDim.x;
+            if (i < tot) gs[i] = i % NP < Ne ? v[u] : 0.0f;
+        }
     }
     for (int i = threadIdx.x; i < it.z; i += blockDim.x) xs[i] = ex[(int64_t)it.y + i];
     __syncthreads();
@@ -369,9 +381,30 @@ __global__ __launch_bounds__(256) void k_os_wgrad(const float *__restrict__ hL, 
         float acc[NP];
 #pragma unroll
         for (int k = 0; k < NP; ++k) acc[k] = 0.0f;
-#pragma unroll 4
-        for (int i = 0; i < it.z; ++i) {
-            const float hv = h < din ? hL[(int64_t)xs[i] * din + h] : 1.0f;
+        // eight entries' h values read together (row din, the bias row, is 1; its lanes
+        // read a valid element and discard it), then accumulated in entry order
+        const int hc = h < din ? h : din - 1;
+        int i = 0;
+        for (; i + 8 <= it.z; i += 8) {
+            float hv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) hv[u] = hL[(int64_t)xs[i + u] * din + hc];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const float hu = h < din ? hv[u] : 1.0f;
+                const float4 *g4 = reinterpret_cast<const float4 *>(gs + (i + u) * NP);
+#pragma unroll
+                for (int q = 0; q < NP / 4; ++q) {
+                    const float4 g = g4[q];
+                    acc[4 * q + 0] = fmaf(hu, g.x, acc[4 * q + 0]);
+                    acc[4 * q + 1] = fmaf(hu, g.y, acc[4 * q + 1]);
+                    acc[4 * q + 2] = fmaf(hu, g.z, acc[4 * q + 2]);
+                    acc[4 * q + 3] = fmaf(hu, g.w, acc[4 * q + 3]);
+                }
+            }
+        }
+        for (; i < it.z; ++i) {
+            const float hv = h < din ? hL[(int64_t)xs[i] * din + hc] : 1.0f;
             const float4 *g4 = reinterpret_cast<const float4 *>(gs + i * NP);
 #pragma unroll
             for (int q = 0; q < NP / 4; ++q) {
