@@ -271,15 +271,20 @@ __global__ __launch_bounds__(256) void k_os_drows(const float *__restrict__ WT, 
     __shared__ float gs[kOsTile * NP];
     const int4 tl = tiles[blockIdx.x];
     const int p = tl.x;
+    // reads issued unconditionally (clamped indices) so that they overlap; padding zeroed
     for (int i = threadIdx.x; i < tl.z * NP; i += blockDim.x) {
         const int e = i / NP, k = i % NP;
-        gs[i] = k < Ne ? dOsp[((int64_t)tl.y + e) * Ne + k] : 0.0f;
+        const float v = dOsp[((int64_t)tl.y + e) * Ne + (k < Ne ? k : 0)];
+        gs[i] = k < Ne ? v : 0.0f;
     }
     __syncthreads();
     for (int h = threadIdx.x; h < din; h += blockDim.x) {
         float w[NP];
 #pragma unroll
-        for (int k = 0; k < NP; ++k) w[k] = k < Ne ? WT[((int64_t)p * Ne + k) * din + h] : 0.0f;
+        for (int k = 0; k < NP; ++k) w[k] = WT[((int64_t)p * Ne + (k < Ne ? k : 0)) * din + h];
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+            if (k >= Ne) w[k] = 0.0f;
         for (int e = 0; e < tl.z; ++e) {
             const float4 *g4 = reinterpret_cast<const float4 *>(gs + e * NP);
             float s = 0.0f;
