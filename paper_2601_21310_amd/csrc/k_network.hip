@@ -1,10 +1,12 @@
 // Network kernels for the neural backflow amplitude (Eqs. 2-4) and its adjoint.
 //
-//   k_embed     h1 = tanh(b1 + sum_{p in occ(x)} W1[p,:])      (layer 1 on 0/1 input)
+//   k_embed     h1 = tanh(b1 + sum_{p in occ(x)} W1[p,:])      (layer 1 on 0/1 input;
+//               k_embed_tiled for one weight set, LDS-staged)
 //   k_gemm_f32  C = epi(A B) on MFMA v_mfma_f32_32x32x2f32, 128x128 tiles, fused
 //               epilogues: +bias, tanh(+bias), *(1 - h^2); split-K for weight grads
 //   k_orb_lu    A(x) = Phi0[occ] + O[x, occ] -> Gauss-Jordan with partial pivoting,
-//               row per lane, log|det| in FP64, sign, and A^-1 for the adjoint
+//               row per lane (rows stay put, positions are exchanged), log|det| in
+//               FP64, sign, and A^-1 for the adjoint
 //   k_det_bwd   dL/dO[x, p*Ne+k] = c_x (A_x^-T)[j,k] for p = i_j, 0 elsewhere,
 //               c_x = 2 (v_x - E psi_x) psi_x / psi^T psi            (Eq. 12)
 //   (both also take the occupied-row layout of the output layer, k_outsplit.hip)
@@ -468,7 +470,8 @@ __device__ __forceinline__ int occupied_so(uint64_t a, uint64_t b, int M, int na
     return r < na ? p : M + p;
 }
 
-// G lanes per configuration; lane r of a group holds row r of [A | I].
+// G lanes per configuration; lane r of a group holds row r of [A | I] (its row position
+// changes with the pivoting, the data stays in the lane).
 template <int G>
 __global__ __launch_bounds__(256) void k_orb_lu(const uint64_t *__restrict__ dets, int64_t n, int M, int na, int nb,
                                                 const float *__restrict__ O, const float *__restrict__ Phi0g,
