@@ -74,17 +74,18 @@ __global__ __launch_bounds__(256) void k_embed(const uint64_t *__restrict__ dets
     }
 }
 
-// One weight set: a workgroup takes 64 columns of h1 for kEmbedTileCfg configurations and
-// stages those columns of W1 (N_o x 64) in LDS once, so that W1 is read from L2 once per
+// One weight set: a workgroup takes 128 columns of h1 for kEmbedTileCfg configurations and
+// stages those columns of W1 (N_o x 128) in LDS once, so that W1 is read from L2 once per
 // workgroup rather than once per configuration; each wave takes one configuration at a
-// time (its occupied orbitals are uniform over the wave).  Same sums, same order as
-// k_embed.
-constexpr int kEmbedTileCols = 64, kEmbedTileCfg = 64;
+// time (its occupied orbitals are uniform over the wave), two adjacent columns per lane
+// (the kernel is VALU-bound: the per-configuration gather arithmetic is shared by two
+// outputs).  Same sums, same order as k_embed.
+constexpr int kEmbedTileCols = 128, kEmbedTileCfg = 64;  // two columns per lane
 
 __global__ __launch_bounds__(256) void k_embed_tiled(const uint64_t *__restrict__ dets, int64_t n, int M, int d1,
                                                      const float *__restrict__ W1, const float *__restrict__ b1,
                                                      float *__restrict__ h1, float *__restrict__ U) {
-    extern __shared__ float Ws[];  // [N_o][64]
+    extern __shared__ float Ws[];  // [N_o][128]
     __shared__ uint64_t Ds[2 * kEmbedTileCfg];
     __shared__ unsigned char Ps[kEmbedTileCfg][128];  // occupied spin-orbitals, ascending
     const int No = 2 * M;
@@ -128,30 +129,39 @@ __global__ __launch_bounds__(256) void k_embed_tiled(const uint64_t *__restrict_
     }
     __syncthreads();
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    const int c = c0 + lane;
-    const float bc = c < d1 ? b1[c] : 0.0f;
+    const int c = c0 + 2 * lane;  // this lane's two columns c, c + 1 (d1 is even)
+    const float bc0 = c < d1 ? b1[c] : 0.0f, bc1 = c + 1 < d1 ? b1[c + 1] : 0.0f;
     for (int j = wave; j < kEmbedTileCfg; j += blockDim.x / kWave) {
         const int64_t x = x0 + j;
         if (x >= n) break;
         const int ne = popc64(Ds[2 * j]) + popc64(Ds[2 * j + 1]);
         // occupied rows ascending (alpha, then beta), eight LDS reads in flight at a time
-        float s = bc;
+        float s0 = bc0, s1 = bc1;
         for (int r0 = 0; r0 < ne; r0 += 8) {
-            float v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = Ws[(r0 + u < ne ? Ps[j][r0 + u] : 0) * kEmbedTileCols + lane];
+            float2 v[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                if (r0 + u < ne) s += v[u];
+                v[u] = *reinterpret_cast<const float2 *>(
+                    Ws + (r0 + u < ne ? Ps[j][r0 + u] : 0) * kEmbedTileCols + 2 * lane);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (r0 + u < ne) {
+                    s0 += v[u].x;
+                    s1 += v[u].y;
+                }
         }
-        if (c < d1) h1[x * d1 + c] = tanhf(s);
+        if (c + 1 < d1) {
+            *reinterpret_cast<float2 *>(h1 + x * d1 + c) = make_float2(tanhf(s0), tanhf(s1));
+        } else if (c < d1) {
+            h1[x * d1 + c] = tanhf(s0);
+        }
     }
 }
 
 void launch_embed(hipStream_t st, const uint64_t *dets, int64_t n, int M, int d1, const float *W1, const float *b1,
                   float *h1, float *U, RowProblems rp, int64_t offW1, int64_t offb1) {
     if (n <= 0) return;
-    if (!rp.pid) {
+    if (!rp.pid && d1 % 2 == 0) {
         dim3 grid((unsigned)((n + kEmbedTileCfg - 1) / kEmbedTileCfg),
                   (unsigned)((d1 + kEmbedTileCols - 1) / kEmbedTileCols));
         hipLaunchKernelGGL(k_embed_tiled, grid, dim3(256), sizeof(float) * 2 * M * kEmbedTileCols, st, dets, n, M, d1,
