@@ -373,7 +373,9 @@ uint64_t or_key_hash(uint64_t a, uint64_t b) { return mix64(a ^ mix64(b)); }
 
 typedef struct {
     uint64_t a, b;
-    double w;
+    double w;     /* sum of H_ax psi_x */
+    double c;     /* sum of |H_ax psi_x| (bounds the rounding error of w) */
+    int64_t k;    /* number of contributions */
     int used;
 } slot_t;
 
@@ -389,36 +391,41 @@ static void map_init(map_t *m, size_t cap) {
     m->n = 0;
 }
 
-static void map_add(map_t *m, uint64_t a, uint64_t b, double w);
+static slot_t *map_slot(map_t *m, uint64_t a, uint64_t b);
 
 static void map_grow(map_t *m) {
     map_t g;
     map_init(&g, m->cap * 2);
     for (size_t i = 0; i < m->cap; ++i)
-        if (m->s[i].used) map_add(&g, m->s[i].a, m->s[i].b, m->s[i].w);
+        if (m->s[i].used) *map_slot(&g, m->s[i].a, m->s[i].b) = m->s[i];
     free(m->s);
     *m = g;
 }
 
-static void map_add(map_t *m, uint64_t a, uint64_t b, double w) {
+/* the slot of key (a, b), created empty (w = c = k = 0) if absent */
+static slot_t *map_slot(map_t *m, uint64_t a, uint64_t b) {
     if (2 * (m->n + 1) > m->cap) map_grow(m);
     size_t i = (size_t)(or_key_hash(a, b) >> 7) & (m->cap - 1);
     for (;;) {
         slot_t *s = &m->s[i];
         if (!s->used) {
+            memset(s, 0, sizeof *s);
             s->used = 1;
             s->a = a;
             s->b = b;
-            s->w = w;
             m->n++;
-            return;
+            return s;
         }
-        if (s->a == a && s->b == b) {
-            s->w += w;
-            return;
-        }
+        if (s->a == a && s->b == b) return s;
         i = (i + 1) & (m->cap - 1);
     }
+}
+
+static void map_add(map_t *m, uint64_t a, uint64_t b, double w) {
+    slot_t *s = map_slot(m, a, b);
+    s->w += w;
+    s->c += fabs(w);
+    s->k += 1;
 }
 
 /*
@@ -427,23 +434,37 @@ static void map_add(map_t *m, uint64_t a, uint64_t b, double w) {
  * or_key_hash has (hash & sample_mask) == sample_val are kept (mask 0 keeps all).
  * A term whose numerator is exactly 0 contributes 0.  Statistics out:
  *   stats_i[0] = (x, a) pairs generated, stats_i[1] = kept unique a,
- *   stats_i[2] = terms with |E - H_aa| < 1e-8;  stats_d[0] = min |E - H_aa|.
+ *   stats_i[2] = terms with |E - H_aa| < 1e-8,
+ *   stats_i[3] = sum of or_key_hash(a) over the kept a (mod 2^64),
+ *   stats_i[4] = xor of or_key_hash(a) over the kept a
+ *     (with stats_i[1], an order-free fingerprint of the kept set);
+ *   stats_d[0] = min |E - H_aa|,
+ *   stats_d[1] = sum_a |t_a|, t_a = w_a^2 / (E - H_aa),
+ *   stats_d[2] = sum_a 2 |w_a| c_a / |E - H_aa|, c_a = sum_x |H_ax psi_x|,
+ *   stats_d[3] = sum_a 2 |w_a| k_a / |E - H_aa|, k_a = number of x with a pair to a,
+ *   stats_d[4] = sum_a |t_a| (|E| + |H_aa|) / |E - H_aa|
+ *     (first-order sensitivities of the sum to relative errors in the terms, to
+ *     relative errors in the H_ax psi_x, to an absolute error per H_ax psi_x, and to
+ *     relative errors in E and H_aa: error bars for another implementation).
  * Work is split over threads by key hash, so each thread owns a private map.
  */
 double or_pt2_external(int M, const double *h, const double *eri, double ecore, const uint64_t *dets,
                        int64_t n, const double *psi, double E, uint64_t sample_mask, uint64_t sample_val,
                        int64_t *stats_i, double *stats_d) {
     int64_t n_pairs = 0, n_keys = 0, n_tiny = 0;
-    double total = 0.0, min_den = INFINITY;
+    uint64_t fp_sum = 0, fp_xor = 0;
+    double total = 0.0, min_den = INFINITY, sens[4] = {0.0, 0.0, 0.0, 0.0};
     int nthr = 1;
 #ifdef _OPENMP
     nthr = omp_get_max_threads();
 #endif
     double *part_sum = (double *)calloc((size_t)nthr, sizeof(double));
     double *part_min = (double *)malloc(sizeof(double) * (size_t)nthr);
+    double *part_sens = (double *)calloc(4 * (size_t)nthr, sizeof(double));
     int64_t *part_keys = (int64_t *)calloc((size_t)nthr, sizeof(int64_t));
     int64_t *part_tiny = (int64_t *)calloc((size_t)nthr, sizeof(int64_t));
     int64_t *part_pairs = (int64_t *)calloc((size_t)nthr, sizeof(int64_t));
+    uint64_t *part_fp = (uint64_t *)calloc(2 * (size_t)nthr, sizeof(uint64_t));
     for (int t = 0; t < nthr; ++t) part_min[t] = INFINITY;
 #pragma omp parallel num_threads(nthr)
     {
@@ -474,12 +495,23 @@ double or_pt2_external(int M, const double *h, const double *eri, double ecore, 
         for (size_t q = 0; q < m.cap; ++q) {
             if (!m.s[q].used) continue;
             part_keys[t]++;
-            double den = E - or_hdiag(M, h, eri, ecore, m.s[q].a, m.s[q].b);
+            uint64_t hk = or_key_hash(m.s[q].a, m.s[q].b);
+            part_fp[2 * t] += hk;
+            part_fp[2 * t + 1] ^= hk;
+            double haa = or_hdiag(M, h, eri, ecore, m.s[q].a, m.s[q].b);
+            double den = E - haa;
             double ad = fabs(den);
             if (ad < part_min[t]) part_min[t] = ad;
             if (ad < 1e-8) part_tiny[t]++;
             double w = m.s[q].w;
-            if (w != 0.0) s += w * w / den;
+            if (w != 0.0) {
+                double term = w * w / den;
+                s += term;
+                part_sens[4 * t + 0] += fabs(term);
+                part_sens[4 * t + 1] += 2.0 * fabs(w) * m.s[q].c / ad;
+                part_sens[4 * t + 2] += 2.0 * fabs(w) * (double)m.s[q].k / ad;
+                part_sens[4 * t + 3] += fabs(term) * (fabs(E) + fabs(haa)) / ad;
+            }
         }
         part_sum[t] = s;
         free(ex);
@@ -489,6 +521,9 @@ double or_pt2_external(int M, const double *h, const double *eri, double ecore, 
         total += part_sum[t];
         n_keys += part_keys[t];
         n_tiny += part_tiny[t];
+        fp_sum += part_fp[2 * t];
+        fp_xor ^= part_fp[2 * t + 1];
+        for (int k = 0; k < 4; ++k) sens[k] += part_sens[4 * t + k];
         if (part_min[t] < min_den) min_den = part_min[t];
     }
     n_pairs = part_pairs[0];
@@ -496,14 +531,72 @@ double or_pt2_external(int M, const double *h, const double *eri, double ecore, 
         stats_i[0] = n_pairs;
         stats_i[1] = n_keys;
         stats_i[2] = n_tiny;
+        stats_i[3] = (int64_t)fp_sum;
+        stats_i[4] = (int64_t)fp_xor;
     }
-    if (stats_d) stats_d[0] = min_den;
+    if (stats_d) {
+        stats_d[0] = min_den;
+        for (int k = 0; k < 4; ++k) stats_d[1 + k] = sens[k];
+    }
     free(part_sum);
     free(part_min);
+    free(part_sens);
     free(part_keys);
     free(part_tiny);
     free(part_pairs);
+    free(part_fp);
     return total;
+}
+
+/*
+ * The set P = C(S) \ S of Eq. 1 written out: every determinant a of the sector that
+ * is a single or double excitation of some x in S and is not itself in S, each once,
+ * in canonical order (ascending alpha, then beta).  With psi given, also
+ * w_a = sum_{x in S} H_ax psi_x and H_aa.  Single-threaded, for small S: returns |P|
+ * and writes min(|P|, cap) entries (keys[2k], keys[2k+1]; w and haa may be NULL).
+ */
+static int cmp_key(const void *x, const void *y) {
+    const uint64_t *u = (const uint64_t *)x, *v = (const uint64_t *)y;
+    return cmp_det(u[0], u[1], v[0], v[1]);
+}
+
+int64_t or_pt2_plist(int M, const double *h, const double *eri, double ecore, const uint64_t *dets, int64_t n,
+                     const double *psi, uint64_t *keys, double *w_out, double *haa_out, int64_t cap) {
+    map_t m;
+    map_init(&m, 1024);
+    int64_t ecap = or_excitations(M, dets[0], dets[1], NULL, 0);
+    uint64_t *ex = (uint64_t *)malloc(sizeof(uint64_t) * 2 * (size_t)(ecap > 0 ? ecap : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t xa = dets[2 * i], xb = dets[2 * i + 1];
+        int64_t ne = or_excitations(M, xa, xb, ex, ecap);
+        for (int64_t k = 0; k < ne; ++k) {
+            uint64_t aa = ex[2 * k], ab = ex[2 * k + 1];
+            if (find_det(dets, n, aa, ab) >= 0) continue;
+            double hax = psi ? or_hxy(M, h, eri, ecore, aa, ab, xa, xb) * psi[i] : 0.0;
+            map_add(&m, aa, ab, hax);
+        }
+    }
+    free(ex);
+    /* (alpha, beta, index into the map) triples, sorted canonically */
+    int64_t np_ = (int64_t)m.n, j = 0;
+    uint64_t *list = (uint64_t *)malloc(sizeof(uint64_t) * 3 * (size_t)(np_ > 0 ? np_ : 1));
+    for (size_t q = 0; q < m.cap; ++q)
+        if (m.s[q].used) {
+            list[3 * j] = m.s[q].a;
+            list[3 * j + 1] = m.s[q].b;
+            list[3 * j + 2] = (uint64_t)q;
+            ++j;
+        }
+    qsort(list, (size_t)np_, 3 * sizeof(uint64_t), cmp_key);
+    for (int64_t k = 0; k < np_ && k < cap; ++k) {
+        keys[2 * k] = list[3 * k];
+        keys[2 * k + 1] = list[3 * k + 1];
+        if (w_out) w_out[k] = m.s[list[3 * k + 2]].w;
+        if (haa_out) haa_out[k] = or_hdiag(M, h, eri, ecore, list[3 * k], list[3 * k + 1]);
+    }
+    free(list);
+    free(m.s);
+    return np_;
 }
 
 /*
