@@ -55,6 +55,12 @@ def lib():
         L.or_pt2_plist.argtypes = [C.c_int, _dp, _dp, C.c_double, _u64p, C.c_int64, _opt(_dp), _opt(_u64p),
                                    _opt(_dp), _opt(_dp), C.c_int64]
         L.or_pt2_plist.restype = C.c_int64
+        L.or_pt2_external_hb.argtypes = [C.c_int, _dp, _dp, C.c_double, _u64p, C.c_int64, _dp, C.c_double,
+                                         C.c_uint64, C.c_uint64, C.c_double, _i64p, _dp]
+        L.or_pt2_external_hb.restype = C.c_double
+        L.or_pt2_plist_hb.argtypes = [C.c_int, _dp, _dp, C.c_double, _u64p, C.c_int64, _opt(_dp), C.c_double,
+                                      _opt(_u64p), _opt(_dp), _opt(_dp), C.c_int64]
+        L.or_pt2_plist_hb.restype = C.c_int64
         L.or_w_keys.argtypes = [C.c_int, _dp, _dp, C.c_double, _u64p, C.c_int64, _dp, _u64p, C.c_int64,
                                 _dp, _opt(_dp)]
         L.or_w_keys.restype = C.c_int
@@ -62,6 +68,8 @@ def lib():
         L.or_key_hash.restype = C.c_uint64
         L.or_num_threads.argtypes = []
         L.or_num_threads.restype = C.c_int
+        L.or_set_num_threads.argtypes = [C.c_int]
+        L.or_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -149,9 +157,11 @@ def key_hash(a, b):
     return int(lib().or_key_hash(int(a), int(b)))
 
 
-def pt2_external(M, h, eri, ecore, dets, psi, E, sample_mask=0, sample_val=0):
+def pt2_external(M, h, eri, ecore, dets, psi, E, sample_mask=0, sample_val=0, eps_hb=0.0):
     """Unnormalised external EN sum over P = C(S) minus S (Eq. 13, second term).
 
+    eps_hb > 0: only the keys a with max_x |H_ax psi_x| >= eps_hb ||psi||_2 (the heat-bath
+    screen of Eq. 14 on the normalised psi; each kept key with its whole w_a).
     Returns (sum, stats) with stats: pairs, n_p, n_tiny, min_den; the order-free
     fingerprint of the kept keys fp_sum / fp_xor (sum mod 2^64 and xor of key_hash);
     and first-order sensitivities of the sum (sum_abs = sum |t_a|; sens_rel_c, to a
@@ -159,28 +169,33 @@ def pt2_external(M, h, eri, ecore, dets, psi, E, sample_mask=0, sample_val=0):
     sens_den, to relative errors in E and H_aa).
     """
     dets = _dets(dets)
+    psi = _f64(psi)
     si = np.zeros(5, dtype=np.int64)
     sd = np.zeros(5, dtype=np.float64)
-    s = lib().or_pt2_external(M, _f64(h).ravel(), _f64(eri).ravel(), float(ecore), dets.ravel(),
-                              dets.shape[0], _f64(psi), float(E), int(sample_mask), int(sample_val), si, sd)
+    eps_abs = float(eps_hb) * float(np.sqrt(psi @ psi)) if eps_hb > 0 else 0.0
+    s = lib().or_pt2_external_hb(M, _f64(h).ravel(), _f64(eri).ravel(), float(ecore), dets.ravel(),
+                                 dets.shape[0], psi, float(E), int(sample_mask), int(sample_val), eps_abs, si, sd)
     return s, {"pairs": int(si[0]), "n_p": int(si[1]), "n_tiny": int(si[2]),
                "fp_sum": int(si[3]) & 0xFFFFFFFFFFFFFFFF, "fp_xor": int(si[4]) & 0xFFFFFFFFFFFFFFFF,
                "min_den": float(sd[0]), "sum_abs": float(sd[1]), "sens_rel_c": float(sd[2]),
                "sens_abs_c": float(sd[3]), "sens_den": float(sd[4])}
 
 
-def pt2_plist(M, h, eri, ecore, dets, psi=None):
+def pt2_plist(M, h, eri, ecore, dets, psi=None, eps_hb=0.0):
     """P = C(S) minus S written out in canonical order (Eq. 1), with w_a and H_aa when
-    psi is given.  Returns (keys uint64[|P|, 2], w, haa) (w, haa None without psi)."""
+    psi is given; eps_hb > 0 (psi needed) keeps only the a with max_x |H_ax psi_x| >=
+    eps_hb ||psi||_2 (Eq. 14).  Returns (keys uint64[|P|, 2], w, haa) (w, haa None
+    without psi)."""
     dets = _dets(dets)
     L = lib()
     hf, ef = _f64(h).ravel(), _f64(eri).ravel()
     p = None if psi is None else _f64(psi)
-    n_p = L.or_pt2_plist(M, hf, ef, float(ecore), dets.ravel(), dets.shape[0], p, None, None, None, 0)
+    eps_abs = float(eps_hb) * float(np.sqrt(p @ p)) if (eps_hb > 0 and p is not None) else 0.0
+    n_p = L.or_pt2_plist_hb(M, hf, ef, float(ecore), dets.ravel(), dets.shape[0], p, eps_abs, None, None, None, 0)
     keys = np.zeros(2 * max(n_p, 1), dtype=np.uint64)
     w = np.zeros(max(n_p, 1)) if psi is not None else None
     haa = np.zeros(max(n_p, 1)) if psi is not None else None
-    L.or_pt2_plist(M, hf, ef, float(ecore), dets.ravel(), dets.shape[0], p, keys, w, haa, n_p)
+    L.or_pt2_plist_hb(M, hf, ef, float(ecore), dets.ravel(), dets.shape[0], p, eps_abs, keys, w, haa, n_p)
     keys = keys[: 2 * n_p].reshape(-1, 2)
     if psi is None:
         return keys, None, None
@@ -201,3 +216,7 @@ def w_keys(M, h, eri, ecore, dets, psi, keys):
 
 def num_threads():
     return int(lib().or_num_threads())
+
+
+def set_num_threads(k):
+    lib().or_set_num_threads(int(k))

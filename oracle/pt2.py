@@ -26,11 +26,13 @@ def internal_sum(psi, v, diag, E):
     return float(np.sum(num[keep] / den[keep]))
 
 
-def pt2(M, h, eri, ecore, dets, psi, v, diag, E, sample_mask=0, sample_val=0):
-    """Returns dict(dE, internal, external, norm, stats) (internal/external unnormalised)."""
+def pt2(M, h, eri, ecore, dets, psi, v, diag, E, sample_mask=0, sample_val=0, eps_hb=0.0):
+    """Returns dict(dE, internal, external, norm, stats) (internal/external unnormalised).
+    eps_hb > 0: the external sum runs over the heat-bath-screened P of Eq. 14 (keys whose
+    largest coupling |H_ax psi_x| reaches eps_hb times ||psi||_2)."""
     psi = np.asarray(psi, dtype=np.float64)
     norm = float(psi @ psi)
     internal = internal_sum(psi, v, diag, E)
-    external, stats = ham.pt2_external(M, h, eri, ecore, dets, psi, E, sample_mask, sample_val)
+    external, stats = ham.pt2_external(M, h, eri, ecore, dets, psi, E, sample_mask, sample_val, eps_hb)
     return {"dE": (internal + external) / norm, "internal": internal, "external": external,
             "norm": norm, "stats": stats}

@@ -375,6 +375,7 @@ typedef struct {
     uint64_t a, b;
     double w;     /* sum of H_ax psi_x */
     double c;     /* sum of |H_ax psi_x| (bounds the rounding error of w) */
+    double mx;    /* largest |H_ax psi_x| (the heat-bath measure of a, Eq. 14) */
     int64_t k;    /* number of contributions */
     int used;
 } slot_t;
@@ -425,13 +426,17 @@ static void map_add(map_t *m, uint64_t a, uint64_t b, double w) {
     slot_t *s = map_slot(m, a, b);
     s->w += w;
     s->c += fabs(w);
+    if (fabs(w) > s->mx) s->mx = fabs(w);
     s->k += 1;
 }
 
 /*
  * External part of Eq. 13, unnormalised: sum over a in P = C(S) \ S of
  * w_a^2 / (E - H_aa), with w_a = sum_{x in S} H_ax psi_x.  Only keys whose
- * or_key_hash has (hash & sample_mask) == sample_val are kept (mask 0 keeps all).
+ * or_key_hash has (hash & sample_mask) == sample_val are kept (mask 0 keeps all), and
+ * only keys whose largest single coupling max_x |H_ax psi_x| is at least eps_abs (the
+ * heat-bath screen of Eq. 14 with the threshold in the scale of psi; 0 keeps all); w_a
+ * of a kept key is its whole sum.
  * A term whose numerator is exactly 0 contributes 0.  Statistics out:
  *   stats_i[0] = (x, a) pairs generated, stats_i[1] = kept unique a,
  *   stats_i[2] = terms with |E - H_aa| < 1e-8,
@@ -448,9 +453,9 @@ static void map_add(map_t *m, uint64_t a, uint64_t b, double w) {
  *     relative errors in E and H_aa: error bars for another implementation).
  * Work is split over threads by key hash, so each thread owns a private map.
  */
-double or_pt2_external(int M, const double *h, const double *eri, double ecore, const uint64_t *dets,
-                       int64_t n, const double *psi, double E, uint64_t sample_mask, uint64_t sample_val,
-                       int64_t *stats_i, double *stats_d) {
+double or_pt2_external_hb(int M, const double *h, const double *eri, double ecore, const uint64_t *dets,
+                          int64_t n, const double *psi, double E, uint64_t sample_mask, uint64_t sample_val,
+                          double eps_abs, int64_t *stats_i, double *stats_d) {
     int64_t n_pairs = 0, n_keys = 0, n_tiny = 0;
     uint64_t fp_sum = 0, fp_xor = 0;
     double total = 0.0, min_den = INFINITY, sens[4] = {0.0, 0.0, 0.0, 0.0};
@@ -494,6 +499,7 @@ double or_pt2_external(int M, const double *h, const double *eri, double ecore, 
         double s = 0.0;
         for (size_t q = 0; q < m.cap; ++q) {
             if (!m.s[q].used) continue;
+            if (m.s[q].mx < eps_abs) continue; /* screened out (Eq. 14) */
             part_keys[t]++;
             uint64_t hk = or_key_hash(m.s[q].a, m.s[q].b);
             part_fp[2 * t] += hk;
@@ -548,11 +554,18 @@ double or_pt2_external(int M, const double *h, const double *eri, double ecore, 
     return total;
 }
 
+double or_pt2_external(int M, const double *h, const double *eri, double ecore, const uint64_t *dets,
+                       int64_t n, const double *psi, double E, uint64_t sample_mask, uint64_t sample_val,
+                       int64_t *stats_i, double *stats_d) {
+    return or_pt2_external_hb(M, h, eri, ecore, dets, n, psi, E, sample_mask, sample_val, 0.0, stats_i, stats_d);
+}
+
 /*
  * The set P = C(S) \ S of Eq. 1 written out: every determinant a of the sector that
  * is a single or double excitation of some x in S and is not itself in S, each once,
  * in canonical order (ascending alpha, then beta).  With psi given, also
- * w_a = sum_{x in S} H_ax psi_x and H_aa.  Single-threaded, for small S: returns |P|
+ * w_a = sum_{x in S} H_ax psi_x and H_aa, and with eps_abs > 0 only the a whose
+ * largest coupling max_x |H_ax psi_x| reaches eps_abs (the screened set of Eq. 14).  Single-threaded, for small S: returns |P|
  * and writes min(|P|, cap) entries (keys[2k], keys[2k+1]; w and haa may be NULL).
  */
 static int cmp_key(const void *x, const void *y) {
@@ -560,8 +573,9 @@ static int cmp_key(const void *x, const void *y) {
     return cmp_det(u[0], u[1], v[0], v[1]);
 }
 
-int64_t or_pt2_plist(int M, const double *h, const double *eri, double ecore, const uint64_t *dets, int64_t n,
-                     const double *psi, uint64_t *keys, double *w_out, double *haa_out, int64_t cap) {
+int64_t or_pt2_plist_hb(int M, const double *h, const double *eri, double ecore, const uint64_t *dets, int64_t n,
+                        const double *psi, double eps_abs, uint64_t *keys, double *w_out, double *haa_out,
+                        int64_t cap) {
     map_t m;
     map_init(&m, 1024);
     int64_t ecap = or_excitations(M, dets[0], dets[1], NULL, 0);
@@ -577,11 +591,13 @@ int64_t or_pt2_plist(int M, const double *h, const double *eri, double ecore, co
         }
     }
     free(ex);
-    /* (alpha, beta, index into the map) triples, sorted canonically */
-    int64_t np_ = (int64_t)m.n, j = 0;
+    /* (alpha, beta, index into the map) triples of the kept keys, sorted canonically */
+    int64_t np_ = 0, j = 0;
+    for (size_t q = 0; q < m.cap; ++q)
+        if (m.s[q].used && m.s[q].mx >= eps_abs) ++np_;
     uint64_t *list = (uint64_t *)malloc(sizeof(uint64_t) * 3 * (size_t)(np_ > 0 ? np_ : 1));
     for (size_t q = 0; q < m.cap; ++q)
-        if (m.s[q].used) {
+        if (m.s[q].used && m.s[q].mx >= eps_abs) {
             list[3 * j] = m.s[q].a;
             list[3 * j + 1] = m.s[q].b;
             list[3 * j + 2] = (uint64_t)q;
@@ -597,6 +613,11 @@ int64_t or_pt2_plist(int M, const double *h, const double *eri, double ecore, co
     free(list);
     free(m.s);
     return np_;
+}
+
+int64_t or_pt2_plist(int M, const double *h, const double *eri, double ecore, const uint64_t *dets, int64_t n,
+                     const double *psi, uint64_t *keys, double *w_out, double *haa_out, int64_t cap) {
+    return or_pt2_plist_hb(M, h, eri, ecore, dets, n, psi, 0.0, keys, w_out, haa_out, cap);
 }
 
 /*
@@ -627,6 +648,15 @@ int or_w_keys(int M, const double *h, const double *eri, double ecore, const uin
         free(ex);
     }
     return 0;
+}
+
+/* set the number of OpenMP threads the oracle uses (timing of the oracle on fewer cores) */
+void or_set_num_threads(int k) {
+#ifdef _OPENMP
+    if (k > 0) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
 }
 
 /* number of OpenMP threads the oracle will use */
