@@ -28,19 +28,19 @@ from . import hamiltonian as ham
 from .energy import _torch_csr, scaled_psi
 
 
-def _rank(a, b):
-    return bin(int(a)).count("1") + bin(int(b)).count("1")
-
-
 def coupling_block(M, h, eri, ecore, rows, cols) -> sp.csr_matrix:
     """<r|H|c> for every r in rows and c in cols at excitation rank 1 or 2 (r != c), by the
     Slater-Condon rules; pairs are found by comparing the bit strings (brute force)."""
     rows = np.asarray(rows, dtype=np.uint64).reshape(-1, 2)
     cols = np.asarray(cols, dtype=np.uint64).reshape(-1, 2)
+
+    def popcount(v):
+        return np.unpackbits(np.ascontiguousarray(v).view(np.uint8)).reshape(v.shape[0], 64).sum(axis=1)
+
     ri, ci, val = [], [], []
     for i, (ra, rb) in enumerate(rows):
-        da = np.array([bin(int(ra) ^ int(c)).count("1") for c in cols[:, 0]])
-        db = np.array([bin(int(rb) ^ int(c)).count("1") for c in cols[:, 1]])
+        da = popcount(cols[:, 0] ^ ra)
+        db = popcount(cols[:, 1] ^ rb)
         for j in np.nonzero((da + db >= 2) & (da + db <= 4))[0]:
             ri.append(i)
             ci.append(int(j))
