@@ -36,36 +36,73 @@ def n_excitations(M, na, nb):
 
 
 def cpu_baseline(p, sample_n: int):
-    """Time the oracle (as it stands) on the first sample_n dets of S: H_SS by its
-    definition, amplitudes + energy + gradient in FP64, and the PT2 external sum."""
-    import numpy as np
+    """Time the oracle (as it stands) on the first sample_n dets of S: amplitudes + energy +
+    gradient in FP64 (the headline unit), H_SS by its definition, and the PT2 external sum
+    on the first sample_n / 20 dets.  Protocol: one warm run, then the median of three
+    timed runs, with all host cores; the amplitudes + gradient step also on one core."""
+    import statistics
+
     import scipy.sparse as sp
+    import torch
 
     from oracle import energy
     from oracle import hamiltonian as ham
     from oracle import pt2 as opt2
     wl = p.wl
     S = p.dets[:sample_n]
-    t0 = time.perf_counter()
-    row_ptr, col, val, diag = ham.csr_rows(wl.M, p.h, p.eri, p.e_core, S)
-    t1 = time.perf_counter()
-    H = (sp.csr_matrix((val, col, row_ptr), shape=(len(S), len(S))) + sp.diags(diag)).tocsr()
-    o = energy.energy_and_grad(p.theta, wl.widths, S, wl.M, wl.n_elec, H)
-    t2 = time.perf_counter()
     npt2 = max(1, sample_n // 20)
-    sub = S[:npt2]
-    Hs = H[:npt2, :npt2]
-    psi = o["psi"][:npt2]
-    res = opt2.pt2(wl.M, p.h, p.eri, p.e_core, sub, psi, Hs @ psi, diag[:npt2], o["E"])
-    t3 = time.perf_counter()
     nexc = n_excitations(wl.M, wl.n_alpha, wl.n_beta)
+    cores = ham.num_threads()
+    torch_threads = torch.get_num_threads()
+
+    def hss():
+        return ham.csr_rows(wl.M, p.h, p.eri, p.e_core, S)
+
+    row_ptr, col, val, diag = hss()
+    H = (sp.csr_matrix((val, col, row_ptr), shape=(len(S), len(S))) + sp.diags(diag)).tocsr()
+
+    def egrad():
+        return energy.energy_and_grad(p.theta, wl.widths, S, wl.M, wl.n_elec, H)
+
+    o = egrad()
+    psi = o["psi"][:npt2]
+    Hs = H[:npt2, :npt2]
+
+    def pt2():
+        return opt2.pt2(wl.M, p.h, p.eri, p.e_core, S[:npt2], psi, Hs @ psi, diag[:npt2], o["E"])
+
+    def median3(fn):
+        fn()  # warm run
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return statistics.median(ts)
+
+    t_e = median3(egrad)
+    t_h = median3(hss)
+    t_p = median3(pt2)
+    # one core: torch and the oracle's OpenMP part each on one thread
+    n1 = max(64, sample_n // 8)
+    S1 = S[:n1]
+    H1 = H[:n1, :n1]
+    torch.set_num_threads(1)
+    ham.set_num_threads(1)
+    try:
+        t_e1 = median3(lambda: energy.energy_and_grad(p.theta, wl.widths, S1, wl.M, wl.n_elec, H1))
+    finally:
+        torch.set_num_threads(torch_threads)
+        ham.set_num_threads(cores)
     return {
-        "value": sample_n / (t2 - t1), "unit": "amps+grads/s", "cores": ham.num_threads(), "kind": "oracle",
-        "sample": (f"first {sample_n} dets of S: amplitudes+energy+gradient (torch FP64) {t2 - t1:.2f}s; "
-                   f"H_SS by definition {t1 - t0:.2f}s; PT2 external sum on first {npt2} dets "
-                   f"({npt2 * nexc} pairs) {t3 - t2:.2f}s"),
-        "h_elements_per_s": sample_n * (nexc + 1) / (t1 - t0),
-        "pt2_pairs_per_s": res["stats"]["pairs"] / (t3 - t2),
+        "value": sample_n / t_e, "unit": "amps+grads/s", "cores": cores, "kind": "oracle",
+        "sample": (f"first {sample_n} dets of S, median of 3 after a warm run: amplitudes+energy+gradient "
+                   f"(torch FP64, {torch_threads} threads) {t_e:.2f}s; H_SS by definition {t_h:.2f}s; PT2 external "
+                   f"sum on the first {npt2} dets ({npt2 * nexc} pairs) {t_p:.2f}s; one core: "
+                   f"amplitudes+energy+gradient on the first {n1} dets {t_e1:.2f}s"),
+        "single_thread_amps_grads_per_s": n1 / t_e1,
+        "h_elements_per_s": sample_n * (nexc + 1) / t_h,
+        "pt2_pairs_per_s": npt2 * nexc / t_p,
     }
 
 
@@ -111,12 +148,13 @@ def bench_sweep(args, dnqs, synth, torch):
                "h_elements_per_s": n * (nexc + 1) / (t_h * 1e-3)}
         for name in ("fp32", args.precision):
             pr = getattr(dnqs, PRECISIONS[name])
-            r = ctx.energy_and_grad(wl.widths, theta, conn, precision=pr)   # tunes new shapes
-            r = ctx.energy_and_grad(wl.widths, theta, conn, precision=pr)
+            rc = args.recompute
+            r = ctx.energy_and_grad(wl.widths, theta, conn, precision=pr, recompute=rc)   # tunes new shapes
+            r = ctx.energy_and_grad(wl.widths, theta, conn, precision=pr, recompute=rc)
             torch.cuda.synchronize()
             ctx.timing_reset()
             for _ in range(max(args.steps, 3)):
-                r = ctx.energy_and_grad(wl.widths, theta, conn, precision=pr)
+                r = ctx.energy_and_grad(wl.widths, theta, conn, precision=pr, recompute=rc)
             torch.cuda.synchronize()
             t = ctx.timing_get("egrad")[0] / max(args.steps, 3)
             peak = FP32_PEAK_TFLOPS if name == "fp32" else BF16_PEAK_TFLOPS / 3.0
@@ -124,6 +162,7 @@ def bench_sweep(args, dnqs, synth, torch):
             # flops of the full-width network (gemm_flops): with the occupied-row output
             # layer the GEMMs do less work, so this is a dense-equivalent rate
             row[name] = {"energy_and_grad_ms": t, "amps_grads_per_s": n / (t * 1e-3), "E": r["E"].item(),
+                         "recompute": bool(rc), "device_bytes_held": ctx.allocator.live_bytes,
                          "dense_equiv_gemm_tflops": tf, "gemm_peak_tflops": peak, "dense_equiv_frac": tf / peak}
         if n * nexc <= args.sweep_pt2_max:
             r = ctx.energy_and_grad(wl.widths, theta, conn, want_grad=False, precision=getattr(dnqs, PRECISIONS[args.precision]))
@@ -247,14 +286,16 @@ def main():
     ap.add_argument("--precision", choices=list(PRECISIONS), default="mixed")
     ap.add_argument("--out-scale", type=float, default=1e-2,
                     help="scale of the Glorot output layer (small, as the paper initialises it)")
-    ap.add_argument("--cpu-sample", type=int, default=50000,
-                    help="dets of S the oracle is timed on (about 10-30 s of host work)")
+    ap.add_argument("--cpu-sample", type=int, default=12000,
+                    help="dets of S the oracle is timed on (about 10-30 s of host work in all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", default="",
                     help="instead of the headline run: comma-separated |S| values on --workload (e.g. "
                          "m56_12a12b with 1e4,3e4,1e5,3e5,1e6): H_SS, energy+gradient and, up to --sweep-pt2-max "
                          "pairs, PT2 for each")
     ap.add_argument("--sweep-pt2-max", type=float, default=2e10)
+    ap.add_argument("--recompute", action="store_true",
+                    help="in the sweep: keep only the last hidden layer, recomputing the others by row block")
     ap.add_argument("--curve", type=int, default=0,
                     help="instead of the headline run: energy+gradient over a synthetic dissociation curve of "
                          "this many geometries (M=20, 6a+6b, |S| log-uniform in [2^10, 2^16]), sequential vs "
@@ -354,18 +395,37 @@ def main():
     o = out["out"].cpu().numpy()
     c = out["counts"].cpu().numpy()
     pairs = int(c[0])
-    # Roofline of the dominant kernel, the PT2 reduce: it streams one 8-byte pair
-    # descriptor per (x, a) pair (its gathers of dets, psi and integrals hit L2);
-    # duration = its average HIP-event time on the library stream.
+    # Roofline of the dominant kernel, the PT2 reduce, on the group-by model of the PT2
+    # step: a pair's key and value (16 + 4 bytes) are written once and read once, and the
+    # reduce is the read half, 20 bytes per pair.  The reduce's own HBM stream (one 8-byte
+    # descriptor per pair) and its measured traffic are kept beside it.
     t_red = avg["pt2_reduce"]
     # reduce launches per pt2 call (more than one when the key space is sliced)
     red_per_call = fam["pt2_reduce"][1] / max(fam["pt2"][1], 1)
-    red_bytes = 8.0 * pairs / max(red_per_call, 1.0)
+    red_bytes = 20.0 * pairs / max(red_per_call, 1.0)
     achieved = red_bytes / (t_red * 1e-3) / 1e9
     traffic = measured_traffic("k_pt2_reduce", wl.name)
     # the whole PT2 phase against the 40 B/pair group-by model (write + read of a
     # 16-byte key and a 4-byte value per pair)
     pt2_model = 40.0 * pairs
+    # PT2 where the method evaluates it, after convergence: the lowest eigenvector of
+    # H_SS (GPU Lanczos) stands in for a converged network; the timed step's PT2 runs on
+    # the random-init network's psi, where E sits inside the spread of H_aa (intruder
+    # terms), so its value is a timing figure only
+    conn = ctx.build_connections(dets, validate=False)
+    lz = ctx.lanczos(conn, max_iter=400, tol=1e-9)
+    vec = lz["vec"]
+    la_gs = torch.log(torch.abs(vec))
+    sg_gs = torch.sign(vec).to(torch.int8)
+    ctx.timing(True)
+    ctx.timing_reset()
+    gs = ctx.pt2(conn, la_gs, sg_gs, lz["E"])
+    torch.cuda.synchronize()
+    t_gs = ctx.timing_get("pt2")[0]
+    ctx.timing(False)
+    gso = gs["out"].cpu().numpy()
+    conn.free()
+    E_diag = lz["E"].item()
     line = {
         "metric": "amps+grads/s and H/PT2 elements/s at |S|=1e5; mixed vs FP32 at 1e-5 Ha",
         "value": n / (t_e * 1e-3),
@@ -385,12 +445,18 @@ def main():
             "pt2_pairs_per_s": pairs / (t_p * 1e-3), "pt2_pairs": pairs, "pt2_unique_P": int(c[1]),
             "pt2_sub_buckets": int(c[3]),
         },
-        "results": {"E": E, "dE_pt2": float(o[0]), "E_total": E + float(o[0]), "min_denominator": float(o[3])},
+        "results": {"E": E, "E_diag": E_diag, "lanczos_iters": lz["iters"], "lanczos_residual": lz["residual"],
+                    "dE_pt2_ground_state": float(gso[0]), "E_total_ground_state": E_diag + float(gso[0]),
+                    "min_denominator_ground_state": float(gso[3]), "pt2_ground_state_ms": t_gs,
+                    "dE_pt2_timed_step": float(o[0]), "min_denominator_timed_step": float(o[3]),
+                    "timed_step_note": "random-init network psi: timing only (E inside the H_aa spread)"},
         "precisions": compare,
         "autotune": ctx.tune_export().strip().splitlines(),
         "roofline": {"kernel": "k_pt2_reduce", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": red_bytes, "launch_ms": t_red},
+                     "algorithmic_bytes_per_launch": red_bytes, "model": "20 B/pair (read half of the group-by)",
+                     "launch_ms": t_red,
+                     "descriptor_stream_GBs": 8.0 * pairs / max(red_per_call, 1.0) / (t_red * 1e-3) / 1e9},
         "pt2_phase_roofline": {"model": "40 B/pair group-by", "bytes": pt2_model, "ms": t_p,
                                "achieved": pt2_model / (t_p * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": pt2_model / (t_p * 1e-3) / 1e9 / HBM_PEAK_GBS},

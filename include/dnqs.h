@@ -24,7 +24,8 @@
  *   "dev" = device memory of the context's device, "host" = host memory.  The caller
  *   owns every pointer it passes; the library never frees them and never keeps them
  *   past the call, except where a call says otherwise.  The library owns the context
- *   and connection objects and the device memory behind them.
+ *   and connection objects; the device memory behind them comes from the caller's
+ *   allocator given to dnqs_create (or from hipMalloc when none is given).
  *
  * Streams and synchronisation
  *   Work is enqueued on the context's stream (dnqs_create / dnqs_set_stream).
@@ -87,8 +88,19 @@ typedef struct {
 /* ------------------------------------------------------------------ context */
 
 /* Create a context on HIP device `device`, enqueuing on `stream` (a hipStream_t;
- * NULL = the null stream).  *out receives the context. */
-dnqs_status dnqs_create(dnqs_ctx **out, int device, void *stream);
+ * NULL = the null stream).  *out receives the context.
+ * Device memory: every buffer the library holds (staged integrals, connection objects,
+ * workspaces) is obtained from alloc(bytes, user) and returned through release(p, user)
+ * when both are given (e.g. a framework's caching allocator, which then stays the only
+ * owner of device memory; the memory must be usable on `stream` and on a second stream
+ * of the same device that the context creates, and is returned only after the work
+ * queued on both has finished); alloc returns NULL on failure (the call then fails with
+ * DNQS_ENOMEM; there is no fallback).  With both NULL the library uses hipMalloc /
+ * hipFree.  The callbacks are called from the thread that makes the library call, only
+ * outside dnqs_capture_begin / dnqs_capture_end, and must outlive the context and every
+ * connection object made with it. */
+dnqs_status dnqs_create(dnqs_ctx **out, int device, void *stream, void *(*alloc)(size_t bytes, void *user),
+                        void (*release)(void *p, void *user), void *user);
 void dnqs_destroy(dnqs_ctx *ctx);
 dnqs_status dnqs_set_stream(dnqs_ctx *ctx, void *stream);
 /* Message for the last failure on ctx (static storage owned by ctx); "" if none.
@@ -116,15 +128,49 @@ dnqs_status dnqs_set_integrals(dnqs_ctx *ctx, int slot, int M, int n_alpha, int 
  * is every pair of S at excitation rank 1 or 2 (the connected set of Eq. 1 read as
  * excitation rank <= 2, restricted to S).  The result keeps:
  *   row_ptr int64[n+1], col int32[nnz] (ascending within each row), val FP32[nnz]
- *   (off-diagonal only), diag FP64[n], a copy of S, and a device hash set of S.
+ *   (off-diagonal only), diag FP64[n], and a copy of S.
  * flags: DNQS_VALIDATE checks ordering, uniqueness and sector on the device first
- * (DNQS_EINVAL on failure).  *out receives a new object owned by the caller through
- * dnqs_conn_free.  1 <= n < 2^31.  Synchronises the stream. */
+ * (DNQS_EINVAL on failure).  DNQS_EMIT_P also lists the rest of the connected set,
+ * P = C(S) \ S (Eq. 1; Sec. 2.1's perturbative space), sorted in canonical order and
+ * unique, with its diagonal H_aa (FP64) and an order-free fingerprint of P:
+ * {sum over a in P of h(a) mod 2^64, XOR over a in P of h(a)} with the key hash
+ * h(a) = mix(alpha ^ mix(beta)), mix the SplitMix64 output function (the same
+ * fingerprint dnqs_pt2 reports for any size).  DNQS_EMIT_HPS (implies EMIT_P) also
+ * keeps H_PS: row a of P holds <a|H|x> for the x in S at excitation rank 1 or 2 from
+ * a, CSR with int64 row pointers, int32 columns ascending, FP32 values (the couplings
+ * Sec. 2.3's proxy objective and Eq. 13 use).  Listing P holds every pair (x, a) once:
+ * DNQS_ECAPACITY if |S| n_exc >= 2^31.  *out receives a new object owned by the caller
+ * through dnqs_conn_free.  1 <= n < 2^31.  Synchronises the stream. */
 #define DNQS_VALIDATE 1u
+#define DNQS_EMIT_P 2u
+#define DNQS_EMIT_HPS 4u
 dnqs_status dnqs_build_connections(dnqs_ctx *ctx, int slot, const uint64_t *dets, int64_t n, unsigned flags,
                                    dnqs_conn **out);
+/* Target set T = [V; P] of the target-space objectives (Sec. 2.3): V = the determinants of
+ * cv (an ordinary set from dnqs_build_connections), P = p_dets (dev uint64[n_p][2],
+ * canonical order, unique, none in V; DNQS_VALIDATE checks the order, the sector and
+ * that no member of P is in V; e.g. the screened set of dnqs_heatbath_candidates).  The
+ * result is a connection object over T, rows and amplitudes in the order V then P, whose
+ * matrix is the proxy Hamiltonian of Eq. 8: H_VV, H_VP and H_PV exact (Slater-Condon,
+ * FP32 values), the P-P block reduced to its FP64 diagonal.  dnqs_energy_and_grad on it
+ * evaluates the Proxy objective (Eqs. 9-10) or, with DNQS_ASYM / DNQS_ASYM_ESTIMATOR, the
+ * Asymmetric one (Eqs. 6-7).  The exact Rayleigh quotient over T that removes the proxy's
+ * bias after optimisation (Sec. 2.4) is dnqs_build_connections on T in canonical order
+ * (e.g. from dnqs_select_topk with K = |T|).  1 <= |V| + n_p < 2^31.  Synchronises the
+ * stream. */
+dnqs_status dnqs_build_target(dnqs_ctx *ctx, int slot, const dnqs_conn *cv, const uint64_t *p_dets, int64_t n_p,
+                              unsigned flags, dnqs_conn **out);
 /* n_dets, nnz (off-diagonal) of a connection object (host outputs, either may be NULL). */
 dnqs_status dnqs_conn_info(const dnqs_conn *conn, int64_t *n_dets, int64_t *nnz);
+/* |P|, nnz(H_PS) (-1 without DNQS_EMIT_HPS) and the fingerprint {sum, xor} of P (host
+ * outputs, any may be NULL); DNQS_ESTATE if P was not built. */
+dnqs_status dnqs_conn_p_info(const dnqs_conn *conn, int64_t *n_p, int64_t *nnz_ps, uint64_t *fingerprint);
+/* Copy P and H_PS into caller buffers (dev): p_dets uint64[|P|][2] (canonical order),
+ * p_diag FP64[|P|] (H_aa), row_ptr int64[|P|+1], col int32[nnz_ps], val FP32[nnz_ps];
+ * any pointer may be NULL to skip it.  DNQS_ESTATE if the part asked for was not built.
+ * Enqueued on the context's stream. */
+dnqs_status dnqs_conn_export_p(dnqs_ctx *ctx, const dnqs_conn *conn, uint64_t *p_dets, double *p_diag,
+                               int64_t *row_ptr, int32_t *col, float *val);
 /* The occupied-row plan of the output layer kept with the connections (see
  * dnqs_energy_and_grad): n_dense = orbitals computed densely, or -1 when the full-width
  * layer is used; n_entries = (configuration, other occupied orbital) rows.  Host
@@ -163,9 +209,44 @@ dnqs_status dnqs_amplitudes(dnqs_ctx *ctx, int slot, const dnqs_net *net, const 
  * is forked from and joined back to the context's stream with events, so the call is
  * still ordered with that stream as a whole (no fork inside dnqs_capture_begin/end). */
 #define DNQS_FULL_OUTPUT 1u
+/* On a target set T = [V; P] (dnqs_build_target), the default objective is the Proxy mode
+ * of Sec. 2.3: E = psi_T^T H~ psi_T / psi_T^T psi_T with the proxy Hamiltonian of Eq. 8,
+ * and grad its exact gradient (Eq. 10).  DNQS_ASYM selects the Asymmetric objective
+ * (Eq. 6), E = psi_V^T H_VT psi_T / psi_V^T psi_V (normalised on V, local energies over
+ * T), with its exact gradient (every amplitude of T differentiated: the terms through
+ * psi on P that Eq. 7 drops are included); DNQS_ASYM_ESTIMATOR the same energy with the
+ * gradient estimator of Eq. 7, 2 sum_V p_V(x) (E_loc(x) - E) d ln|psi(x)| (not the
+ * gradient of E: the paper's non-conservative field).  With either flag stats[0] is
+ * psi_V^T psi_V, stats[2] is psi_V^T H_VT psi_T, and v_out holds the vector v' whose
+ * residual 2 (v' - E psi) / psi_V^T psi_V is the derivative of E with respect to psi
+ * (exact) or the estimator's coefficient. */
+#define DNQS_ASYM 2u
+#define DNQS_ASYM_ESTIMATOR 4u
+/* DNQS_RECOMPUTE: keep only the last hidden layer h_{L-1} (the output layer reads it for
+ * every configuration); the embedding's occupations and h_1 .. h_{L-2} are formed by
+ * blocks of rows in the forward pass and formed again by block in the backward pass
+ * (micro-batched gradient accumulation, Sec. 3.1), so their memory is that of one block.
+ * The weight gradients' split-K partials fall on block boundaries, so the results equal
+ * those without the flag bit for bit.  No effect for networks with one hidden layer. */
+#define DNQS_RECOMPUTE 8u
 dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, const float *theta,
                                  const dnqs_conn *conn, int precision, unsigned flags, double *energy,
                                  double *stats, float *grad, double *v_out, double *log_abs, int8_t *sign);
+
+/* ------------------------------------------------------------------ Lanczos
+ * Lowest eigenpair of H_SS (conn) by the Lanczos iteration: E_diag = lambda_min(H_SS),
+ * the exact energy within the variational space that the post-optimisation analysis
+ * compares E with (Sec. 2.4), and its eigenvector, the converged psi at which Eq. 13 is
+ * evaluated.  The matrix is H_SS as stored (FP32 off-diagonal values, FP64 diagonal);
+ * Krylov vectors are FP64 and fully re-orthogonalised (two Gram-Schmidt rounds), every
+ * reduction in a fixed order (reproducible to the bit).  start: dev FP64[n] initial
+ * vector (NULL: the diagonal's lowest entries weighted up plus a fixed pseudo-random
+ * spread).  Stops when the Ritz residual |H y - lambda y| <= tol max(1, |lambda|), at
+ * max_iter (1..4096) vectors or on an invariant subspace.  energy: dev FP64[1]; vec:
+ * dev FP64[n] unit Ritz vector (NULL: not formed); iters, residual: host (NULL: not
+ * returned).  Holds (max_iter + 1) n FP64 values of workspace.  Synchronises the stream. */
+dnqs_status dnqs_lanczos(dnqs_ctx *ctx, const dnqs_conn *conn, int max_iter, double tol, const double *start,
+                         double *energy, double *vec, int *iters, double *residual);
 
 /* ------------------------------------------------------------------ PT2
  * Epstein-Nesbet correction of Eq. 13 for psi on S = conn's determinants, given
@@ -173,17 +254,31 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
  *   dE = ( sum_{a in S} (v_a - E psi_a)^2 / (E - H_aa)
  *        + sum_{a in P} w_a^2 / (E - H_aa) ) / psi^T psi,
  *   v = H_SS psi, w_a = sum_{x in S} H_ax psi_x, P = C(S) \ S (unscreened).
- * A term whose numerator is exactly 0 contributes 0.  |S| <= 2^24 (DNQS_EINVAL otherwise).
- * out (dev FP64[4]) = {dE, internal sum, external sum (both unnormalised), min|E-H_aa|}
- * counts (dev int64[4]) = {(x,a) pairs generated, |P|, terms with |E-H_aa| < 1e-8,
- *                          sub-buckets of the on-chip reduction}.
+ * Both sums use couplings computed in FP64 from the integrals (not the FP32 values of
+ * H_SS): every pair (x, a) of S x C(S) is generated once, and w_a (a in P) and the
+ * off-diagonal part of v_a (a in S) are summed from them.  A term whose numerator is
+ * exactly 0 contributes 0.  The sums do not depend on the order of the work on the
+ * device: w_a is accumulated in fixed point (integers), and each partial sum over keys
+ * exactly (integer limbs) before a fixed-order FP64 sum, so repeated calls give the
+ * same bits.  |S| <= 2^24 (DNQS_EINVAL otherwise).
+ * out (dev FP64[4]) = {dE, internal sum, external sum, min|E-H_aa|}; the two sums are
+ *   unnormalised and taken for psi scaled so that max_x |psi_x| = 1 (dE does not depend
+ *   on the scale)
+ * counts (dev int64[6]) = {(x,a) pairs generated, |P|, terms with |E-H_aa| < 1e-8,
+ *                          sub-buckets of the on-chip reduction, fingerprint of P:
+ *                          sum of h(a) mod 2^64, XOR of h(a) (as in dnqs_build_connections)}.
  * opts may be NULL.  With opts->sample_mask != 0 only keys a whose
  * SplitMix64-based key hash h(a) = mix(alpha ^ mix(beta)) has (h & sample_mask) == 0
- * enter the external sum and |P| (the internal sum is always complete).  With
- * opts->export_cap > 0 up to export_cap kept keys are written to export_keys
- * (dev uint64[cap][2]) with export_w (w_a, for psi scaled so that max_x |psi_x| = 1)
- * and export_haa (H_aa) (dev FP64[cap]), and the number of kept keys to export_count
- * (dev int64[1]; may exceed export_cap).
+ * enter the external sum, |P| and the fingerprint (the internal sum is always
+ * complete).  With opts->export_cap > 0 up to export_cap kept keys are written to
+ * export_keys (dev uint64[cap][2]) with export_w (w_a, for psi scaled so that
+ * max_x |psi_x| = 1) and export_haa (H_aa) (dev FP64[cap]), and the number of kept keys
+ * to export_count (dev int64[1]; may exceed export_cap).  When all kept keys fit
+ * (count <= cap) they are in canonical order.
+ * With opts->eps_hb > 0 the external sum, |P|, the fingerprint and the export cover only
+ * the heat-bath-screened set of Eq. 14 (Sec. 3.2): the a in P whose largest coupling
+ * max_x |H_ax psi_x| reaches eps_hb for psi normalised to ||psi||_2 = 1; each such a
+ * with its whole w_a (eps_hb = 0: all of P).
  * Memory: the external sum materialises an 8-byte descriptor per (x, a) pair twice.
  * When 16 bytes x pairs exceed opts->max_pair_bytes (0: half of the free device memory
  * at the call), the key space is cut into 2^k slices by the top k bits of the key hash
@@ -198,9 +293,34 @@ typedef struct {
     double *export_haa;
     int64_t *export_count;
     int64_t max_pair_bytes;
+    double eps_hb;
 } dnqs_pt2_opts;
 dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const double *log_abs, const int8_t *sign,
                      const double *energy, const dnqs_pt2_opts *opts, double *out, int64_t *counts);
+
+/* ------------------------------------------------------------------ subspace evolution
+ * The two steps of Algorithm 1's outer loop that change the variational set.
+ *
+ * dnqs_heatbath_candidates: the screened perturbative set P_k of step 1 (Eq. 14,
+ * Sec. 3.2) for psi on S = conn's determinants, given as (log_abs, sign) (dev, any
+ * scale): every a outside S at excitation rank 1 or 2 from some x in S with
+ * max_x |<a|H|x> psi_x| >= eps_hb for psi normalised to ||psi||_2 = 1 (eps_hb = 0: all of
+ * P = C(S) \ S), sorted in canonical order and unique.  The first min(|P_k|, cap)
+ * determinants go to out_dets (dev uint64[cap][2]); *n_out (host) = |P_k|, which may
+ * exceed cap (call again with a larger buffer).  Every (x, a) candidate is held once:
+ * DNQS_ECAPACITY if |S| n_exc >= 2^31.  Synchronises the stream.
+ *
+ * dnqs_select_topk: the Top-K selector of step 3 (Sec. 2.4, Fixed-Size Selection): of the
+ * n determinants dets (dev uint64[n][2], any order, unique) with amplitudes
+ * (log_abs, sign) (dev; sign NULL: all non-zero; sign 0 counts as the smallest), the
+ * min(K, n) with the largest |psi| (equal |psi|: the lower determinant first), written in
+ * canonical order to out_dets (dev uint64[K][2]); *n_out (host) = min(K, n).
+ * Synchronises the stream. */
+dnqs_status dnqs_heatbath_candidates(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const double *log_abs,
+                                     const int8_t *sign, double eps_hb, int64_t cap, uint64_t *out_dets,
+                                     int64_t *n_out);
+dnqs_status dnqs_select_topk(dnqs_ctx *ctx, int slot, const uint64_t *dets, const double *log_abs,
+                             const int8_t *sign, int64_t n, int64_t K, uint64_t *out_dets, int64_t *n_out);
 
 /* ------------------------------------------------------------------ batched geometries
  * Several independent problems (e.g. the geometries of a dissociation curve), each with

@@ -4,7 +4,8 @@ energy and gradient, and Epstein-Nesbet PT2, as hand-written HIP kernels for gfx
 behind a C ABI (include/dnqs.h).  This package is the Python binding.
 """
 from ._native import (FP32, MIXED, SPLIT_BF16, Connections, Context, DetNQSEnergy, DnqsError, Graph, LIB_PATH,
+                      TorchAllocator,
                       dets_to_device, dets_to_host, lib)
 
-__all__ = ["FP32", "MIXED", "SPLIT_BF16", "Connections", "Context", "DetNQSEnergy", "DnqsError", "Graph", "LIB_PATH",
+__all__ = ["FP32", "MIXED", "SPLIT_BF16", "Connections", "Context", "TorchAllocator", "DetNQSEnergy", "DnqsError", "Graph", "LIB_PATH",
            "dets_to_device", "dets_to_host", "lib"]

@@ -18,7 +18,12 @@ LIB_PATH = os.path.join(HERE, "libdnqs.so")
 MAX_LAYERS = 8
 FP32, MIXED, SPLIT_BF16 = 0, 1, 2
 VALIDATE = 1
+EMIT_P = 2
+EMIT_HPS = 4
 FULL_OUTPUT = 1
+ASYM = 2
+ASYM_ESTIMATOR = 4
+RECOMPUTE = 8
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ECAPACITY", -5: "ESTATE", -6: "EDOMAIN"}
 
@@ -57,7 +62,41 @@ class AdamwCfg(C.Structure):
 class PT2Opts(C.Structure):
     _fields_ = [("sample_mask", C.c_uint64), ("export_cap", C.c_int64), ("export_keys", C.c_void_p),
                 ("export_w", C.c_void_p), ("export_haa", C.c_void_p), ("export_count", C.c_void_p),
-                ("max_pair_bytes", C.c_int64)]
+                ("max_pair_bytes", C.c_int64), ("eps_hb", C.c_double)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class TorchAllocator:
+    """Device memory for the library from torch's caching allocator, on the context's
+    stream (torch stays the only owner of device memory).  Counts calls and live bytes."""
+
+    def __init__(self, device: int, stream: int):
+        self.device = device
+        self.stream = stream
+        self.n_alloc = 0
+        self.n_release = 0
+        self.live = {}
+
+    def alloc(self, nbytes: int):
+        try:
+            p = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+        except torch.cuda.OutOfMemoryError:
+            return None
+        self.n_alloc += 1
+        self.live[p] = int(nbytes)
+        return p
+
+    def release(self, p: int):
+        self.n_release += 1
+        self.live.pop(p, None)
+        torch.cuda.caching_allocator_delete(p)
+
+    @property
+    def live_bytes(self):
+        return sum(self.live.values())
 
 
 _lib = None
@@ -72,7 +111,7 @@ def lib():
                               "python paper_2601_21310_amd/build.py")
         L = C.CDLL(LIB_PATH)
         vp, i64, i32, u64, dbl = C.c_void_p, C.c_int64, C.c_int, C.c_uint64, C.c_double
-        L.dnqs_create.argtypes = [C.POINTER(vp), i32, vp]
+        L.dnqs_create.argtypes = [C.POINTER(vp), i32, vp, ALLOC_FN, RELEASE_FN, vp]
         L.dnqs_destroy.argtypes = [vp]
         L.dnqs_destroy.restype = None
         L.dnqs_set_stream.argtypes = [vp, vp]
@@ -84,12 +123,18 @@ def lib():
         L.dnqs_build_connections.argtypes = [vp, i32, vp, i64, C.c_uint, C.POINTER(vp)]
         L.dnqs_conn_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
         L.dnqs_conn_output_plan.argtypes = [vp, C.POINTER(i32), C.POINTER(i64)]
+        L.dnqs_conn_p_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(u64)]
+        L.dnqs_build_target.argtypes = [vp, i32, vp, vp, i64, C.c_uint, C.POINTER(vp)]
+        L.dnqs_conn_export_p.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.dnqs_conn_export.argtypes = [vp, vp, vp, vp, vp, vp]
         L.dnqs_conn_free.argtypes = [vp]
         L.dnqs_conn_free.restype = None
         L.dnqs_amplitudes.argtypes = [vp, i32, C.POINTER(Net), vp, vp, i64, i32, vp, vp]
         L.dnqs_energy_and_grad.argtypes = [vp, i32, C.POINTER(Net), vp, vp, i32, C.c_uint, vp, vp, vp, vp, vp, vp]
         L.dnqs_pt2.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(PT2Opts), vp, vp]
+        L.dnqs_lanczos.argtypes = [vp, vp, i32, dbl, vp, vp, vp, C.POINTER(i32), C.POINTER(dbl)]
+        L.dnqs_heatbath_candidates.argtypes = [vp, i32, vp, vp, vp, dbl, i64, vp, C.POINTER(i64)]
+        L.dnqs_select_topk.argtypes = [vp, i32, vp, vp, vp, i64, i64, vp, C.POINTER(i64)]
         L.dnqs_energy_and_grad_batched.argtypes = [vp, C.POINTER(Net), i32, C.POINTER(Problem), i32, C.c_uint]
         L.dnqs_adamw_batched.argtypes = [vp, C.POINTER(Net), i32, C.POINTER(Problem), vp, vp, C.POINTER(AdamwCfg), vp]
         L.dnqs_capture_begin.argtypes = [vp]
@@ -105,7 +150,8 @@ def lib():
         L.dnqs_tune_export.restype = i64
         L.dnqs_tune_import.argtypes = [vp, C.c_char_p]
         for fn in ("dnqs_create", "dnqs_set_stream", "dnqs_set_integrals", "dnqs_build_connections",
-                   "dnqs_conn_info", "dnqs_conn_output_plan", "dnqs_conn_export", "dnqs_amplitudes", "dnqs_energy_and_grad", "dnqs_pt2",
+                   "dnqs_conn_info", "dnqs_conn_output_plan", "dnqs_build_target", "dnqs_conn_export", "dnqs_conn_p_info", "dnqs_conn_export_p", "dnqs_amplitudes", "dnqs_energy_and_grad", "dnqs_pt2", "dnqs_lanczos",
+                   "dnqs_heatbath_candidates", "dnqs_select_topk",
                    "dnqs_energy_and_grad_batched", "dnqs_adamw_batched", "dnqs_capture_begin", "dnqs_capture_end",
                    "dnqs_graph_launch", "dnqs_timing_enable", "dnqs_timing_reset", "dnqs_timing_get",
                    "dnqs_autotune", "dnqs_tune_import"):
@@ -160,6 +206,32 @@ class Connections:
         torch.cuda.current_stream(dev).synchronize()
         return row_ptr, col[: self.nnz], val[: self.nnz], diag
 
+    def p_info(self):
+        """(|P|, nnz(H_PS) or -1, (fingerprint sum, fingerprint xor)) of a set built with emit_p."""
+        np_, nnz = C.c_int64(), C.c_int64()
+        fp = (C.c_uint64 * 2)()
+        self._ctx._check(lib().dnqs_conn_p_info(self.handle, C.byref(np_), C.byref(nnz), fp))
+        return np_.value, nnz.value, (int(fp[0]), int(fp[1]))
+
+    def export_p(self):
+        """(P int64[|P|,2], H_aa float64, and when built H_PS row_ptr int64, col int32, val float32)."""
+        dev = self._ctx.device
+        n_p, nnz, _ = self.p_info()
+        pd = torch.empty((max(n_p, 1), 2), dtype=torch.int64, device=f"cuda:{dev}")
+        pdiag = torch.empty(max(n_p, 1), dtype=torch.float64, device=f"cuda:{dev}")
+        rp = col = val = None
+        if nnz >= 0:
+            rp = torch.empty(n_p + 1, dtype=torch.int64, device=f"cuda:{dev}")
+            col = torch.empty(max(nnz, 1), dtype=torch.int32, device=f"cuda:{dev}")
+            val = torch.empty(max(nnz, 1), dtype=torch.float32, device=f"cuda:{dev}")
+        self._ctx._check(lib().dnqs_conn_export_p(self._ctx.handle, self.handle, _ptr(pd), _ptr(pdiag), _ptr(rp),
+                                                   _ptr(col), _ptr(val)))
+        torch.cuda.current_stream(dev).synchronize()
+        res = {"p": pd[:n_p], "diag": pdiag[:n_p]}
+        if nnz >= 0:
+            res.update(row_ptr=rp, col=col[:nnz], val=val[:nnz])
+        return res
+
     def free(self):
         if self.handle:
             lib().dnqs_conn_free(self.handle)
@@ -173,18 +245,39 @@ class Connections:
 
 
 class Context:
-    """One library context on one GPU, enqueuing on torch's current stream."""
+    """One library context on one GPU, enqueuing on torch's current stream.
 
-    def __init__(self, device: int = 0):
+    allocator: "torch" (default: torch's caching allocator, a TorchAllocator), None (the
+    library's own hipMalloc / hipFree) or an object with alloc(nbytes) -> int or None and
+    release(ptr)."""
+
+    def __init__(self, device: int = 0, allocator="torch"):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the dnqs library runs only on gfx950 GPUs")
         self.device = device
         h = C.c_void_p()
         stream = torch.cuda.current_stream(device).cuda_stream
-        st = lib().dnqs_create(C.byref(h), device, C.c_void_p(stream))
+        if allocator == "torch":
+            allocator = TorchAllocator(device, stream)
+        self.allocator = allocator
+        if allocator is None:
+            self._cb = (ALLOC_FN(), RELEASE_FN())
+        else:
+            def _alloc(nbytes, user, _a=allocator):
+                try:
+                    return _a.alloc(nbytes)
+                except Exception:
+                    return None
+
+            def _release(p, user, _a=allocator):
+                _a.release(p)
+
+            self._cb = (ALLOC_FN(_alloc), RELEASE_FN(_release))
+        st = lib().dnqs_create(C.byref(h), device, C.c_void_p(stream), self._cb[0], self._cb[1], None)
         if st != 0:
             raise DnqsError(st, lib().dnqs_last_error(None).decode())
         self.handle = h
+        self.stream = stream
         self._slots = {}
 
     def _check(self, st):
@@ -193,7 +286,11 @@ class Context:
 
     def sync_stream(self):
         """Point the context at torch's current stream."""
-        self._check(lib().dnqs_set_stream(self.handle, C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)))
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        self._check(lib().dnqs_set_stream(self.handle, C.c_void_p(stream)))
+        self.stream = stream
+        if isinstance(self.allocator, TorchAllocator):
+            self.allocator.stream = stream
 
     def close(self):
         if getattr(self, "handle", None):
@@ -220,13 +317,25 @@ class Context:
     def shape(self, slot=0):
         return self._slots[slot]
 
-    def build_connections(self, dets, slot=0, validate=True) -> Connections:
+    def build_connections(self, dets, slot=0, validate=True, emit_p=False, emit_hps=False) -> Connections:
         dets = _dev_tensor(dets, torch.int64, "dets", self.device)
         n = dets.shape[0]
         h = C.c_void_p()
-        self._check(lib().dnqs_build_connections(self.handle, slot, _ptr(dets), n, VALIDATE if validate else 0,
-                                                 C.byref(h)))
+        flags = (VALIDATE if validate else 0) | (EMIT_P if emit_p else 0) | (EMIT_HPS if emit_hps else 0)
+        self._check(lib().dnqs_build_connections(self.handle, slot, _ptr(dets), n, flags, C.byref(h)))
         return Connections(self, h, slot, dets)
+
+    def build_target(self, conn: Connections, p_dets, validate=True) -> Connections:
+        """The target set T = [V; P] of conn's V and the determinants p_dets (proxy matrix
+        of Eq. 8); energy_and_grad on it evaluates the Proxy or Asymmetric objective."""
+        p_dets = _dev_tensor(p_dets, torch.int64, "p_dets", self.device)
+        h = C.c_void_p()
+        self._check(lib().dnqs_build_target(self.handle, conn.slot, conn.handle, _ptr(p_dets), p_dets.shape[0],
+                                            VALIDATE if validate else 0, C.byref(h)))
+        T = torch.cat([conn.dets, p_dets], dim=0)
+        c = Connections(self, h, conn.slot, T)
+        c.n_v = conn.n
+        return c
 
     def param_count(self, widths, slot=0):
         M, na, nb = self._slots[slot]
@@ -246,7 +355,9 @@ class Context:
         return la, sg
 
     def energy_and_grad(self, widths, theta, conn: Connections, want_grad=True, precision=FP32, keep=True,
-                        full_output=False):
+                        full_output=False, mode="default", recompute=False):
+        """mode: "default" (Eq. 11 on a set S; the Proxy objective on a target set), "asym"
+        (Eq. 6 with its exact gradient) or "asym_estimator" (Eq. 6 with Eq. 7's estimator)."""
         theta = _dev_tensor(theta, torch.float32, "theta", self.device)
         if theta.numel() != self.param_count(widths, conn.slot):
             raise ValueError("theta has the wrong size for this network")
@@ -259,21 +370,25 @@ class Context:
         la = torch.empty(n, dtype=torch.float64, device=dev) if keep else None
         sg = torch.empty(n, dtype=torch.int8, device=dev) if keep else None
         net = Net.from_widths(widths)
+        flags = (FULL_OUTPUT if full_output else 0) | {"default": 0, "asym": ASYM, "asym_estimator": ASYM_ESTIMATOR}[mode]
+        flags |= RECOMPUTE if recompute else 0
         self._check(lib().dnqs_energy_and_grad(self.handle, conn.slot, C.byref(net), _ptr(theta), conn.handle,
-                                               precision, FULL_OUTPUT if full_output else 0, _ptr(E), _ptr(stats),
-                                               _ptr(grad), _ptr(v), _ptr(la), _ptr(sg)))
+                                               precision, flags, _ptr(E), _ptr(stats), _ptr(grad), _ptr(v), _ptr(la),
+                                               _ptr(sg)))
         return {"E": E, "stats": stats, "grad": grad, "v": v, "logabs": la, "sign": sg}
 
-    def pt2(self, conn: Connections, logabs, sign, energy, sample_mask=0, export_cap=0, max_pair_bytes=0):
+    def pt2(self, conn: Connections, logabs, sign, energy, sample_mask=0, export_cap=0, max_pair_bytes=0,
+            eps_hb=0.0):
         dev = energy.device
         logabs = _dev_tensor(logabs, torch.float64, "logabs", self.device)
         sign = _dev_tensor(sign, torch.int8, "sign", self.device)
         energy = _dev_tensor(energy, torch.float64, "energy", self.device)
         out = torch.empty(4, dtype=torch.float64, device=dev)
-        counts = torch.empty(4, dtype=torch.int64, device=dev)
+        counts = torch.empty(6, dtype=torch.int64, device=dev)
         opts = PT2Opts()
         opts.sample_mask = int(sample_mask)
         opts.max_pair_bytes = int(max_pair_bytes)
+        opts.eps_hb = float(eps_hb)
         ex = None
         if export_cap > 0:
             ex = {"keys": torch.empty((export_cap, 2), dtype=torch.int64, device=dev),
@@ -291,6 +406,48 @@ class Context:
         if ex is not None:
             res["export"] = ex
         return res
+
+    def lanczos(self, conn: Connections, max_iter=300, tol=1e-10, start=None, want_vec=True):
+        """Lowest eigenpair of H_SS: {"E": dev float64[1], "vec": dev float64[n] or None,
+        "iters": int, "residual": float}."""
+        dev = f"cuda:{self.device}"
+        E = torch.empty(1, dtype=torch.float64, device=dev)
+        vec = torch.empty(conn.n, dtype=torch.float64, device=dev) if want_vec else None
+        if start is not None:
+            start = _dev_tensor(start, torch.float64, "start", self.device)
+        it, res = C.c_int(), C.c_double()
+        self._check(lib().dnqs_lanczos(self.handle, conn.handle, int(max_iter), float(tol), _ptr(start), _ptr(E),
+                                       _ptr(vec), C.byref(it), C.byref(res)))
+        return {"E": E, "vec": vec, "iters": it.value, "residual": res.value}
+
+    def heatbath_candidates(self, conn: Connections, logabs, sign, eps_hb, cap=None):
+        """The screened perturbative set P_k (Eq. 14) as a dev int64[|P_k|, 2] tensor
+        in canonical order."""
+        logabs = _dev_tensor(logabs, torch.float64, "logabs", self.device)
+        sign = _dev_tensor(sign, torch.int8, "sign", self.device)
+        cap = int(cap) if cap is not None else 1 << 20
+        while True:
+            out = torch.empty((max(cap, 1), 2), dtype=torch.int64, device=logabs.device)
+            n = C.c_int64()
+            self._check(lib().dnqs_heatbath_candidates(self.handle, conn.slot, conn.handle, _ptr(logabs), _ptr(sign),
+                                                       float(eps_hb), cap, _ptr(out), C.byref(n)))
+            if n.value <= cap:
+                return out[: n.value]
+            cap = n.value
+
+    def select_topk(self, dets, logabs, sign, K, slot=0):
+        """The min(K, n) determinants of dets with the largest |psi| (ties: lower first),
+        in canonical order (dev int64[k, 2])."""
+        dets = _dev_tensor(dets, torch.int64, "dets", self.device)
+        logabs = _dev_tensor(logabs, torch.float64, "logabs", self.device)
+        if sign is not None:
+            sign = _dev_tensor(sign, torch.int8, "sign", self.device)
+        n = dets.shape[0]
+        out = torch.empty((max(min(n, K), 1), 2), dtype=torch.int64, device=dets.device)
+        k = C.c_int64()
+        self._check(lib().dnqs_select_topk(self.handle, slot, _ptr(dets), _ptr(logabs), _ptr(sign), n, int(K),
+                                           _ptr(out), C.byref(k)))
+        return out[: k.value]
 
     # -------------------------------------------------------------- batched geometries
     def batch(self, widths, slots, conns, thetas, want_grad=True):

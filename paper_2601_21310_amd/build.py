@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdnqs.so")
-SOURCES = ["dnqs_api.hip", "k_hamiltonian.hip", "k_network.hip", "k_energy.hip", "k_pt2.hip", "k_pt2_part.hip", "k_pt2_reduce.hip", "k_gemm_x3.hip", "k_batch.hip", "k_optim.hip", "k_outsplit.hip"]
+SOURCES = ["dnqs_api.hip", "k_hamiltonian.hip", "k_network.hip", "k_energy.hip", "k_pt2.hip", "k_pt2_part.hip", "k_pt2_reduce.hip", "k_gemm_x3.hip", "k_batch.hip", "k_optim.hip", "k_outsplit.hip", "k_sort.hip", "k_pset.hip", "k_lanczos.hip", "k_modes.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

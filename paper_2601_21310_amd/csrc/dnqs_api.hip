@@ -25,6 +25,8 @@ struct Slot {
     double ecore = 0.0;
     double *h64 = nullptr, *eri64 = nullptr, *J = nullptr, *K = nullptr, *eri_pk = nullptr;
     float *eri32 = nullptr;
+    // 2^wexp bounds every |<a|H|x>| of the sector (a != x): max|h| + 2 N_e max|(pq|rs)|
+    int wexp = 0;
 };
 
 struct Buf {
@@ -59,6 +61,31 @@ thread_local std::string g_create_error;
 
 }  // namespace
 
+// Where the library's device memory comes from: the caller's allocator (e.g. torch's
+// caching allocator, so that the caller stays the only owner of device memory), or
+// hipMalloc / hipFree when the caller brings none.  dev_alloc and dev_free are the only
+// places device memory is obtained and returned.
+struct DevAlloc {
+    void *(*alloc)(size_t bytes, void *user) = nullptr;
+    void (*release)(void *p, void *user) = nullptr;
+    void *user = nullptr;
+};
+
+static hipError_t dev_alloc(const DevAlloc &a, void **p, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (!a.alloc) return hipMalloc(p, bytes);
+    *p = a.alloc(bytes, a.user);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+
+static void dev_free(const DevAlloc &a, void *p) {
+    if (!p) return;
+    if (!a.alloc)
+        (void)hipFree(p);
+    else
+        a.release(p, a.user);
+}
+
 // Concatenated layout of a batch of problems (built once per set of conns).
 struct BatchPlan {
     bool valid = false;
@@ -74,7 +101,13 @@ struct BatchPlan {
     double *diag = nullptr;
     int *tile_pid = nullptr;  // per 128-row tile
     int2 *ksplit = nullptr;   // weight-gradient k ranges, problem by problem
-    int *zoff = nullptr;      // first ksplit entry of each problem
+    int2 *zrange = nullptr;   // ksplit entries [x, y) of each problem
+    std::vector<int64_t> end; // end of each problem's padded span
+    // work items of the per-problem reductions: {problem, first row, rows, 0}, largest
+    // problem first (one workgroup each); per-item partials
+    int4 *items = nullptr;
+    int nitems = 0;
+    double *ipart = nullptr;
     int nz = 0;
     // per-call pointers (rebuilt when they change, outside any capture)
     std::vector<ProbDev> P_h;
@@ -86,6 +119,7 @@ struct BatchPlan {
 
 struct dnqs_ctx {
     int device = 0;
+    DevAlloc alloc;
     hipStream_t stream = nullptr;
     std::string err;
     Slot slots[DNQS_MAX_SLOTS];
@@ -104,6 +138,10 @@ struct dnqs_ctx {
     hipEvent_t ev_fwd[2] = {};  // forward output layer: input ready, sparse rows done
 };
 
+namespace {
+void plan_free(dnqs_ctx *ctx, BatchPlan &b);
+}
+
 struct dnqs_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -112,6 +150,7 @@ struct dnqs_graph {
 
 struct dnqs_conn {
     int device = 0;
+    DevAlloc alloc;
     int slot = 0;
     int M = 0, na = 0, nb = 0;
     int64_t n = 0, nnz = 0;
@@ -120,9 +159,16 @@ struct dnqs_conn {
     int32_t *col = nullptr;
     float *val = nullptr;
     double *diag = nullptr;
-    uint64_t *set_keys = nullptr;
-    int32_t *set_idx = nullptr;
-    uint64_t set_mask = 0;
+    // target set T = [V; P] (dnqs_build_target): n_v = |V| (0: an ordinary set S)
+    int64_t n_v = 0;
+    // P = C(S) \ S (DNQS_EMIT_P) and H_PS (DNQS_EMIT_HPS); p_n < 0: not built
+    int64_t p_n = -1, ps_nnz = -1;
+    uint64_t p_fp[2] = {0, 0};
+    uint64_t *p_dets = nullptr;
+    double *p_diag = nullptr;
+    int64_t *ps_row_ptr = nullptr;
+    int32_t *ps_col = nullptr;
+    float *ps_val = nullptr;
     // occupied-row plan of the orbital output layer (k_outsplit.hip); os_nd < 0: not used
     int os_nd = -1;
     int64_t os_ne = 0, os_ntiles = 0, os_nitems = 0;
@@ -162,13 +208,13 @@ dnqs_status ws_get(dnqs_ctx *ctx, const std::string &name, size_t bytes, void **
             // queued kernels may still use the old buffer (on either stream)
             HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
             if (ctx->aux) HIPCHK(ctx, hipStreamSynchronize(ctx->aux));
-            HIPCHK(ctx, hipFree(b.p));
+            dev_free(ctx->alloc, b.p);
         }
         b.p = nullptr;
         b.bytes = 0;
         size_t want = bytes + bytes / 8;
         want = (want + 255) & ~(size_t)255;
-        hipError_t e = hipMalloc(&b.p, want);
+        hipError_t e = dev_alloc(ctx->alloc, &b.p, want);
         if (e != hipSuccess) {
             b.p = nullptr;
             (void)hipGetLastError();
@@ -395,27 +441,101 @@ std::vector<GemmCfg> gemm_candidates(int M, int N, int64_t K, bool wgrad, bool p
 
 bool precision_ok(int p) { return p == DNQS_FP32 || p == DNQS_MIXED || p == DNQS_SPLIT_BF16; }
 
+// Split-K of a weight gradient over K rows: chunks of a power of two rows (at least 256),
+// so that the ranges of a split count are the same whether the rows are processed at
+// once or in blocks of any larger power of two (the activation-recomputing backward
+// reproduces the stored one's partial sums exactly).
+int wgrad_chunk(int64_t K, int splits) {
+    int64_t want = (K + std::max(splits, 1) - 1) / std::max(splits, 1);
+    int64_t c = 256;
+    while (c < want) c <<= 1;
+    return (int)c;
+}
+
+// The configuration a weight-gradient GEMM of this shape runs with: the tuned one, else
+// the default (first candidate).
+GemmCfg wgrad_cfg(dnqs_ctx *ctx, int eng, int M, int N, int64_t K) {
+    auto it = ctx->tuned.find(TuneKey{eng, 1, M, N, (int)K});
+    if (it != ctx->tuned.end()) return it->second;
+    return gemm_candidates(M, N, K, true, false)[0];
+}
+
+// Embedding and hidden layers 1 .. upto (<= L-1) for nb configurations (a block of rows):
+// U (the occupations, if given), the layers into block workspaces returned in hs[], except
+// h_{L-1}, which goes to `last` when that is given.
+dnqs_status hidden_block(dnqs_ctx *ctx, const Slot &sl, const NetView &nv, const float *theta, const uint64_t *dets,
+                         int64_t nb, int precision, float *U, float *last, float **hs, int upto) {
+    hipStream_t st = ctx->stream;
+    const int M = sl.M, L = nv.L;
+    const int *w = nv.w;
+    float *h = nullptr;
+    if (L == 2 && last)
+        h = last;
+    else
+        TRY(ws_t(ctx, "rc_h1", (size_t)nb * w[1], &h));
+    launch_embed(st, dets, nb, M, w[1], theta + nv.offW[1], theta + nv.offb[1], h, U);
+    CHECK_LAUNCH(ctx);
+    hs[1] = h;
+    for (int l = 2; l <= upto; ++l) {
+        float *out = nullptr;
+        if (l == L - 1 && last)
+            out = last;
+        else
+            TRY(ws_t(ctx, "rc_h" + std::to_string(l), (size_t)nb * w[l], &out));
+        GemmArgs g{};
+        g.M = (int)nb;
+        g.N = w[l];
+        g.K = w[l - 1];
+        g.A = hs[l - 1];
+        g.lda = w[l - 1];
+        g.B = theta + nv.offW[l];
+        g.ldb = w[l];
+        g.C = out;
+        g.ldc = w[l];
+        g.bias = theta + nv.offb[l];
+        g.ones_row = -1;
+        const int eng = gemm_engine(precision, false);
+        if (eng == 1) TRY(weight_planes(ctx, "wpT" + std::to_string(l), theta + nv.offW[l], w[l - 1], w[l], true, g));
+        TRY(tuned_launch(ctx, TuneKey{eng, 0, g.M, g.N, g.K}, gemm_candidates(g.M, g.N, g.K, false, false),
+                         [&](const GemmCfg &c) -> dnqs_status {
+                             launch_gemm(eng, st, g, true, true, EPI_BIAS_TANH, 1, c.tm);
+                             CHECK_LAUNCH(ctx);
+                             return DNQS_OK;
+                         }));
+        hs[l] = out;
+    }
+    return DNQS_OK;
+}
+
 // Forward pass: activations h_1..h_{L-1} kept in workspaces "h1".. (FP32), output layer
 // in "O" (FP32), then orbital rows + LU.  With want_grad also U (occupations) and A^-1.
 // With a connections object that carries an occupied-row plan, the output layer is
 // computed in that form ("O" then holds the dense orbitals' columns, "os_Osp" the entries).
 dnqs_status forward(dnqs_ctx *ctx, const Slot &sl, const NetView &nv, const float *theta, const uint64_t *dets,
                     int64_t n, int precision, bool want_grad, double *logabs, int8_t *sign, float **Ainv_out,
-                    const dnqs_conn *conn = nullptr) {
+                    const dnqs_conn *conn = nullptr, const float *given_last = nullptr) {
     hipStream_t st = ctx->stream;
     const size_t esz = sizeof(float);
     const int M = sl.M, No = 2 * M, Ne = sl.na + sl.nb, L = nv.L;
     const int *w = nv.w;
-    void *U = nullptr;
-    if (want_grad) TRY(ws_get(ctx, "U", (size_t)n * No * esz, &U));
-    void *h = nullptr;
-    TRY(ws_get(ctx, "h1", (size_t)n * w[1] * esz, &h));
-    launch_embed(st, dets, n, M, w[1], theta + nv.offW[1], theta + nv.offb[1], (float *)h, (float *)U);
-    CHECK_LAUNCH(ctx);
-    void *prev = h;
+    void *prev = nullptr;
+    int l0 = 2;
+    if (given_last) {
+        // the hidden layers were formed elsewhere (by blocks of rows): output layer and LU only
+        prev = (void *)given_last;
+        l0 = L;
+    } else {
+        void *U = nullptr;
+        if (want_grad) TRY(ws_get(ctx, "U", (size_t)n * No * esz, &U));
+        void *h = nullptr;
+        TRY(ws_get(ctx, "h1", (size_t)n * w[1] * esz, &h));
+        launch_embed(st, dets, n, M, w[1], theta + nv.offW[1], theta + nv.offb[1], (float *)h, (float *)U);
+        CHECK_LAUNCH(ctx);
+        prev = h;
+    }
     OutSplit os{};
     const bool split = conn && conn->os_nd >= 0 && L >= 2 && os_fwd_fits(w[L - 1], Ne);
-    for (int l = 2; l <= L; ++l) {
+    for (int l = l0; l <= L; ++l) {
         if (l == L && split) {
             const int nd = conn->os_nd, wd = nd * Ne, din = w[L - 1];
             float *WD = nullptr, *OD = nullptr, *Osp = nullptr;
@@ -509,6 +629,87 @@ dnqs_status forward(dnqs_ctx *ctx, const Slot &sl, const NetView &nv, const floa
     return DNQS_OK;
 }
 
+// Layers L-1 .. 1 of the backward pass by blocks of RB rows, recomputing U and
+// h_1 .. h_{L-2} of each block: delta_{L-1} (all rows) is given.  Each block forms the
+// split-K partials of every weight gradient over its own rows (chunk rc_chunk[l], RB a
+// multiple of it, so its splits are the stored pass's) and folds them, in split order,
+// onto the gradient: the same left-to-right sum as the stored pass's one reduction.
+dnqs_status backward_blocks(dnqs_ctx *ctx, const Slot &sl, const NetView &nv, const float *theta,
+                            const uint64_t *dets, int64_t n, int precision, int64_t RB, const int *rc_chunk,
+                            const GemmCfg *rc_cfg, const float *deltaL1, int maxw, float *grad) {
+    hipStream_t st = ctx->stream;
+    const int M = sl.M, No = 2 * M, L = nv.L;
+    const int *w = nv.w;
+    int64_t cnt[DNQS_MAX_LAYERS + 1] = {};
+    const int64_t rb = std::min(RB, n);
+    size_t part_len = 1;
+    for (int l = 1; l <= L - 1; ++l) {
+        cnt[l] = (int64_t)(w[l - 1] + 1) * w[l];
+        part_len = std::max(part_len, (size_t)cnt[l] * (size_t)((rb + rc_chunk[l] - 1) / rc_chunk[l]));
+    }
+    float *part = nullptr;  // one block's split partials of one layer
+    TRY(ws_t(ctx, "rc_part", part_len, &part));
+    float *U = nullptr, *dblk[2] = {};
+    TRY(ws_t(ctx, "rc_U", (size_t)rb * No, &U));
+    TRY(ws_t(ctx, "rc_d0", (size_t)rb * maxw, &dblk[0]));
+    TRY(ws_t(ctx, "rc_d1", (size_t)rb * maxw, &dblk[1]));
+    const int eng = gemm_engine(precision, false);
+    for (int64_t r0 = 0; r0 < n; r0 += RB) {
+        const int64_t nb = std::min(RB, n - r0);
+        float *hs[DNQS_MAX_LAYERS + 1] = {};
+        TRY(hidden_block(ctx, sl, nv, theta, dets + 2 * r0, nb, precision, U, nullptr, hs, L - 2));
+        const float *delta = deltaL1 + r0 * w[L - 1];
+        int which = 0;
+        for (int l = L - 1; l >= 1; --l) {
+            const int din = w[l - 1], dout = w[l];
+            const float *hp = l == 1 ? U : hs[l - 1];
+            GemmArgs g{};
+            g.M = din + 1;
+            g.N = dout;
+            g.K = (int)nb;
+            g.A = hp;
+            g.lda = din;
+            g.B = delta;
+            g.ldb = dout;
+            g.ldc = dout;
+            g.ones_row = din;
+            g.C = part;
+            g.c_split_stride = cnt[l];
+            g.k_chunk = rc_chunk[l];
+            const int sp = (int)((nb + rc_chunk[l] - 1) / rc_chunk[l]);
+            launch_gemm(eng, st, g, false, true, EPI_STORE, sp, rc_cfg[l].tm);
+            CHECK_LAUNCH(ctx);
+            launch_fold_splits(st, part, sp, cnt[l], grad + nv.offW[l], r0 > 0);
+            CHECK_LAUNCH(ctx);
+            if (l == 1) break;
+            float *dnext = dblk[which];
+            which ^= 1;
+            GemmArgs d{};
+            d.M = (int)nb;
+            d.N = din;
+            d.K = dout;
+            d.A = delta;
+            d.lda = dout;
+            d.B = theta + nv.offW[l];
+            d.ldb = dout;
+            d.C = dnext;
+            d.ldc = din;
+            d.act = hs[l - 1];
+            d.ldact = din;
+            d.ones_row = -1;
+            if (eng == 1) TRY(weight_planes(ctx, "wp" + std::to_string(l), theta + nv.offW[l], din, dout, false, d));
+            TRY(tuned_launch(ctx, TuneKey{eng, 2, d.M, d.N, d.K}, gemm_candidates(d.M, d.N, d.K, false, false),
+                             [&](const GemmCfg &c) -> dnqs_status {
+                                 launch_gemm(eng, st, d, true, false, EPI_DTANH, 1, c.tm);
+                                 CHECK_LAUNCH(ctx);
+                                 return DNQS_OK;
+                             }));
+            delta = dnext;
+        }
+    }
+    return DNQS_OK;
+}
+
 dnqs_status validate_dets_dev(dnqs_ctx *ctx, const Slot &sl, const uint64_t *dets, int64_t n, bool order) {
     int *err = nullptr;
     TRY(ws_t(ctx, "valid_err", 1, &err));
@@ -563,7 +764,7 @@ dnqs_status os_plan(dnqs_ctx *ctx, dnqs_conn *c) {
         icount[p] = (int)items.size() - ifirst[p];
     }
     auto dalloc = [&](void **ptr, size_t bytes) -> dnqs_status {
-        HIPCHK(ctx, hipMalloc(ptr, bytes > 0 ? bytes : 16));
+        HIPCHK(ctx, dev_alloc(c->alloc, ptr, bytes > 0 ? bytes : 16));
         return DNQS_OK;
     };
     TRY(dalloc((void **)&c->os_dpos, sizeof(int) * No));
@@ -599,14 +800,247 @@ dnqs_status os_plan(dnqs_ctx *ctx, dnqs_conn *c) {
     return DNQS_OK;
 }
 
+// Hash set of S (load <= 1/2) in workspaces, for membership probes of excitations.
+dnqs_status s_hash_set(dnqs_ctx *ctx, const uint64_t *dets, int64_t n, DetSet *S) {
+    hipStream_t st = ctx->stream;
+    uint64_t cap = 1024;
+    while (cap < (uint64_t)(2 * n)) cap <<= 1;
+    uint64_t *set_keys = nullptr;
+    int32_t *set_idx = nullptr;
+    TRY(ws_t(ctx, "ps_set_keys", (size_t)cap * 2, &set_keys));
+    TRY(ws_t(ctx, "ps_set_idx", (size_t)cap, &set_idx));
+    launch_fill_u64(st, set_keys, 2 * cap, kEmptyKey);
+    launch_detset_insert(st, dets, n, set_keys, set_idx, cap - 1);
+    CHECK_LAUNCH(ctx);
+    *S = DetSet{set_keys, set_idx, cap - 1};
+    return DNQS_OK;
+}
+
+// The determinants a outside S at excitation rank 1 or 2 from some x in S (P of Eq. 1),
+// or with psi (scaled) and hb_eps > 0 those with max_x |<a|H|x> psi_x| >= hb_eps
+// sqrt(norm2[0]) (Eq. 14), sorted in canonical order and unique, into the workspace
+// "ps_p" (*out, *n_out entries).  Every candidate pair is held once: DNQS_ECAPACITY when
+// |S| n_exc >= 2^31.  Synchronises the stream.
+dnqs_status list_candidates(dnqs_ctx *ctx, const Slot &sl, const uint64_t *dets, int64_t n, const DetSet &S,
+                            const double *psi, double hb_eps, const double *norm2, uint64_t **out,
+                            int64_t *n_out) {
+    hipStream_t st = ctx->stream;
+    const int M = sl.M;
+    const int64_t nexc = n_excitations(sl.M, sl.na, sl.nb);
+    if ((double)n * (double)nexc >= 2147483647.0)
+        return fail(ctx, DNQS_ECAPACITY, "candidates are listed only for |S| n_exc < 2^31 (here %.3g)",
+                    (double)n * nexc);
+    Ham H = make_ham(sl);
+    int32_t *cnt = nullptr;
+    int64_t *off = nullptr, *bsum = nullptr, *tot = nullptr;
+    TRY(ws_t(ctx, "ps_cnt", (size_t)n, &cnt));
+    TRY(ws_t(ctx, "ps_off", (size_t)n + 1, &off));
+    TRY(ws_t(ctx, "ps_bsum", (size_t)scan_blocks(n) + 1, &bsum));
+    TRY(ws_t(ctx, "ps_tot", 2, &tot));
+    launch_pc_pass(st, H, dets, n, S, psi, hb_eps, norm2, cnt, nullptr, nullptr, nullptr, false);
+    launch_exclusive_scan(st, cnt, n, off, bsum, tot);
+    CHECK_LAUNCH(ctx);
+    int64_t m = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&m, tot, sizeof m, hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    const bool two = M > 32;
+    uint64_t *ka = nullptr, *kb = nullptr, *key = nullptr;
+    int32_t *perm = nullptr;
+    TRY(ws_t(ctx, "ps_ka", (size_t)std::max<int64_t>(m, 1), &ka));
+    if (two) TRY(ws_t(ctx, "ps_kb", (size_t)std::max<int64_t>(m, 1), &kb));
+    TRY(ws_t(ctx, "ps_perm", (size_t)std::max<int64_t>(m, 1), &perm));
+    launch_pc_pass(st, H, dets, n, S, psi, hb_eps, norm2, nullptr, off, ka, kb, true);
+    CHECK_LAUNCH(ctx);
+    // sort the candidates into canonical order
+    SortScratch w{};
+    const size_t nc = sort_scratch_counts(m);
+    TRY(ws_t(ctx, "sort_keys", (size_t)std::max<int64_t>(m, 1), &w.keys));
+    TRY(ws_t(ctx, "sort_vals", (size_t)std::max<int64_t>(m, 1), &w.vals));
+    TRY(ws_t(ctx, "sort_counts", nc, &w.counts));
+    TRY(ws_t(ctx, "sort_offs", nc, &w.offs));
+    TRY(ws_t(ctx, "sort_bsum", (size_t)scan_blocks((int64_t)nc) + 1, &w.bsum));
+    TRY(ws_t(ctx, "sort_total", 1, &w.total));
+    launch_iota_i32(st, perm, m);
+    if (!two) {
+        launch_radix_sort(st, ka, perm, m, 2 * M, w);
+    } else {
+        TRY(ws_t(ctx, "ps_key", (size_t)std::max<int64_t>(m, 1), &key));
+        HIPCHK(ctx, hipMemcpyAsync(key, kb, (size_t)m * 8, hipMemcpyDeviceToDevice, st));
+        launch_radix_sort(st, key, perm, m, M, w);
+        launch_gather_u64(st, ka, perm, m, key);
+        launch_radix_sort(st, key, perm, m, M, w);
+    }
+    CHECK_LAUNCH(ctx);
+    // drop duplicates
+    int32_t *flag = nullptr;
+    int64_t *pos = nullptr, *bsum2 = nullptr;
+    TRY(ws_t(ctx, "ps_flag", (size_t)std::max<int64_t>(m, 1), &flag));
+    TRY(ws_t(ctx, "ps_pos", (size_t)std::max<int64_t>(m, 1), &pos));
+    TRY(ws_t(ctx, "ps_bsum2", (size_t)scan_blocks(m) + 1, &bsum2));
+    int64_t np = 0;
+    if (m > 0) {
+        launch_unique(st, ka, kb, perm, m, two, M, flag, pos, bsum2, tot + 1, nullptr, false);
+        CHECK_LAUNCH(ctx);
+        HIPCHK(ctx, hipMemcpyAsync(&np, tot + 1, sizeof np, hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));
+    }
+    uint64_t *pd = nullptr;
+    TRY(ws_t(ctx, "ps_p", (size_t)std::max<int64_t>(np, 1) * 2, &pd));
+    if (m > 0) launch_unique(st, ka, kb, perm, m, two, M, flag, pos, bsum2, tot + 1, pd, true);
+    CHECK_LAUNCH(ctx);
+    *out = pd;
+    *n_out = np;
+    return DNQS_OK;
+}
+
+// P = C(S) \ S of the connections c, sorted and unique, with H_aa, the fingerprint and
+// (hps) the rows H_PS (k_pset.hip).
+dnqs_status build_pset(dnqs_ctx *ctx, const Slot &sl, dnqs_conn *c, bool hps) {
+    hipStream_t st = ctx->stream;
+    const int64_t n = c->n;
+    DetSet S{};
+    TRY(s_hash_set(ctx, c->dets, n, &S));
+    uint64_t *pw = nullptr;
+    int64_t np = 0;
+    TRY(list_candidates(ctx, sl, c->dets, n, S, nullptr, 0.0, nullptr, &pw, &np));
+    c->p_n = np;
+    HIPCHK(ctx, dev_alloc(c->alloc, (void **)&c->p_dets, (size_t)std::max<int64_t>(np, 1) * 16));
+    HIPCHK(ctx, dev_alloc(c->alloc, (void **)&c->p_diag, (size_t)std::max<int64_t>(np, 1) * 8));
+    if (np > 0) HIPCHK(ctx, hipMemcpyAsync(c->p_dets, pw, (size_t)np * 16, hipMemcpyDeviceToDevice, st));
+    unsigned long long *fp = nullptr;
+    int64_t *tot = nullptr;
+    TRY(ws_t(ctx, "ps_fp", 2, &fp));
+    TRY(ws_t(ctx, "ps_tot", 2, &tot));
+    HIPCHK(ctx, hipMemsetAsync(fp, 0, 16, st));
+    launch_fingerprint(st, c->p_dets, np, fp);
+    Ham H = make_ham(sl);
+    if (np > 0) launch_diag(st, H, c->p_dets, np, c->p_diag);
+    CHECK_LAUNCH(ctx);
+    HIPCHK(ctx, hipMemcpyAsync(c->p_fp, fp, 16, hipMemcpyDeviceToHost, st));
+    if (hps) {
+        int32_t *rc = nullptr;
+        int64_t *roff = nullptr, *rbsum = nullptr;
+        TRY(ws_t(ctx, "ps_rcnt", (size_t)std::max<int64_t>(np, 1), &rc));
+        TRY(ws_t(ctx, "ps_roff", (size_t)std::max<int64_t>(np, 1), &roff));
+        TRY(ws_t(ctx, "ps_rbsum", (size_t)scan_blocks(np) + 1, &rbsum));
+        int64_t nnz = 0;
+        HIPCHK(ctx, hipMemsetAsync(tot, 0, sizeof(int64_t), st));
+        if (np > 0) {
+            launch_hps_pass(st, H, c->p_dets, np, S, rc, nullptr, nullptr, nullptr, false);
+            launch_exclusive_scan(st, rc, np, roff, rbsum, tot);
+            CHECK_LAUNCH(ctx);
+            HIPCHK(ctx, hipMemcpyAsync(&nnz, tot, sizeof nnz, hipMemcpyDeviceToHost, st));
+            HIPCHK(ctx, hipStreamSynchronize(st));
+        }
+        c->ps_nnz = nnz;
+        HIPCHK(ctx, dev_alloc(c->alloc, (void **)&c->ps_row_ptr, (size_t)(np + 1) * 8));
+        HIPCHK(ctx, dev_alloc(c->alloc, (void **)&c->ps_col, (size_t)std::max<int64_t>(nnz, 1) * 4));
+        HIPCHK(ctx, dev_alloc(c->alloc, (void **)&c->ps_val, (size_t)std::max<int64_t>(nnz, 1) * 4));
+        if (np > 0) launch_hps_pass(st, H, c->p_dets, np, S, rc, roff, c->ps_col, c->ps_val, true);
+        launch_rows_finish(st, roff, np, tot, c->ps_row_ptr, c->ps_col, c->ps_val);
+        CHECK_LAUNCH(ctx);
+    }
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    return DNQS_OK;
+}
+
+// The exported keys of a PT2 call in canonical order (with their w_a and H_aa), when
+// all of them fit the caller's buffers; the reduce writes them in workgroup order.
+dnqs_status pt2_export_sort(dnqs_ctx *ctx, int M, const dnqs_pt2_opts &o) {
+    hipStream_t st = ctx->stream;
+    int64_t cnt = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&cnt, o.export_count, sizeof cnt, hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    if (cnt > o.export_cap || cnt < 2) return DNQS_OK;
+    SortScratch w{};
+    const size_t nc = sort_scratch_counts(cnt);
+    int32_t *perm = nullptr;
+    uint64_t *key = nullptr, *tmp = nullptr;
+    TRY(ws_t(ctx, "sort_keys", (size_t)cnt, &w.keys));
+    TRY(ws_t(ctx, "sort_vals", (size_t)cnt, &w.vals));
+    TRY(ws_t(ctx, "sort_counts", nc, &w.counts));
+    TRY(ws_t(ctx, "sort_offs", nc, &w.offs));
+    TRY(ws_t(ctx, "sort_bsum", (size_t)scan_blocks((int64_t)nc) + 1, &w.bsum));
+    TRY(ws_t(ctx, "sort_total", 1, &w.total));
+    TRY(ws_t(ctx, "ex_perm", (size_t)cnt, &perm));
+    TRY(ws_t(ctx, "ex_key", (size_t)cnt, &key));
+    TRY(ws_t(ctx, "ex_tmp", (size_t)cnt * 2, &tmp));
+    launch_sort_dets(st, o.export_keys, cnt, M, perm, key, w);
+    launch_permute_words(st, o.export_keys, perm, cnt, 2, tmp);
+    HIPCHK(ctx, hipMemcpyAsync(o.export_keys, tmp, (size_t)cnt * 16, hipMemcpyDeviceToDevice, st));
+    launch_permute_words(st, (const uint64_t *)o.export_w, perm, cnt, 1, tmp);
+    HIPCHK(ctx, hipMemcpyAsync(o.export_w, tmp, (size_t)cnt * 8, hipMemcpyDeviceToDevice, st));
+    launch_permute_words(st, (const uint64_t *)o.export_haa, perm, cnt, 1, tmp);
+    HIPCHK(ctx, hipMemcpyAsync(o.export_haa, tmp, (size_t)cnt * 8, hipMemcpyDeviceToDevice, st));
+    CHECK_LAUNCH(ctx);
+    return DNQS_OK;
+}
+
+// Lowest eigenvalue of the symmetric tridiagonal matrix (diagonal a, off-diagonal b)
+// by bisection on the Sturm count, then its eigenvector by inverse iteration with the
+// shift just below it (T - sigma I is then positive definite: elimination without
+// pivoting is stable).  Host arithmetic on at most a few hundred entries.
+double tri_lowest(const std::vector<double> &a, const std::vector<double> &b, std::vector<double> &y) {
+    const int m = (int)a.size();
+    double lo = INFINITY, hi = -INFINITY;
+    for (int i = 0; i < m; ++i) {
+        const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    auto below = [&](double x) {  // eigenvalues < x
+        int c = 0;
+        double q = a[0] - x;
+        if (q < 0) ++c;
+        for (int i = 1; i < m; ++i) {
+            if (q == 0.0) q = 1e-300;
+            q = a[i] - x - b[i - 1] * b[i - 1] / q;
+            if (q < 0) ++c;
+        }
+        return c;
+    };
+    for (int it = 0; it < 200 && hi - lo > 4e-16 * std::max(std::fabs(lo), std::fabs(hi)); ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (below(mid) >= 1)
+            hi = mid;
+        else
+            lo = mid;
+    }
+    const double lam = 0.5 * (lo + hi);
+    const double sigma = lo - 1e-12 * std::max(1.0, std::fabs(lam)) - (hi - lo);
+    y.assign(m, 1.0);
+    std::vector<double> d(m), l(m);
+    // LDL^T of T - sigma I
+    d[0] = a[0] - sigma;
+    for (int i = 1; i < m; ++i) {
+        l[i] = b[i - 1] / d[i - 1];
+        d[i] = a[i] - sigma - l[i] * b[i - 1];
+    }
+    for (int it = 0; it < 4; ++it) {
+        for (int i = 1; i < m; ++i) y[i] -= l[i] * y[i - 1];
+        for (int i = 0; i < m; ++i) y[i] /= d[i];
+        for (int i = m - 2; i >= 0; --i) y[i] -= l[i + 1] * y[i + 1];
+        double nrm = 0.0;
+        for (int i = 0; i < m; ++i) nrm += y[i] * y[i];
+        nrm = std::sqrt(nrm);
+        for (int i = 0; i < m; ++i) y[i] /= nrm;
+    }
+    return lam;
+}
+
 }  // namespace
 
 // ====================================================================== ABI
 extern "C" {
 
-dnqs_status dnqs_create(dnqs_ctx **out, int device, void *stream) {
+dnqs_status dnqs_create(dnqs_ctx **out, int device, void *stream, void *(*alloc)(size_t bytes, void *user),
+                        void (*release)(void *p, void *user), void *user) {
     if (!out) {
         g_create_error = "out is NULL";
+        return DNQS_EINVAL;
+    }
+    if ((alloc == nullptr) != (release == nullptr)) {
+        g_create_error = "alloc and release must both be given or both be NULL";
         return DNQS_EINVAL;
     }
     *out = nullptr;
@@ -635,6 +1069,9 @@ dnqs_status dnqs_create(dnqs_ctx **out, int device, void *stream) {
     dnqs_ctx *c = new dnqs_ctx();
     c->device = device;
     c->stream = (hipStream_t)stream;
+    c->alloc.alloc = alloc;
+    c->alloc.release = release;
+    c->alloc.user = user;
     *out = c;
     return DNQS_OK;
 }
@@ -654,15 +1091,11 @@ void dnqs_destroy(dnqs_ctx *ctx) {
     for (hipEvent_t e : ctx->ev_fwd)
         if (e) (void)hipEventDestroy(e);
     for (auto &kv : ctx->ws)
-        if (kv.second.p) (void)hipFree(kv.second.p);
+        dev_free(ctx->alloc, kv.second.p);
     for (auto &s : ctx->slots) {
         if (!s.set) continue;
-        (void)hipFree(s.h64);
-        (void)hipFree(s.eri64);
-        (void)hipFree(s.eri32);
-        (void)hipFree(s.eri_pk);
-        (void)hipFree(s.J);
-        (void)hipFree(s.K);
+        for (void *q : {(void *)s.h64, (void *)s.eri64, (void *)s.eri32, (void *)s.eri_pk, (void *)s.J, (void *)s.K})
+            dev_free(ctx->alloc, q);
     }
     for (auto &kv : ctx->times)
         for (auto &p : kv.second.ev) {
@@ -670,10 +1103,7 @@ void dnqs_destroy(dnqs_ctx *ctx) {
             (void)hipEventDestroy(p.second);
         }
     for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
-    BatchPlan &b = ctx->plan;
-    for (void *q : {(void *)b.dets, (void *)b.pid, (void *)b.row_ptr, (void *)b.col, (void *)b.val, (void *)b.diag,
-                    (void *)b.tile_pid, (void *)b.ksplit, (void *)b.zoff, (void *)b.P_d, (void *)b.ptr_d})
-        if (q) (void)hipFree(q);
+    plan_free(ctx, ctx->plan);
     delete ctx;
 }
 
@@ -701,25 +1131,28 @@ dnqs_status dnqs_set_integrals(dnqs_ctx *ctx, int slot, int M, int n_alpha, int 
         return fail(ctx, DNQS_EINVAL, "electron counts (%d, %d) invalid for M = %d", n_alpha, n_beta, M);
     if (!h || !eri) return fail(ctx, DNQS_EINVAL, "h or eri is NULL");
     if (!std::isfinite(e_core)) return fail(ctx, DNQS_EINVAL, "e_core is not finite");
+    {
+        const size_t m2 = (size_t)M * M;
+        for (size_t i = 0; i < m2; ++i)
+            if (!std::isfinite(h[i])) return fail(ctx, DNQS_EINVAL, "h[%zu] is not finite", i);
+        for (size_t i = 0; i < m2 * m2; ++i)
+            if (!std::isfinite(eri[i])) return fail(ctx, DNQS_EINVAL, "eri[%zu] is not finite", i);
+    }
     TRY(set_device(ctx));
     Slot &s = ctx->slots[slot];
     if (s.set) {
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-        (void)hipFree(s.h64);
-        (void)hipFree(s.eri64);
-        (void)hipFree(s.eri32);
-        (void)hipFree(s.eri_pk);
-        (void)hipFree(s.J);
-        (void)hipFree(s.K);
+        for (void *q : {(void *)s.h64, (void *)s.eri64, (void *)s.eri32, (void *)s.eri_pk, (void *)s.J, (void *)s.K})
+            dev_free(ctx->alloc, q);
         s = Slot();
     }
     const size_t m2 = (size_t)M * M, m4 = m2 * m2;
-    HIPCHK(ctx, hipMalloc(&s.h64, m2 * sizeof(double)));
-    HIPCHK(ctx, hipMalloc(&s.eri64, m4 * sizeof(double)));
-    HIPCHK(ctx, hipMalloc(&s.eri32, m4 * sizeof(float)));
-    HIPCHK(ctx, hipMalloc(&s.J, m2 * sizeof(double)));
-    HIPCHK(ctx, hipMalloc(&s.K, m2 * sizeof(double)));
-    HIPCHK(ctx, hipMalloc(&s.eri_pk, packed_eri_size(M) * sizeof(double)));
+    HIPCHK(ctx, dev_alloc(ctx->alloc, (void **)&s.h64, m2 * sizeof(double)));
+    HIPCHK(ctx, dev_alloc(ctx->alloc, (void **)&s.eri64, m4 * sizeof(double)));
+    HIPCHK(ctx, dev_alloc(ctx->alloc, (void **)&s.eri32, m4 * sizeof(float)));
+    HIPCHK(ctx, dev_alloc(ctx->alloc, (void **)&s.J, m2 * sizeof(double)));
+    HIPCHK(ctx, dev_alloc(ctx->alloc, (void **)&s.K, m2 * sizeof(double)));
+    HIPCHK(ctx, dev_alloc(ctx->alloc, (void **)&s.eri_pk, packed_eri_size(M) * sizeof(double)));
     HIPCHK(ctx, hipMemcpyAsync(s.h64, h, m2 * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(s.eri64, eri, m4 * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
     launch_stage_integrals(ctx->stream, M, s.eri64, s.eri32, s.J, s.K);
@@ -730,6 +1163,15 @@ dnqs_status dnqs_set_integrals(dnqs_ctx *ctx, int slot, int M, int n_alpha, int 
     s.na = n_alpha;
     s.nb = n_beta;
     s.ecore = e_core;
+    {
+        double mh = 0.0, me = 0.0;
+        for (size_t i = 0; i < m2; ++i) mh = std::max(mh, std::fabs(h[i]));
+        for (size_t i = 0; i < m4; ++i) me = std::max(me, std::fabs(eri[i]));
+        const double bound = mh + 2.0 * (n_alpha + n_beta) * me;
+        int e = 0;
+        if (bound > 0.0) (void)std::frexp(bound, &e);  // bound < 2^e
+        s.wexp = e + 1;
+    }
     s.set = true;
     return DNQS_OK;
 }
@@ -738,16 +1180,13 @@ void dnqs_conn_free(dnqs_conn *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
-    (void)hipFree(c->dets);
-    (void)hipFree(c->row_ptr);
-    (void)hipFree(c->col);
-    (void)hipFree(c->val);
-    (void)hipFree(c->diag);
-    (void)hipFree(c->set_keys);
-    (void)hipFree(c->set_idx);
+    for (void *q : {(void *)c->dets, (void *)c->row_ptr, (void *)c->col, (void *)c->val, (void *)c->diag})
+        dev_free(c->alloc, q);
+    for (void *q : {(void *)c->p_dets, (void *)c->p_diag, (void *)c->ps_row_ptr, (void *)c->ps_col, (void *)c->ps_val})
+        dev_free(c->alloc, q);
     for (void *q : {(void *)c->os_dpos, (void *)c->os_dorb, (void *)c->os_ifirst, (void *)c->os_icount,
                     (void *)c->os_ex, (void *)c->os_ej, (void *)c->os_idx, (void *)c->os_tiles, (void *)c->os_items})
-        if (q) (void)hipFree(q);
+        dev_free(c->alloc, q);
     delete c;
 }
 
@@ -759,6 +1198,8 @@ dnqs_status dnqs_build_connections(dnqs_ctx *ctx, int slot, const uint64_t *dets
     TRY(check_slot(ctx, slot));
     if (!dets) return fail(ctx, DNQS_EINVAL, "dets is NULL");
     if (n < 1 || n >= (int64_t)1 << 31) return fail(ctx, DNQS_EINVAL, "n = %lld out of range", (long long)n);
+    if (flags & ~(DNQS_VALIDATE | DNQS_EMIT_P | DNQS_EMIT_HPS))
+        return fail(ctx, DNQS_EINVAL, "unknown flags 0x%x", flags);
     TRY(set_device(ctx));
     const Slot &sl = ctx->slots[slot];
     hipStream_t st = ctx->stream;
@@ -766,6 +1207,7 @@ dnqs_status dnqs_build_connections(dnqs_ctx *ctx, int slot, const uint64_t *dets
     Timer tm(ctx, "hss");
     dnqs_conn *c = new dnqs_conn();
     c->device = ctx->device;
+    c->alloc = ctx->alloc;
     c->slot = slot;
     c->M = sl.M;
     c->na = sl.na;
@@ -782,18 +1224,9 @@ dnqs_status dnqs_build_connections(dnqs_ctx *ctx, int slot, const uint64_t *dets
             return cleanup(fail(ctx, e_ == hipErrorOutOfMemory ? DNQS_ENOMEM : DNQS_EHIP, "%s: %s", #call,     \
                                 hipGetErrorString(e_)));                                                   \
     } while (0)
-    CHK_C(hipMalloc(&c->dets, (size_t)n * 16));
+    CHK_C(dev_alloc(c->alloc, (void **)&c->dets, (size_t)n * 16));
     CHK_C(hipMemcpyAsync(c->dets, dets, (size_t)n * 16, hipMemcpyDeviceToDevice, st));
-    // hash set of S at load <= 1/2
-    uint64_t cap = 1024;
-    while (cap < (uint64_t)(2 * n)) cap <<= 1;
-    c->set_mask = cap - 1;
-    CHK_C(hipMalloc(&c->set_keys, cap * 16));
-    CHK_C(hipMalloc(&c->set_idx, cap * sizeof(int32_t)));
-    launch_fill_u64(st, c->set_keys, 2 * cap, kEmptyKey);
-    launch_detset_insert(st, c->dets, n, c->set_keys, c->set_idx, c->set_mask);
-    CHK_C(hipGetLastError());
-    CHK_C(hipMalloc(&c->diag, (size_t)n * sizeof(double)));
+    CHK_C(dev_alloc(c->alloc, (void **)&c->diag, (size_t)n * sizeof(double)));
     Ham H = make_ham(sl);
     launch_diag(st, H, c->dets, n, c->diag);
     CHK_C(hipGetLastError());
@@ -815,17 +1248,137 @@ dnqs_status dnqs_build_connections(dnqs_ctx *ctx, int slot, const uint64_t *dets
     CHK_C(hipMemcpyAsync(&nnz, total, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     CHK_C(hipStreamSynchronize(st));
     c->nnz = nnz;
-    CHK_C(hipMalloc(&c->row_ptr, (size_t)(n + 1) * sizeof(int64_t)));
-    CHK_C(hipMalloc(&c->col, (size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t)));
-    CHK_C(hipMalloc(&c->val, (size_t)(nnz > 0 ? nnz : 1) * sizeof(float)));
+    CHK_C(dev_alloc(c->alloc, (void **)&c->row_ptr, (size_t)(n + 1) * sizeof(int64_t)));
+    CHK_C(dev_alloc(c->alloc, (void **)&c->col, (size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t)));
+    CHK_C(dev_alloc(c->alloc, (void **)&c->val, (size_t)(nnz > 0 ? nnz : 1) * sizeof(float)));
     launch_hss_fill(st, H, c->dets, n, nsub, offs, c->col, c->val);
     CHK_C(hipGetLastError());
     launch_row_ptr(st, offs, n, nsub, nnz, c->row_ptr);
     CHK_C(hipGetLastError());
+    if (nnz > 0) launch_hss_values(st, H, c->dets, n, c->row_ptr, c->col, c->val);
+    CHK_C(hipGetLastError());
     if ((s = os_plan(ctx, c)) != DNQS_OK) return cleanup(s);
+    if (flags & (DNQS_EMIT_P | DNQS_EMIT_HPS))
+        if ((s = build_pset(ctx, sl, c, (flags & DNQS_EMIT_HPS) != 0)) != DNQS_OK) return cleanup(s);
     tm.stop();
     CHK_C(hipStreamSynchronize(st));
 #undef CHK_C
+    *out = c;
+    return DNQS_OK;
+}
+
+dnqs_status dnqs_build_target(dnqs_ctx *ctx, int slot, const dnqs_conn *cv, const uint64_t *p_dets, int64_t n_p,
+                              unsigned flags, dnqs_conn **out) {
+    if (!ctx) return DNQS_EINVAL;
+    if (!out) return fail(ctx, DNQS_EINVAL, "out is NULL");
+    *out = nullptr;
+    TRY(check_slot(ctx, slot));
+    const Slot &sl = ctx->slots[slot];
+    if (!cv || (n_p > 0 && !p_dets)) return fail(ctx, DNQS_EINVAL, "NULL pointer argument");
+    if (cv->n_v > 0) return fail(ctx, DNQS_EINVAL, "the connections are already a target set");
+    if (cv->M != sl.M || cv->na != sl.na || cv->nb != sl.nb)
+        return fail(ctx, DNQS_EINVAL, "connections were built for another sector");
+    if (n_p < 0 || cv->n + n_p >= (int64_t)1 << 31) return fail(ctx, DNQS_EINVAL, "n_p out of range");
+    if (flags & ~DNQS_VALIDATE) return fail(ctx, DNQS_EINVAL, "unknown flags 0x%x", flags);
+    TRY(set_device(ctx));
+    hipStream_t st = ctx->stream;
+    if ((flags & DNQS_VALIDATE) && n_p > 0) TRY(validate_dets_dev(ctx, sl, p_dets, n_p, true));
+    Timer tm(ctx, "target");
+    const int64_t nv = cv->n, np = n_p, nt = nv + np;
+    DetSet S{};
+    TRY(s_hash_set(ctx, cv->dets, nv, &S));
+    if (flags & DNQS_VALIDATE) {
+        int *cnt_in = nullptr;
+        TRY(ws_t(ctx, "tg_in", 1, &cnt_in));
+        HIPCHK(ctx, hipMemsetAsync(cnt_in, 0, sizeof(int), st));
+        launch_count_in_set(st, p_dets, np, S, cnt_in);
+        CHECK_LAUNCH(ctx);
+        int h = 0;
+        HIPCHK(ctx, hipMemcpyAsync(&h, cnt_in, sizeof h, hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));
+        if (h) return fail(ctx, DNQS_EINVAL, "%d determinants of P are members of V", h);
+    }
+    Ham H = make_ham(sl);
+    // H_PV: rows over P, columns in V (ascending)
+    int32_t *rc = nullptr, *pvc = nullptr, *tcnt = nullptr, *vpc = nullptr, *len = nullptr;
+    int64_t *pvr = nullptr, *rbsum = nullptr, *tot = nullptr, *vpr = nullptr, *voff = nullptr, *toff = nullptr;
+    float *pvv = nullptr, *vpv = nullptr;
+    TRY(ws_t(ctx, "tg_rc", (size_t)std::max<int64_t>(np, 1), &rc));
+    TRY(ws_t(ctx, "tg_pvr", (size_t)np + 1, &pvr));
+    TRY(ws_t(ctx, "tg_bsum", (size_t)scan_blocks(std::max(nt, np)) + 1, &rbsum));
+    TRY(ws_t(ctx, "tg_tot", 4, &tot));
+    HIPCHK(ctx, hipMemsetAsync(tot, 0, 4 * sizeof(int64_t), st));
+    int64_t nnz_pv = 0;
+    if (np > 0) {
+        launch_hps_pass(st, H, p_dets, np, S, rc, nullptr, nullptr, nullptr, false);
+        launch_exclusive_scan(st, rc, np, pvr, rbsum, tot);
+        CHECK_LAUNCH(ctx);
+        HIPCHK(ctx, hipMemcpyAsync(&nnz_pv, tot, sizeof nnz_pv, hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));
+    }
+    TRY(ws_t(ctx, "tg_pvc", (size_t)std::max<int64_t>(nnz_pv, 1), &pvc));
+    TRY(ws_t(ctx, "tg_pvv", (size_t)std::max<int64_t>(nnz_pv, 1), &pvv));
+    if (np > 0) launch_hps_pass(st, H, p_dets, np, S, rc, pvr, pvc, pvv, true);
+    launch_rows_finish(st, pvr, np, tot, pvr, pvc, pvv);
+    // H_VP = H_PV^T: rows over V, columns in P (ascending)
+    TRY(ws_t(ctx, "tg_tcnt", (size_t)std::max<int64_t>(nv, 1), &tcnt));
+    TRY(ws_t(ctx, "tg_voff", (size_t)nv + 1, &voff));
+    TRY(ws_t(ctx, "tg_vpr", (size_t)nv + 1, &vpr));
+    TRY(ws_t(ctx, "tg_vpc", (size_t)std::max<int64_t>(nnz_pv, 1), &vpc));
+    TRY(ws_t(ctx, "tg_vpv", (size_t)std::max<int64_t>(nnz_pv, 1), &vpv));
+    HIPCHK(ctx, hipMemsetAsync(tcnt, 0, sizeof(int32_t) * nv, st));
+    launch_csr_transpose(st, pvr, pvc, pvv, np, nv, tcnt, voff, rbsum, tot + 1, vpr, vpc, vpv, false);
+    HIPCHK(ctx, hipMemsetAsync(tcnt, 0, sizeof(int32_t) * nv, st));
+    launch_csr_transpose(st, pvr, pvc, pvv, np, nv, tcnt, voff, rbsum, tot + 1, vpr, vpc, vpv, true);
+    CHECK_LAUNCH(ctx);
+    // the proxy matrix over T
+    dnqs_conn *c = new dnqs_conn();
+    c->device = ctx->device;
+    c->alloc = ctx->alloc;
+    c->slot = slot;
+    c->M = sl.M;
+    c->na = sl.na;
+    c->nb = sl.nb;
+    c->n = nt;
+    c->n_v = nv;
+    auto cleanup = [&](dnqs_status s2) {
+        dnqs_conn_free(c);
+        return s2;
+    };
+#define CHK_T(call)                                                                                        \
+    do {                                                                                                   \
+        hipError_t e_ = (call);                                                                            \
+        if (e_ != hipSuccess)                                                                              \
+            return cleanup(fail(ctx, e_ == hipErrorOutOfMemory ? DNQS_ENOMEM : DNQS_EHIP, "%s: %s", #call,     \
+                                hipGetErrorString(e_)));                                                   \
+    } while (0)
+    dnqs_status s2;
+    if ((s2 = ws_t(ctx, "tg_len", (size_t)nt, &len)) != DNQS_OK) return cleanup(s2);
+    if ((s2 = ws_t(ctx, "tg_toff", (size_t)nt + 1, &toff)) != DNQS_OK) return cleanup(s2);
+    launch_target_assemble(st, cv->row_ptr, cv->col, cv->val, vpr, vpc, vpv, pvr, pvc, pvv, nv, np, len, toff,
+                           rbsum, tot + 2, nullptr, nullptr, false);
+    CHK_T(hipGetLastError());
+    int64_t nnz = 0;
+    CHK_T(hipMemcpyAsync(&nnz, tot + 2, sizeof nnz, hipMemcpyDeviceToHost, st));
+    CHK_T(hipStreamSynchronize(st));
+    c->nnz = nnz;
+    CHK_T(dev_alloc(c->alloc, (void **)&c->dets, (size_t)nt * 16));
+    CHK_T(dev_alloc(c->alloc, (void **)&c->diag, (size_t)nt * 8));
+    CHK_T(dev_alloc(c->alloc, (void **)&c->row_ptr, (size_t)(nt + 1) * 8));
+    CHK_T(dev_alloc(c->alloc, (void **)&c->col, (size_t)std::max<int64_t>(nnz, 1) * 4));
+    CHK_T(dev_alloc(c->alloc, (void **)&c->val, (size_t)std::max<int64_t>(nnz, 1) * 4));
+    CHK_T(hipMemcpyAsync(c->dets, cv->dets, (size_t)nv * 16, hipMemcpyDeviceToDevice, st));
+    if (np > 0) CHK_T(hipMemcpyAsync(c->dets + 2 * nv, p_dets, (size_t)np * 16, hipMemcpyDeviceToDevice, st));
+    CHK_T(hipMemcpyAsync(c->diag, cv->diag, (size_t)nv * 8, hipMemcpyDeviceToDevice, st));
+    if (np > 0) launch_diag(st, H, p_dets, np, c->diag + nv);
+    launch_target_assemble(st, cv->row_ptr, cv->col, cv->val, vpr, vpc, vpv, pvr, pvc, pvv, nv, np, len, toff,
+                           rbsum, tot + 2, c->col, c->val, true);
+    launch_row_ptr_from_offsets(st, toff, nt, tot + 2, c->row_ptr);
+    CHK_T(hipGetLastError());
+#undef CHK_T
+    if ((s2 = os_plan(ctx, c)) != DNQS_OK) return cleanup(s2);
+    tm.stop();
+    HIPCHK(ctx, hipStreamSynchronize(st));
     *out = c;
     return DNQS_OK;
 }
@@ -841,6 +1394,37 @@ dnqs_status dnqs_conn_output_plan(const dnqs_conn *conn, int *n_dense, int64_t *
     if (!conn) return DNQS_EINVAL;
     if (n_dense) *n_dense = conn->os_nd;
     if (n_entries) *n_entries = conn->os_nd >= 0 ? conn->os_ne : 0;
+    return DNQS_OK;
+}
+
+dnqs_status dnqs_conn_p_info(const dnqs_conn *conn, int64_t *n_p, int64_t *nnz_ps, uint64_t *fingerprint) {
+    if (!conn) return DNQS_EINVAL;
+    if (conn->p_n < 0) return DNQS_ESTATE;
+    if (n_p) *n_p = conn->p_n;
+    if (nnz_ps) *nnz_ps = conn->ps_nnz;
+    if (fingerprint) {
+        fingerprint[0] = conn->p_fp[0];
+        fingerprint[1] = conn->p_fp[1];
+    }
+    return DNQS_OK;
+}
+
+dnqs_status dnqs_conn_export_p(dnqs_ctx *ctx, const dnqs_conn *c, uint64_t *p_dets, double *p_diag, int64_t *row_ptr,
+                               int32_t *col, float *val) {
+    if (!ctx) return DNQS_EINVAL;
+    if (!c) return fail(ctx, DNQS_EINVAL, "conn is NULL");
+    if (c->p_n < 0) return fail(ctx, DNQS_ESTATE, "P was not built (DNQS_EMIT_P)");
+    if ((row_ptr || col || val) && c->ps_nnz < 0) return fail(ctx, DNQS_ESTATE, "H_PS was not built (DNQS_EMIT_HPS)");
+    TRY(set_device(ctx));
+    hipStream_t st = ctx->stream;
+    const int64_t np = c->p_n;
+    if (p_dets && np) HIPCHK(ctx, hipMemcpyAsync(p_dets, c->p_dets, (size_t)np * 16, hipMemcpyDeviceToDevice, st));
+    if (p_diag && np) HIPCHK(ctx, hipMemcpyAsync(p_diag, c->p_diag, (size_t)np * 8, hipMemcpyDeviceToDevice, st));
+    if (row_ptr) HIPCHK(ctx, hipMemcpyAsync(row_ptr, c->ps_row_ptr, (size_t)(np + 1) * 8, hipMemcpyDeviceToDevice, st));
+    if (col && c->ps_nnz > 0)
+        HIPCHK(ctx, hipMemcpyAsync(col, c->ps_col, (size_t)c->ps_nnz * 4, hipMemcpyDeviceToDevice, st));
+    if (val && c->ps_nnz > 0)
+        HIPCHK(ctx, hipMemcpyAsync(val, c->ps_val, (size_t)c->ps_nnz * 4, hipMemcpyDeviceToDevice, st));
     return DNQS_OK;
 }
 
@@ -879,7 +1463,13 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
                                  const dnqs_conn *conn, int precision, unsigned flags, double *energy,
                                  double *stats, float *grad, double *v_out, double *log_abs, int8_t *sign) {
     if (!ctx) return DNQS_EINVAL;
-    if (flags & ~DNQS_FULL_OUTPUT) return fail(ctx, DNQS_EINVAL, "unknown flags 0x%x", flags);
+    if (flags & ~(DNQS_FULL_OUTPUT | DNQS_ASYM | DNQS_ASYM_ESTIMATOR | DNQS_RECOMPUTE))
+        return fail(ctx, DNQS_EINVAL, "unknown flags 0x%x", flags);
+    const bool asym = (flags & (DNQS_ASYM | DNQS_ASYM_ESTIMATOR)) != 0;
+    if ((flags & DNQS_ASYM) && (flags & DNQS_ASYM_ESTIMATOR))
+        return fail(ctx, DNQS_EINVAL, "DNQS_ASYM and DNQS_ASYM_ESTIMATOR exclude each other");
+    if (asym && conn && conn->n_v <= 0)
+        return fail(ctx, DNQS_EINVAL, "the Asymmetric objective needs a target set (dnqs_build_target)");
     TRY(check_slot(ctx, slot));
     const Slot &sl = ctx->slots[slot];
     NetView nv;
@@ -903,7 +1493,39 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
     float *Ainv = nullptr;
     const bool want_grad = grad != nullptr;
     const bool full_out = (flags & DNQS_FULL_OUTPUT) != 0;
-    TRY(forward(ctx, sl, nv, theta, conn->dets, n, precision, want_grad, la, sg, &Ainv, full_out ? nullptr : conn));
+    // Activation recomputation: only h_{L-1} (read by the output layer's forward and
+    // backward over all rows) is kept; h_1 .. h_{L-2} and U are formed by blocks of RB rows
+    // in the forward pass and formed again by block in the backward pass.  RB is a multiple
+    // of every hidden layer's weight-gradient split chunk (powers of two), so each block
+    // writes whole split partials: the gradient equals the stored path's bit for bit.
+    const bool recompute = (flags & DNQS_RECOMPUTE) && L >= 3;
+    int64_t RB = n;
+    int rc_chunk[DNQS_MAX_LAYERS + 1] = {};
+    GemmCfg rc_cfg[DNQS_MAX_LAYERS + 1];
+    if (recompute) {
+        int64_t maxc = 256;
+        for (int l = 1; l <= L - 1; ++l) {
+            rc_cfg[l] = wgrad_cfg(ctx, gemm_engine(precision, false), w[l - 1] + 1, w[l], n);
+            rc_chunk[l] = wgrad_chunk(n, rc_cfg[l].splits);
+            maxc = std::max<int64_t>(maxc, rc_chunk[l]);
+        }
+        // about eight blocks, 16384 to 65536 rows each (a power of two)
+        int64_t want = 16384;
+        while (want < 65536 && want * 8 < n) want <<= 1;
+        RB = std::max<int64_t>(want, maxc);
+        float *hL1 = nullptr;
+        TRY(ws_t(ctx, "h" + std::to_string(L - 1), (size_t)n * w[L - 1], &hL1));
+        for (int64_t r0 = 0; r0 < n; r0 += RB) {
+            float *hs[DNQS_MAX_LAYERS + 1] = {};
+            TRY(hidden_block(ctx, sl, nv, theta, conn->dets + 2 * r0, std::min(RB, n - r0), precision, nullptr,
+                             hL1 + r0 * w[L - 1], hs, L - 1));
+        }
+        TRY(forward(ctx, sl, nv, theta, conn->dets, n, precision, want_grad, la, sg, &Ainv,
+                    full_out ? nullptr : conn, hL1));
+    } else {
+        TRY(forward(ctx, sl, nv, theta, conn->dets, n, precision, want_grad, la, sg, &Ainv,
+                    full_out ? nullptr : conn));
+    }
     double *psi = nullptr, *v = v_out, *part = nullptr, *part2 = nullptr;
     TRY(ws_t(ctx, "psi", (size_t)n, &psi));
     if (!v) TRY(ws_t(ctx, "v", (size_t)n, &v));
@@ -911,7 +1533,19 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
     TRY(ws_t(ctx, "red_part2", (size_t)spmv_blocks(n), &part2));
     launch_scale_psi(st, la, sg, n, part, stats + 1, psi);
     CHECK_LAUNCH(ctx);
-    launch_spmv_energy(st, conn->row_ptr, conn->col, conn->val, conn->diag, psi, n, v, part, part2, stats, energy);
+    if (asym) {
+        double *u = nullptr, *up = nullptr;
+        TRY(ws_t(ctx, "asym_u", (size_t)n, &u));
+        TRY(ws_t(ctx, "asym_up", (size_t)n, &up));
+        TRY(ws_t(ctx, "red_part3", (size_t)asym_blocks(n), &part2));
+        double *part4 = nullptr;
+        TRY(ws_t(ctx, "red_part4", (size_t)asym_blocks(n), &part4));
+        launch_energy_asym(st, conn->row_ptr, conn->col, conn->val, conn->diag, psi, n, conn->n_v, u, up, part2,
+                           part4, stats, energy, (flags & DNQS_ASYM_ESTIMATOR) ? 1 : 0, v);
+    } else {
+        launch_spmv_energy(st, conn->row_ptr, conn->col, conn->val, conn->diag, psi, n, v, part, part2, stats,
+                           energy);
+    }
     CHECK_LAUNCH(ctx);
     if (!want_grad) return DNQS_OK;
     // adjoint: dO, then layer by layer
@@ -941,14 +1575,14 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
     for (int l = 1; l < L; ++l) maxw = std::max(maxw, w[l]);
     void *dbuf[2];
     TRY(ws_get(ctx, "delta0", (size_t)n * maxw * esz, &dbuf[0]));
-    TRY(ws_get(ctx, "delta1", (size_t)n * maxw * esz, &dbuf[1]));
+    TRY(ws_get(ctx, "delta1", recompute ? 1 : (size_t)n * maxw * esz, &dbuf[1]));
     const void *delta = dO;  // delta_l, starting at l = L
     int which = 0;
     // The weight gradient of layer l and the data gradient delta_{l-1} both read only
     // delta_l: the weight gradients run on the auxiliary stream, overlapping the chain of
     // data gradients.  A data gradient that overwrites a delta buffer waits for the weight
     // gradient that read it; the streams join before db_L is copied.  Not during capture.
-    const bool fork = !ctx->capturing && L < 16;
+    const bool fork = !ctx->capturing && L < 16 && !recompute;
     hipStream_t ast = st;
     if (fork) {
         if (!ctx->aux) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
@@ -989,14 +1623,17 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
                 TRY(tuned_launch(
                     ctx, TuneKey{eng, 1, g.M, g.N, g.K}, gemm_candidates(g.M, g.N, g.K, true, false),
                     [&](const GemmCfg &c) -> dnqs_status {
+                        const int chunk = wgrad_chunk(g.K, c.splits);
+                        const int sp = (int)((g.K + chunk - 1) / chunk);
                         float *partial = nullptr;
-                        TRY(ws_t(ctx, "splitk", (size_t)cnt * c.splits, &partial));
+                        TRY(ws_t(ctx, "splitk", (size_t)cnt * sp, &partial));
                         GemmArgs gs = g;
                         gs.C = partial;
                         gs.c_split_stride = cnt;
-                        launch_gemm(eng, ast, gs, false, true, EPI_STORE, c.splits, c.tm);
+                        gs.k_chunk = chunk;
+                        launch_gemm(eng, ast, gs, false, true, EPI_STORE, sp, c.tm);
                         CHECK_LAUNCH(ctx);
-                        launch_reduce_splits(ast, partial, c.splits, cnt, GD);
+                        launch_reduce_splits(ast, partial, sp, cnt, GD);
                         CHECK_LAUNCH(ctx);
                         return DNQS_OK;
                     },
@@ -1024,14 +1661,17 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
             TRY(tuned_launch(
                 ctx, TuneKey{eng, 1, g.M, g.N, g.K}, gemm_candidates(g.M, g.N, g.K, true, false),
                 [&](const GemmCfg &c) -> dnqs_status {
+                    const int chunk = wgrad_chunk(g.K, c.splits);
+                    const int sp = (int)((g.K + chunk - 1) / chunk);
                     float *partial = nullptr;
-                    TRY(ws_t(ctx, "splitk", (size_t)cnt * c.splits, &partial));
+                    TRY(ws_t(ctx, "splitk", (size_t)cnt * sp, &partial));
                     GemmArgs gs = g;
                     gs.C = partial;
                     gs.c_split_stride = cnt;
-                    launch_gemm(eng, ast, gs, false, true, EPI_STORE, c.splits, c.tm);
+                    gs.k_chunk = chunk;
+                    launch_gemm(eng, ast, gs, false, true, EPI_STORE, sp, c.tm);
                     CHECK_LAUNCH(ctx);
-                    launch_reduce_splits(ast, partial, c.splits, cnt, grad + nv.offW[l]);
+                    launch_reduce_splits(ast, partial, sp, cnt, grad + nv.offW[l]);
                     CHECK_LAUNCH(ctx);
                     return DNQS_OK;
                 },
@@ -1106,11 +1746,156 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
                              }));
         }
         delta = dnext;
+        if (recompute) break;  // layers L-1 .. 1 by blocks of rows, below
     }
+    if (recompute) TRY(backward_blocks(ctx, sl, nv, theta, conn->dets, n, precision, RB, rc_chunk, rc_cfg,
+                                       (const float *)delta, maxw, grad));
     if (fork) HIPCHK(ctx, hipStreamWaitEvent(st, ctx->ev_wdone[1], 0));  // join: every weight gradient is done
     // dPhi0 equals db_L (Phi0 and b_L enter A(x) the same way)
     launch_copy_f32(st, grad + nv.offb[L], grad + nv.offPhi0, (int64_t)No * Ne);
     CHECK_LAUNCH(ctx);
+    return DNQS_OK;
+}
+
+dnqs_status dnqs_lanczos(dnqs_ctx *ctx, const dnqs_conn *conn, int max_iter, double tol, const double *start,
+                         double *energy, double *vec, int *iters, double *residual) {
+    if (!ctx) return DNQS_EINVAL;
+    if (!conn || !energy) return fail(ctx, DNQS_EINVAL, "NULL pointer argument");
+    if (max_iter < 1 || max_iter > 4096) return fail(ctx, DNQS_EINVAL, "max_iter = %d, need 1..4096", max_iter);
+    if (!(tol > 0.0)) return fail(ctx, DNQS_EINVAL, "tol must be positive");
+    TRY(set_device(ctx));
+    hipStream_t st = ctx->stream;
+    const int64_t n = conn->n;
+    const int mmax = (int)std::min<int64_t>(max_iter, n);
+    double *V = nullptr, *w = nullptr, *part = nullptr, *part2 = nullptr, *c = nullptr, *sc = nullptr;
+    TRY(ws_t(ctx, "lz_V", (size_t)n * (mmax + 1), &V));
+    TRY(ws_t(ctx, "lz_w", (size_t)n, &w));
+    TRY(ws_t(ctx, "lz_part", (size_t)std::max<int64_t>({spmv_blocks(n), (int64_t)lanczos_dot_blocks() * (mmax + 1),
+                                                       (int64_t)lanczos_norm_blocks(n)}), &part));
+    TRY(ws_t(ctx, "lz_part2", (size_t)spmv_blocks(n), &part2));
+    TRY(ws_t(ctx, "lz_c", 2 * ((size_t)mmax + 1), &c));
+    TRY(ws_t(ctx, "lz_sc", 8, &sc));  // [0] norm, [1..3] spmv stats, [4] Rayleigh quotient
+    if (start)
+        launch_copy_f64(st, start, w, n);
+    else
+        launch_lz_start(st, conn->diag, n, sc, w);
+    launch_lz_norm(st, w, n, part, sc);
+    launch_lz_scale(st, w, n, sc, V);
+    CHECK_LAUNCH(ctx);
+    std::vector<double> a, b, y;
+    double lam = NAN, res = INFINITY;
+    int m = 0;
+    for (int j = 0; j < mmax; ++j) {
+        double *vj = V + (int64_t)j * n;
+        launch_spmv_energy(st, conn->row_ptr, conn->col, conn->val, conn->diag, vj, n, w, part, part2, sc + 1,
+                           sc + 4);
+        // two rounds of classical Gram-Schmidt against v_0 .. v_j (coefficients c, then
+        // c2); alpha_j = c[j] + c2[j], beta_j = |w| after the second round
+        double *c2 = c + (mmax + 1);
+        launch_lz_dots(st, V, n, j + 1, w, n, part, c, false);
+        launch_lz_orth(st, V, n, j + 1, c, w, n, part, sc);
+        launch_lz_dots(st, V, n, j + 1, w, n, part, c2, false);
+        launch_lz_orth(st, V, n, j + 1, c2, w, n, part, sc);
+        CHECK_LAUNCH(ctx);
+        double hc[3];
+        HIPCHK(ctx, hipMemcpyAsync(hc, c + j, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipMemcpyAsync(hc + 1, c2 + j, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipMemcpyAsync(hc + 2, sc, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));
+        hc[0] += hc[1];
+        hc[1] = hc[2];
+        a.push_back(hc[0]);
+        m = j + 1;
+        lam = tri_lowest(a, b, y);
+        res = hc[1] * std::fabs(y[m - 1]);
+        if (res <= tol * std::max(1.0, std::fabs(lam)) || hc[1] == 0.0 || m == mmax) break;
+        b.push_back(hc[1]);
+        launch_lz_scale(st, w, n, sc, V + (int64_t)(j + 1) * n);
+        CHECK_LAUNCH(ctx);
+    }
+    double *yd = nullptr;
+    TRY(ws_t(ctx, "lz_y", (size_t)m, &yd));
+    HIPCHK(ctx, hipMemcpyAsync(yd, y.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
+    launch_set_f64(st, energy, lam);
+    if (vec) launch_lz_combine(st, V, n, m, yd, n, vec);
+    CHECK_LAUNCH(ctx);
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    if (iters) *iters = m;
+    if (residual) *residual = res;
+    return DNQS_OK;
+}
+
+dnqs_status dnqs_heatbath_candidates(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const double *log_abs,
+                                     const int8_t *sign, double eps_hb, int64_t cap, uint64_t *out_dets,
+                                     int64_t *n_out) {
+    if (!ctx) return DNQS_EINVAL;
+    TRY(check_slot(ctx, slot));
+    const Slot &sl = ctx->slots[slot];
+    if (!conn || !log_abs || !sign || !n_out || (cap > 0 && !out_dets))
+        return fail(ctx, DNQS_EINVAL, "NULL pointer argument");
+    if (conn->M != sl.M || conn->na != sl.na || conn->nb != sl.nb)
+        return fail(ctx, DNQS_EINVAL, "connections were built for another sector");
+    if (!(eps_hb >= 0.0) || !std::isfinite(eps_hb)) return fail(ctx, DNQS_EINVAL, "eps_hb must be finite and >= 0");
+    TRY(set_device(ctx));
+    hipStream_t st = ctx->stream;
+    const int64_t n = conn->n;
+    double *psi = nullptr, *v = nullptr, *part = nullptr, *part2 = nullptr, *stats = nullptr;
+    TRY(ws_t(ctx, "hb_psi", (size_t)n, &psi));
+    TRY(ws_t(ctx, "hb_v", (size_t)n, &v));
+    TRY(ws_t(ctx, "hb_part", (size_t)std::max<int64_t>(spmv_blocks(n), reduce_blocks(n)), &part));
+    TRY(ws_t(ctx, "hb_part2", (size_t)spmv_blocks(n), &part2));
+    TRY(ws_t(ctx, "hb_stats", 4, &stats));
+    launch_scale_psi(st, log_abs, sign, n, part, stats + 1, psi);
+    launch_spmv_energy(st, conn->row_ptr, conn->col, conn->val, conn->diag, psi, n, v, part, part2, stats, stats + 3);
+    CHECK_LAUNCH(ctx);
+    DetSet S{};
+    TRY(s_hash_set(ctx, conn->dets, n, &S));
+    uint64_t *pw = nullptr;
+    int64_t np = 0;
+    TRY(list_candidates(ctx, sl, conn->dets, n, S, psi, eps_hb, stats, &pw, &np));
+    const int64_t k = std::min<int64_t>(np, std::max<int64_t>(cap, 0));
+    if (k > 0) HIPCHK(ctx, hipMemcpyAsync(out_dets, pw, (size_t)k * 16, hipMemcpyDeviceToDevice, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    *n_out = np;
+    return DNQS_OK;
+}
+
+dnqs_status dnqs_select_topk(dnqs_ctx *ctx, int slot, const uint64_t *dets, const double *log_abs,
+                             const int8_t *sign, int64_t n, int64_t K, uint64_t *out_dets, int64_t *n_out) {
+    if (!ctx) return DNQS_EINVAL;
+    TRY(check_slot(ctx, slot));
+    const Slot &sl = ctx->slots[slot];
+    if (!dets || !log_abs || !out_dets || !n_out) return fail(ctx, DNQS_EINVAL, "NULL pointer argument");
+    if (n < 0 || n >= (int64_t)1 << 31 || K < 0) return fail(ctx, DNQS_EINVAL, "n or K out of range");
+    TRY(set_device(ctx));
+    hipStream_t st = ctx->stream;
+    const int64_t k = std::min(n, K);
+    *n_out = k;
+    if (k == 0) return DNQS_OK;
+    SortScratch w{};
+    const size_t nc = sort_scratch_counts(n);
+    int32_t *perm = nullptr;
+    uint64_t *key = nullptr, *tmp = nullptr;
+    TRY(ws_t(ctx, "sort_keys", (size_t)n, &w.keys));
+    TRY(ws_t(ctx, "sort_vals", (size_t)n, &w.vals));
+    TRY(ws_t(ctx, "sort_counts", nc, &w.counts));
+    TRY(ws_t(ctx, "sort_offs", nc, &w.offs));
+    TRY(ws_t(ctx, "sort_bsum", (size_t)scan_blocks((int64_t)nc) + 1, &w.bsum));
+    TRY(ws_t(ctx, "sort_total", 1, &w.total));
+    TRY(ws_t(ctx, "tk_perm", (size_t)n, &perm));
+    TRY(ws_t(ctx, "tk_key", (size_t)n, &key));
+    TRY(ws_t(ctx, "tk_tmp", (size_t)n * 2, &tmp));
+    // canonical order first, then a stable sort by descending log|psi|: equal amplitudes
+    // keep canonical order (ties go to the lower determinant)
+    launch_sort_dets(st, dets, n, sl.M, perm, key, w);
+    launch_topk_key(st, log_abs, sign, perm, n, key);
+    launch_radix_sort(st, key, perm, n, 64, w);
+    launch_permute_words(st, dets, perm, k, 2, tmp);
+    // the selected k in canonical order
+    launch_sort_dets(st, tmp, k, sl.M, perm, key, w);
+    launch_permute_words(st, tmp, perm, k, 2, out_dets);
+    CHECK_LAUNCH(ctx);
+    HIPCHK(ctx, hipStreamSynchronize(st));
     return DNQS_OK;
 }
 
@@ -1126,6 +1911,7 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
     if (opts) o = *opts;
     if (o.export_cap > 0 && (!o.export_keys || !o.export_w || !o.export_haa || !o.export_count))
         return fail(ctx, DNQS_EINVAL, "export buffers missing");
+    if (!(o.eps_hb >= 0.0) || !std::isfinite(o.eps_hb)) return fail(ctx, DNQS_EINVAL, "eps_hb must be finite and >= 0");
     if (conn->n > pt2_max_dets())
         return fail(ctx, DNQS_EINVAL, "pt2 supports |S| <= %d (24-bit determinant index in a pair descriptor)",
                     pt2_max_dets());
@@ -1138,7 +1924,7 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
     double *psi = nullptr, *v = nullptr, *part = nullptr, *part2 = nullptr, *stats = nullptr, *e_tmp = nullptr;
     TRY(ws_t(ctx, "pt2_psi", (size_t)n, &psi));
     TRY(ws_t(ctx, "pt2_v", (size_t)n, &v));
-    TRY(ws_t(ctx, "pt2_part", (size_t)std::max<int64_t>({spmv_blocks(n), 4 * 2048, (int64_t)pt2_accumulate_scratch()}),
+    TRY(ws_t(ctx, "pt2_part", (size_t)std::max<int64_t>({spmv_blocks(n), 8 * 2048, (int64_t)pt2_accumulate_scratch()}),
              &part));
     TRY(ws_t(ctx, "pt2_part2", (size_t)spmv_blocks(n), &part2));
     TRY(ws_t(ctx, "pt2_stats", 4, &stats));
@@ -1146,10 +1932,14 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
     launch_scale_psi(st, log_abs, sign, n, part, stats + 1, psi);
     launch_spmv_energy(st, conn->row_ptr, conn->col, conn->val, conn->diag, psi, n, v, part, part2, stats, e_tmp);
     CHECK_LAUNCH(ctx);
-    double *acc = nullptr;  // [internal | external total | current slice attempt]
-    TRY(ws_t(ctx, "pt2_acc", 12, &acc));
-    launch_pt2_internal(st, psi, v, conn->diag, n, energy, part, acc);
-    launch_pt2_init_acc(st, acc + 4);
+    double *acc = nullptr;  // 8-double records: [internal | external total | current slice attempt]
+    TRY(ws_t(ctx, "pt2_acc", 24, &acc));
+    launch_pt2_init_acc(st, acc + 8);
+    CHECK_LAUNCH(ctx);
+    // internal terms, one per member of S, written by the reduce of the slice it hashes into
+    double *int_term = nullptr;
+    TRY(ws_t(ctx, "pt2_int_term", (size_t)n, &int_term));
+    launch_fill_u64(st, (uint64_t *)int_term, n, 0ull);
     CHECK_LAUNCH(ctx);
     int *overflow = nullptr;
     TRY(ws_t(ctx, "pt2_ovf", 1, &overflow));
@@ -1293,40 +2083,42 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
             int32_t *scnt = nullptr;
             int64_t *soffs = nullptr, *sbsum = nullptr;
             uint64_t *skeys = nullptr;
+            int32_t *sidx = nullptr;
+            TRY(ws_t(ctx, "pt2_sidx", (size_t)std::max<int64_t>(n, 1), &sidx));
             TRY(ws_t(ctx, "pt2_scnt", (size_t)nsb, &scnt));
             TRY(ws_t(ctx, "pt2_soffs", (size_t)nsb, &soffs));
             TRY(ws_t(ctx, "pt2_sbsum", (size_t)scan_blocks(nsb) + 1, &sbsum));
             TRY(ws_t(ctx, "pt2_skeys", (size_t)2 * std::max<int64_t>(n, 1), &skeys));
             const int sbits = s1 + (s2 > 0 ? s2 : 0);
             HIPCHK(ctx, hipMemsetAsync(scnt, 0, sizeof(int32_t) * nsb, st));
-            launch_s_sub(st, conn->dets, n, sbits, packed, scnt, nullptr, nullptr, false, ss, slice);
+            launch_s_sub(st, conn->dets, n, sbits, packed, scnt, nullptr, nullptr, nullptr, false, ss, slice);
             CHECK_LAUNCH(ctx);
             launch_exclusive_scan(st, scnt, nsb, soffs, sbsum, tot + 1);
             CHECK_LAUNCH(ctx);
             int64_t n_s = 0;  // members of S in this slice
             HIPCHK(ctx, hipMemcpyAsync(&n_s, tot + 1, sizeof n_s, hipMemcpyDeviceToHost, st));
             HIPCHK(ctx, hipMemsetAsync(scnt, 0, sizeof(int32_t) * nsb, st));
-            launch_s_sub(st, conn->dets, n, sbits, packed, scnt, soffs, skeys, true, ss, slice);
+            launch_s_sub(st, conn->dets, n, sbits, packed, scnt, soffs, skeys, sidx, true, ss, slice);
             CHECK_LAUNCH(ctx);
             HIPCHK(ctx, hipStreamSynchronize(st));
             double *part_r = nullptr;
-            TRY(ws_t(ctx, "pt2_part_r", (size_t)nsb * 4, &part_r));
-            launch_pt2_init_acc(st, acc + 8);
+            TRY(ws_t(ctx, "pt2_part_r", (size_t)nsb * pt2_red_part(), &part_r));
+            launch_pt2_init_acc(st, acc + 16);
             if (o.export_cap > 0)
                 HIPCHK(ctx, hipMemcpyAsync(o.export_count, ex_save, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
             HIPCHK(ctx, hipMemsetAsync(overflow, 0, sizeof(int), st));
             Timer tr(ctx, "pt2_reduce");
-            launch_pt2_reduce(st, H, rec, desc, sb, nsb, skeys, soffs, n_s, vt, energy, o.sample_mask,
-                              ex, part_r, overflow, packed);
+            launch_pt2_reduce(st, H, rec, desc, sb, nsb, skeys, sidx, soffs, n_s, vt, energy, o.sample_mask,
+                              sl.wexp, o.eps_hb, stats, ex, part_r, int_term, overflow, packed);
             CHECK_LAUNCH(ctx);
             tr.stop();
-            launch_pt2_accumulate(st, part_r, nsb, acc + 8, part);  // the internal-term partials are used up
+            launch_pt2_accumulate(st, part_r, nsb, acc + 16, part);
             CHECK_LAUNCH(ctx);
             int ov = 0;
             HIPCHK(ctx, hipMemcpyAsync(&ov, overflow, sizeof ov, hipMemcpyDeviceToHost, st));
             HIPCHK(ctx, hipStreamSynchronize(st));
             if (!ov) {
-                launch_pt2_merge(st, acc + 4, acc + 8);
+                launch_pt2_merge(st, acc + 8, acc + 16);
                 CHECK_LAUNCH(ctx);
                 nsb_used += nsb;
                 break;
@@ -1336,78 +2128,102 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
             ++s2;
         }
     }
-    launch_pt2_final(st, acc, acc + 4, stats, out, counts, pairs, nsb_used);
+    launch_pt2_internal(st, int_term, conn->diag, n, energy, part, acc);
+    CHECK_LAUNCH(ctx);
+    launch_pt2_final(st, acc, acc + 8, stats, out, counts, pairs, nsb_used);
     CHECK_LAUNCH(ctx);
     tm.stop();
+    if (o.export_cap > 0) TRY(pt2_export_sort(ctx, sl.M, o));
     HIPCHK(ctx, hipStreamSynchronize(st));
     return DNQS_OK;
 }
 
 namespace {
 
-void plan_free(BatchPlan &b) {
+void plan_free(dnqs_ctx *ctx, BatchPlan &b) {
     for (void *q : {(void *)b.dets, (void *)b.pid, (void *)b.row_ptr, (void *)b.col, (void *)b.val, (void *)b.diag,
-                    (void *)b.tile_pid, (void *)b.ksplit, (void *)b.zoff, (void *)b.P_d, (void *)b.ptr_d})
-        if (q) (void)hipFree(q);
+                    (void *)b.tile_pid, (void *)b.ksplit, (void *)b.zrange, (void *)b.P_d, (void *)b.ptr_d,
+                    (void *)b.items, (void *)b.ipart})
+        dev_free(ctx->alloc, q);
     b = BatchPlan();
 }
 
 // rows of weight-gradient split-K per work item
 constexpr int64_t kSplitRows = 4096;
 
+// rows per work item of the per-problem reductions
+constexpr int64_t kItemRows = 4096;
+
 dnqs_status plan_build(dnqs_ctx *ctx, int G, const dnqs_problem *pr) {
     BatchPlan &b = ctx->plan;
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    plan_free(b);
+    plan_free(ctx, b);
     b.G = G;
+    // largest problem first in the concatenated layout, so that the work of every launch
+    // over all problems (GEMM tiles, split-K ranges, reduction items) is ordered largest-first
+    std::vector<int> order(G);
+    for (int g = 0; g < G; ++g) order[g] = g;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return pr[x].conn->n > pr[y].conn->n; });
+    b.off.assign(G, 0);
+    b.end.assign(G, 0);
+    b.nn.assign(G, 0);
     int64_t off = 0, nnz = 0;
     for (int g = 0; g < G; ++g) {
         b.conns.push_back(pr[g].conn);
-        b.off.push_back(off);
-        b.nn.push_back(pr[g].conn->n);
-        off += (pr[g].conn->n + 127) / 128 * 128;
+        b.nn[g] = pr[g].conn->n;
         nnz += pr[g].conn->nnz;
+    }
+    for (int g : order) {
+        b.off[g] = off;
+        off += (pr[g].conn->n + 127) / 128 * 128;
+        b.end[g] = off;
     }
     b.ntot = off;
     b.nnz = nnz;
-    HIPCHK(ctx, hipMalloc(&b.dets, (size_t)b.ntot * 16));
-    HIPCHK(ctx, hipMalloc(&b.pid, (size_t)b.ntot * 4));
-    HIPCHK(ctx, hipMalloc(&b.row_ptr, (size_t)(b.ntot + 1) * 8));
-    HIPCHK(ctx, hipMalloc(&b.col, (size_t)std::max<int64_t>(nnz, 1) * 4));
-    HIPCHK(ctx, hipMalloc(&b.val, (size_t)std::max<int64_t>(nnz, 1) * 4));
-    HIPCHK(ctx, hipMalloc(&b.diag, (size_t)b.ntot * 8));
+    HIPCHK(ctx, dev_alloc(ctx->alloc, (void **)&b.dets, (size_t)b.ntot * 16));
+    HIPCHK(ctx, dev_alloc(ctx->alloc, (void **)&b.pid, (size_t)b.ntot * 4));
+    HIPCHK(ctx, dev_alloc(ctx->alloc, (void **)&b.row_ptr, (size_t)(b.ntot + 1) * 8));
+    HIPCHK(ctx, dev_alloc(ctx->alloc, (void **)&b.col, (size_t)std::max<int64_t>(nnz, 1) * 4));
+    HIPCHK(ctx, dev_alloc(ctx->alloc, (void **)&b.val, (size_t)std::max<int64_t>(nnz, 1) * 4));
+    HIPCHK(ctx, dev_alloc(ctx->alloc, (void **)&b.diag, (size_t)b.ntot * 8));
     int64_t nnz_off = 0;
-    for (int g = 0; g < G; ++g) {
+    for (int g : order) {
         const dnqs_conn *c = pr[g].conn;
-        const int64_t end = g + 1 < G ? b.off[g + 1] : b.ntot;
-        launch_cat_problem(ctx->stream, g, b.off[g], c->n, end, c->dets, c->row_ptr, c->col, c->val, c->diag, c->nnz,
-                           nnz_off, b.dets, b.pid, b.row_ptr, b.col, b.val, b.diag);
+        launch_cat_problem(ctx->stream, g, b.off[g], c->n, b.end[g], c->dets, c->row_ptr, c->col, c->val, c->diag,
+                           c->nnz, nnz_off, b.dets, b.pid, b.row_ptr, b.col, b.val, b.diag);
         CHECK_LAUNCH(ctx);
         nnz_off += c->nnz;
     }
     launch_set_i64(ctx->stream, b.row_ptr + b.ntot, nnz);
-    // tile -> problem, split-K ranges
+    // tile -> problem, split-K ranges (layout order), reduction items (layout order)
     std::vector<int> tp(b.ntot / 128);
-    for (int g = 0; g < G; ++g) {
-        const int64_t end = g + 1 < G ? b.off[g + 1] : b.ntot;
-        for (int64_t t = b.off[g] / 128; t < end / 128; ++t) tp[t] = g;
-    }
-    std::vector<int2> ks;
-    std::vector<int> zo;
-    for (int g = 0; g < G; ++g) {
-        zo.push_back((int)ks.size());
+    for (int g = 0; g < G; ++g)
+        for (int64_t t = b.off[g] / 128; t < b.end[g] / 128; ++t) tp[t] = g;
+    std::vector<int2> ks, zr(G);
+    std::vector<int4> it;
+    for (int g : order) {
+        const int z0 = (int)ks.size();
         for (int64_t r = 0; r < b.nn[g]; r += kSplitRows)
             ks.push_back(make_int2((int)(b.off[g] + r), (int)(b.off[g] + std::min(b.nn[g], r + kSplitRows))));
+        zr[g] = make_int2(z0, (int)ks.size());
+        for (int64_t r = 0; r < b.nn[g]; r += kItemRows)
+            it.push_back(make_int4(g, (int)(b.off[g] + r), (int)std::min(kItemRows, b.nn[g] - r), 0));
     }
-    zo.push_back((int)ks.size());
     b.nz = (int)ks.size();
-    HIPCHK(ctx, hipMalloc(&b.tile_pid, tp.size() * sizeof(int)));
-    HIPCHK(ctx, hipMalloc(&b.ksplit, ks.size() * sizeof(int2)));
-    HIPCHK(ctx, hipMalloc(&b.zoff, zo.size() * sizeof(int)));
+    b.nitems = (int)it.size();
+    HIPCHK(ctx, dev_alloc(ctx->alloc, (void **)&b.tile_pid, tp.size() * sizeof(int)));
+    HIPCHK(ctx, dev_alloc(ctx->alloc, (void **)&b.ksplit, std::max<size_t>(ks.size(), 1) * sizeof(int2)));
+    HIPCHK(ctx, dev_alloc(ctx->alloc, (void **)&b.zrange, zr.size() * sizeof(int2)));
+    HIPCHK(ctx, dev_alloc(ctx->alloc, (void **)&b.items, std::max<size_t>(it.size(), 1) * sizeof(int4)));
+    HIPCHK(ctx, dev_alloc(ctx->alloc, (void **)&b.ipart, std::max<size_t>(it.size(), 1) * 2 * sizeof(double)));
     HIPCHK(ctx, hipMemcpyAsync(b.tile_pid, tp.data(), tp.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(ctx, hipMemcpyAsync(b.ksplit, ks.data(), ks.size() * sizeof(int2), hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(ctx, hipMemcpyAsync(b.zoff, zo.data(), zo.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(ctx, hipMalloc(&b.P_d, (size_t)G * sizeof(ProbDev)));
+    if (!ks.empty())
+        HIPCHK(ctx, hipMemcpyAsync(b.ksplit, ks.data(), ks.size() * sizeof(int2), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(b.zrange, zr.data(), zr.size() * sizeof(int2), hipMemcpyHostToDevice, ctx->stream));
+    if (!it.empty())
+        HIPCHK(ctx, hipMemcpyAsync(b.items, it.data(), it.size() * sizeof(int4), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, dev_alloc(ctx->alloc, (void **)&b.P_d, (size_t)G * sizeof(ProbDev)));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     b.valid = true;
     return DNQS_OK;
@@ -1429,9 +2245,10 @@ dnqs_status plan_pointers(dnqs_ctx *ctx, const NetView &nv, int G, const dnqs_pr
     if (same) return DNQS_OK;
     if (ctx->capturing) return fail(ctx, DNQS_ESTATE, "batched pointers changed during graph capture");
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    if (b.ptr_d) HIPCHK(ctx, hipFree(b.ptr_d));
+    dev_free(ctx->alloc, b.ptr_d);
     b.ptr_d = nullptr;
-    HIPCHK(ctx, hipMalloc(&b.ptr_d, ptr.size() * sizeof(void *)));
+    b.ptr_d = nullptr;
+    HIPCHK(ctx, dev_alloc(ctx->alloc, (void **)&b.ptr_d, ptr.size() * sizeof(void *)));
     b.P_h = P;
     b.ptr_h = ptr;
     b.ptr_layers = nv.L;
@@ -1533,7 +2350,8 @@ dnqs_status dnqs_energy_and_grad_batched(dnqs_ctx *ctx, const dnqs_net *net, int
     if (want_grad) TRY(ws_t(ctx, "b_Ainv", (size_t)n * Ne * Ne, &Ainv));
     launch_orb_lu(st, b.dets, n, M, s0.na, s0.nb, (const float *)prev, nullptr, la, sg, Ainv, rp, nv.offPhi0);
     CHECK_LAUNCH(ctx);
-    launch_energy_grouped(st, la, sg, n, G, rp, b.row_ptr, b.col, b.val, b.diag, psi, v, pv, pp);
+    launch_energy_grouped(st, la, sg, n, G, rp, b.row_ptr, b.col, b.val, b.diag, psi, v, pv, pp, b.items, b.nitems,
+                          b.ipart);
     CHECK_LAUNCH(ctx);
     if (!want_grad) return DNQS_OK;
     // ---- adjoint
@@ -1573,7 +2391,7 @@ dnqs_status dnqs_energy_and_grad_batched(dnqs_ctx *ctx, const dnqs_net *net, int
                          [&](const GemmCfg &c) -> dnqs_status {
                              launch_gemm(eng, st, g, false, true, EPI_STORE, b.nz, c.tm);
                              CHECK_LAUNCH(ctx);
-                             launch_reduce_splits_grouped(st, partial, b.zoff, cnt, G, b.P_d, nv.offW[l]);
+                             launch_reduce_splits_grouped(st, partial, b.zrange, cnt, G, b.P_d, nv.offW[l]);
                              CHECK_LAUNCH(ctx);
                              return DNQS_OK;
                          }));

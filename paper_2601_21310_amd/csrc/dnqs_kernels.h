@@ -24,9 +24,68 @@ void launch_hss_count(hipStream_t st, const Ham &H, const uint64_t *dets, int64_
 void launch_hss_fill(hipStream_t st, const Ham &H, const uint64_t *dets, int64_t n, int nsub, const int64_t *offs,
                      int32_t *col, float *val);
 void launch_row_ptr(hipStream_t st, const int64_t *offs, int64_t n, int nsub, int64_t total, int64_t *row_ptr);
+// val[j] = <x|H|col[j]> for the entries of every row x
+void launch_hss_values(hipStream_t st, const Ham &H, const uint64_t *dets, int64_t n, const int64_t *row_ptr,
+                       const int32_t *col, float *val);
 int64_t scan_blocks(int64_t n);
 void launch_exclusive_scan(hipStream_t st, const int32_t *in, int64_t n, int64_t *out, int64_t *bsum,
                            int64_t *total);
+
+// ---------------------------------------------------------------- sort (k_sort.hip)
+// Workspace of a radix sort of n keys: keys, vals [n]; counts, offs [sort_scratch_counts(n)];
+// bsum [scan_blocks(sort_scratch_counts(n)) + 1]; total [1].
+struct SortScratch {
+    uint64_t *keys;
+    int32_t *vals;
+    int32_t *counts;
+    int64_t *offs;
+    int64_t *bsum;
+    int64_t *total;
+};
+size_t sort_scratch_counts(int64_t n);
+// stable ascending sort of keys[0..n) on their low `bits` bits, vals moved along
+void launch_radix_sort(hipStream_t st, uint64_t *keys, int32_t *vals, int64_t n, int bits, const SortScratch &w);
+void launch_iota_i32(hipStream_t st, int32_t *v, int64_t n);
+void launch_gather_u64(hipStream_t st, const uint64_t *src, const int32_t *perm, int64_t n, uint64_t *dst);
+// dst[i] = src[perm[i]], records of `words` 64-bit words
+void launch_permute_words(hipStream_t st, const uint64_t *src, const int32_t *perm, int64_t n, int words,
+                          uint64_t *dst);
+// perm = the canonical order of dets[0..n) (key: n words of scratch)
+void launch_sort_dets(hipStream_t st, const uint64_t *dets, int64_t n, int M, int32_t *perm, uint64_t *key,
+                      const SortScratch &w);
+
+// ---------------------------------------------------------------- P = C(S) \ S (k_pset.hip)
+// psi (scaled, nullable) with hb_eps > 0: heat-bath screen against hb_eps sqrt(norm2[0])
+void launch_pc_pass(hipStream_t st, const Ham &H, const uint64_t *dets, int64_t n, const DetSet &S,
+                    const double *psi, double hb_eps, const double *norm2, int32_t *cnt, const int64_t *off,
+                    uint64_t *ka, uint64_t *kb, bool fill);
+// key[i]: descending log|psi| of determinant perm[i] (sign 0 last), for a radix sort
+void launch_topk_key(hipStream_t st, const double *la, const int8_t *sg, const int32_t *perm, int64_t n,
+                     uint64_t *key);
+void launch_unique(hipStream_t st, const uint64_t *ka, const uint64_t *kb, const int32_t *perm, int64_t m, bool two,
+                   int M, int32_t *flag, int64_t *pos, int64_t *bsum, int64_t *total, uint64_t *p_dets, bool write);
+void launch_fingerprint(hipStream_t st, const uint64_t *p, int64_t m, unsigned long long *fp);
+void launch_hps_pass(hipStream_t st, const Ham &H, const uint64_t *pd, int64_t m, const DetSet &S, int32_t *cnt,
+                     const int64_t *off, int32_t *col, float *val, bool fill);
+void launch_rows_finish(hipStream_t st, const int64_t *off, int64_t m, const int64_t *total, int64_t *row_ptr,
+                        int32_t *col, float *val);
+void launch_row_ptr_from_offsets(hipStream_t st, const int64_t *off, int64_t m, const int64_t *total,
+                                 int64_t *row_ptr);
+
+// ---------------------------------------------------------------- Lanczos (k_lanczos.hip)
+int lanczos_dot_blocks();
+int lanczos_norm_blocks(int64_t n);
+// c[0..m) (+)= V[k] . w for the m vectors V[k] = V + k ldv; part: m * lanczos_dot_blocks()
+void launch_lz_dots(hipStream_t st, const double *V, int64_t ldv, int m, const double *w, int64_t n, double *part,
+                    double *c, bool accumulate);
+// w -= sum_k c[k] V[k]; nrm[0] = |w| (part: lanczos_norm_blocks(n))
+void launch_lz_orth(hipStream_t st, const double *V, int64_t ldv, int m, const double *c, double *w, int64_t n,
+                    double *part, double *nrm);
+void launch_lz_norm(hipStream_t st, const double *w, int64_t n, double *part, double *nrm);
+void launch_lz_scale(hipStream_t st, const double *src, int64_t n, const double *nrm, double *dst);
+void launch_lz_combine(hipStream_t st, const double *V, int64_t ldv, int m, const double *y, int64_t n,
+                       double *out);
+void launch_lz_start(hipStream_t st, const double *diag, int64_t n, double *tmp1, double *v);
 
 // ---------------------------------------------------------------- network
 enum { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_TANH = 2, EPI_DTANH = 3 };
@@ -91,6 +150,7 @@ void launch_gemm_x3(hipStream_t st, const GemmArgs &g, bool a_kcontig, bool b_nc
 // [C][R] (transpose) or [R][C]; lo = hi + R * C
 void launch_split_planes(hipStream_t st, const float *W, int R, int C, bool transpose, void *planes);
 void launch_reduce_splits(hipStream_t st, const float *part, int splits, int64_t count, float *out);
+void launch_fold_splits(hipStream_t st, const float *part, int splits, int64_t count, float *out, bool accumulate);
 int orb_lu_group(int ne);
 // Output layer in the occupied-row form (k_outsplit.hip): the dense orbitals' column
 // blocks in OD (ldd = nd * Ne per configuration, orbital p at dpos[p] * Ne), every other
@@ -151,10 +211,13 @@ void launch_cat_problem(hipStream_t st, int g, int64_t off, int64_t n, int64_t e
                         int64_t nnz_off, uint64_t *dets_cat, int32_t *pid, int64_t *row_ptr_cat, int32_t *col_cat,
                         float *val_cat, double *diag_cat);
 void launch_set_i64(hipStream_t st, int64_t *p, int64_t v);
+// per problem: l_max, psi, v = H psi and E, the per-problem reductions one workgroup per
+// (problem, row chunk) item, items largest problem first
 void launch_energy_grouped(hipStream_t st, const double *la, const int8_t *sg, int64_t ntot, int G, RowProblems rp,
                            const int64_t *row_ptr, const int32_t *col, const float *val, const double *diag,
-                           double *psi, double *v, double *pv, double *pp);
-void launch_reduce_splits_grouped(hipStream_t st, const float *part, const int *zoff, int64_t cnt, int G,
+                           double *psi, double *v, double *pv, double *pp, const int4 *items, int nitems,
+                           double *ipart);
+void launch_reduce_splits_grouped(hipStream_t st, const float *part, const int2 *zrange, int64_t cnt, int G,
                                   const ProbDev *P, int64_t off);
 void launch_copy_grouped(hipStream_t st, const ProbDev *P, int G, int64_t src, int64_t dst, int64_t cnt);
 void launch_adamw_grouped(hipStream_t st, const ProbDev *P, int G, float *m, float *v, int64_t np, const AdamCfg &c,
@@ -169,6 +232,29 @@ void launch_spmv_energy(hipStream_t st, const int64_t *row_ptr, const int32_t *c
                         const double *diag, const double *psi, int64_t n, double *v, double *part_pv,
                         double *part_pp, double *stats, double *energy);
 void launch_set_f64(hipStream_t st, double *p, double v);
+// stats[0] = sum of part_pp, stats[2] = sum of part_pv (fixed order), energy = ratio
+void launch_energy_final(hipStream_t st, const double *part_pv, const double *part_pp, int64_t nb, double *stats,
+                         double *energy);
+
+// ---------------------------------------------------------------- target-set modes (k_modes.hip)
+void launch_count_in_set(hipStream_t st, const uint64_t *p, int64_t m, const DetSet &S, int *count);
+// transpose of an m-row CSR with ncols columns: pass 1 (fill = false) counts into cnt and
+// scans into off / total; pass 2 (cnt zeroed) scatters and sorts each row by column
+void launch_csr_transpose(hipStream_t st, const int64_t *row_ptr, const int32_t *col, const float *val, int64_t m,
+                          int64_t ncols, int32_t *cnt, int64_t *off, int64_t *bsum, int64_t *total,
+                          int64_t *t_row_ptr, int32_t *t_col, float *t_val, bool fill);
+// proxy matrix over T = [V; P] from H_VV, H_VP, H_PV: pass 1 row lengths and offsets,
+// pass 2 the entries
+void launch_target_assemble(hipStream_t st, const int64_t *vv, const int32_t *vvc, const float *vvv,
+                            const int64_t *vp, const int32_t *vpc, const float *vpv, const int64_t *pv,
+                            const int32_t *pvc, const float *pvv, int64_t nv, int64_t np, int32_t *len,
+                            int64_t *off, int64_t *bsum, int64_t *total, int32_t *col, float *val, bool fill);
+int64_t asym_blocks(int64_t n);
+// Asymmetric objective (Eq. 6) on the proxy matrix over T: E, stats (psi_V^T psi_V,
+// psi_V^T H_VT psi_T) and the adjoint's vector v (exact gradient, or Eq. 7's estimator)
+void launch_energy_asym(hipStream_t st, const int64_t *row_ptr, const int32_t *col, const float *val,
+                        const double *diag, const double *psi, int64_t n, int64_t nv, double *u, double *up,
+                        double *part_pv, double *part_pp, double *stats, double *energy, int estimator, double *v);
 void launch_copy_f64(hipStream_t st, const double *a, double *b, int64_t n);
 
 // ---------------------------------------------------------------- PT2
@@ -186,6 +272,7 @@ struct PT2Chunk {
 
 int64_t pt2_l1_groups(int64_t n);
 int pt2_red_tab();
+int pt2_red_part();
 int pt2_max_k1();
 int pt2_max_k2();
 // ss > 0: key-space slice `slice` of 2^ss (targets with those top hash bits only)
@@ -208,20 +295,27 @@ void launch_diag_table(hipStream_t st, const Ham &H, double *vt);
 // keys (sbits hash bits after the ss slice bits): count into cnt (fill == false), or
 // place into skeys at offs[sub] + cursor (cnt used as cursors)
 void launch_s_sub(hipStream_t st, const uint64_t *dets, int64_t n, int sbits, bool packed, int32_t *cnt,
-                  const int64_t *offs, uint64_t *skeys, bool fill, int ss, uint32_t slice);
-// rec: the source records of launch_pt2_records (same packed flag)
+                  const int64_t *offs, uint64_t *skeys, int32_t *sidx, bool fill, int ss, uint32_t slice);
+// rec: the source records of launch_pt2_records (same packed flag); wexp: 2^wexp bounds
+// |H_ax psi_x| (psi scaled to max |psi| = 1); part: kRedPart doubles per sub-bucket;
+// int_term[x]: the internal term of each member x of S in the processed slice;
+// hb_eps > 0: only keys with some |H_ax psi_x| >= hb_eps sqrt(norm2[0]) enter the external sum
 void launch_pt2_reduce(hipStream_t st, const Ham &H, const uint64_t *rec, const uint64_t *desc,
-                       const int64_t *sb, int64_t nsb, const uint64_t *skeys, const int64_t *soffs, int64_t n_s,
-                       const double *vt, const double *energy, uint64_t sample_mask, const PT2Export &ex, double *part,
-                       int *overflow, bool packed);
-// acc += the partials part[4 nb] (sum, min, |P|, tiny), in a fixed order; scratch (if not
-// null) holds pt2_accumulate_scratch() doubles for a two-level sum
+                       const int64_t *sb, int64_t nsb, const uint64_t *skeys, const int32_t *sidx,
+                       const int64_t *soffs, int64_t n_s, const double *vt, const double *energy,
+                       uint64_t sample_mask, int wexp, double hb_eps, const double *norm2, const PT2Export &ex,
+                       double *part, double *int_term, int *overflow, bool packed);
+// acc (8 doubles) += the partial records part[8 nb] (sum, min, |P|, tiny, fingerprint sum and
+// XOR), in a fixed order; scratch (if not null) holds pt2_accumulate_scratch() doubles
+// for a two-level sum
 void launch_pt2_accumulate(hipStream_t st, const double *part, int64_t nb, double *acc, double *scratch = nullptr);
 int pt2_accumulate_scratch();
-void launch_pt2_internal(hipStream_t st, const double *psi, const double *v, const double *diag, int64_t n,
-                         const double *energy, double *part, double *acc_int);
+// acc_int (8 doubles) = fixed-order sum of term[0..n) with min |E - diag| and tiny count;
+// part holds 8 * 2048 doubles
+void launch_pt2_internal(hipStream_t st, const double *term, const double *diag, int64_t n, const double *energy,
+                         double *part, double *acc_int);
 void launch_pt2_init_acc(hipStream_t st, double *acc);
-// acc += part (sum, min, counts): a finished key-space slice into the external total
+// acc += part (8-double records): a finished key-space slice into the external total
 void launch_pt2_merge(hipStream_t st, double *acc, const double *part);
 // per determinant of S: {alpha | beta << 32, psi bits} when packed (M <= 32), else
 // {alpha, beta, psi bits, 0}; rec holds 4 n words

@@ -14,7 +14,8 @@ constexpr int kMaxK1 = 1024;
 constexpr int kMaxK2 = 4096;
 constexpr int kMaxK2Staged = 1024;     // sub-buckets per L1 bucket the staged L2 pass handles
 constexpr int kRedThreads = 512;
-constexpr int kRedTab = 4096;  // LDS hash-table slots per sub-bucket
+constexpr int kRedTab = 3072;  // LDS hash-table slots per sub-bucket (a multiple of kRedThreads)
+constexpr int kRedPart = 8;    // doubles of per-sub-bucket output (see k_pt2_reduce)
 constexpr int kRedSingles = 256;  // single-excitation pairs a reduce workgroup queues in LDS
 
 __device__ __forceinline__ uint32_t l1_bucket(uint64_t h, int s1) { return s1 ? (uint32_t)(h >> (64 - s1)) : 0u; }

@@ -89,13 +89,70 @@ __device__ inline double seg_block_sum(double v) {
     return r;
 }
 
-// stats_g[1] = max over the problem's rows of log|psi|
-__global__ __launch_bounds__(kSegBlock) void k_seg_lmax(const double *__restrict__ la, const ProbDev *__restrict__ P) {
-    const ProbDev p = P[blockIdx.x];
+// ---------------------------------------------------------------- per-item reductions
+// The per-problem reductions are cut into work items {problem, first row, rows} of at
+// most 4096 rows, listed in layout order, largest problem first, and launched one
+// workgroup per item: the dispatcher starts workgroups in index order, so it hands out
+// the items largest problem first and the short problems fill the tail, with no
+// software queue.  Each item's partial result goes to its own slot and the slots of a
+// problem are combined in item order, so the results do not depend on which CU ran which
+// item.  (A persistent form that pulled items from an atomic head was miscompiled: with
+// the head read by one lane and broadcast through LDS, the compiler split the loop so that
+// the other lanes repeated the barrier-and-read part without the lane that takes the next
+// item, and the workgroups spun.)
+
+// ipart[2 item] = max of log|psi| over the item's rows
+__global__ __launch_bounds__(kSegBlock) void k_item_lmax(const double *__restrict__ la, const int4 *__restrict__ items,
+                                                         double *__restrict__ ipart) {
+    const int it = blockIdx.x;
+    const int4 w = items[it];
     double m = -INFINITY;
-    for (int64_t i = threadIdx.x; i < p.n; i += blockDim.x) m = fmax(m, la[p.off + i]);
+    for (int i = threadIdx.x; i < w.z; i += blockDim.x) m = fmax(m, la[(int64_t)w.y + i]);
     m = seg_block_max(m);
-    if (threadIdx.x == 0) p.stats[1] = m;
+    if (threadIdx.x == 0) ipart[2 * it] = m;
+}
+
+// ipart[2 item] = sum of psi v, ipart[2 item + 1] = sum of psi^2 over the item's rows
+__global__ __launch_bounds__(kSegBlock) void k_item_energy(const double *__restrict__ pv, const double *__restrict__ pp,
+                                                           const int4 *__restrict__ items, double *__restrict__ ipart) {
+    const int it = blockIdx.x;
+    const int4 w = items[it];
+    double a = 0.0, c = 0.0;
+    for (int i = threadIdx.x; i < w.z; i += blockDim.x) {
+        a += pv[(int64_t)w.y + i];
+        c += pp[(int64_t)w.y + i];
+    }
+    a = seg_block_sum(a);
+    c = seg_block_sum(c);
+    if (threadIdx.x == 0) {
+        ipart[2 * it] = a;
+        ipart[2 * it + 1] = c;
+    }
+}
+
+// one thread per problem: combine its items in order (items of a problem are contiguous)
+__global__ void k_q_finish(const int4 *__restrict__ items, int nitems, const double *__restrict__ ipart,
+                           const ProbDev *__restrict__ P, int G, int energy) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    double a = energy ? 0.0 : -INFINITY, c = 0.0;
+    for (int it = 0; it < nitems; ++it) {
+        if (items[it].x != g) continue;
+        if (energy) {
+            a += ipart[2 * it];
+            c += ipart[2 * it + 1];
+        } else {
+            a = fmax(a, ipart[2 * it]);
+        }
+    }
+    const ProbDev p = P[g];
+    if (!energy) {
+        p.stats[1] = a;
+        return;
+    }
+    p.stats[0] = c;
+    p.stats[2] = a;
+    p.energy[0] = c > 0.0 ? a / c : NAN;
 }
 
 // psi[x] = sign exp(la - lmax of its problem); 0 on padding rows
@@ -127,41 +184,28 @@ __global__ __launch_bounds__(256) void k_spmv_rows(const int64_t *__restrict__ r
     }
 }
 
-// per problem: stats = {psi^T psi, (lmax), psi^T v}, energy = psi^T v / psi^T psi
-__global__ __launch_bounds__(kSegBlock) void k_seg_energy(const double *__restrict__ pv, const double *__restrict__ pp,
-                                                          const ProbDev *__restrict__ P) {
-    const ProbDev p = P[blockIdx.x];
-    double a = 0.0, c = 0.0;
-    for (int64_t i = threadIdx.x; i < p.n; i += blockDim.x) {
-        a += pv[p.off + i];
-        c += pp[p.off + i];
-    }
-    a = seg_block_sum(a);
-    c = seg_block_sum(c);
-    if (threadIdx.x == 0) {
-        p.stats[0] = c;
-        p.stats[2] = a;
-        p.energy[0] = c > 0.0 ? a / c : NAN;
-    }
-}
-
 void launch_energy_grouped(hipStream_t st, const double *la, const int8_t *sg, int64_t ntot, int G, RowProblems rp,
                            const int64_t *row_ptr, const int32_t *col, const float *val, const double *diag,
-                           double *psi, double *v, double *pv, double *pp) {
-    hipLaunchKernelGGL(k_seg_lmax, dim3(G), dim3(kSegBlock), 0, st, la, rp.P);
+                           double *psi, double *v, double *pv, double *pp, const int4 *items, int nitems,
+                           double *ipart) {
+    const unsigned fg = (unsigned)((G + 63) / 64);
+    if (nitems > 0) hipLaunchKernelGGL(k_item_lmax, dim3((unsigned)nitems), dim3(kSegBlock), 0, st, la, items, ipart);
+    hipLaunchKernelGGL(k_q_finish, dim3(fg), dim3(64), 0, st, items, nitems, ipart, rp.P, G, 0);
     hipLaunchKernelGGL(k_psi_grouped, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, st, la, sg, ntot, rp, psi);
     hipLaunchKernelGGL(k_spmv_rows, dim3((unsigned)((ntot * kWave + 255) / 256)), dim3(256), 0, st, row_ptr, col, val,
                        diag, psi, ntot, v, pv, pp);
-    hipLaunchKernelGGL(k_seg_energy, dim3(G), dim3(kSegBlock), 0, st, pv, pp, rp.P);
+    if (nitems > 0)
+        hipLaunchKernelGGL(k_item_energy, dim3((unsigned)nitems), dim3(kSegBlock), 0, st, pv, pp, items, ipart);
+    hipLaunchKernelGGL(k_q_finish, dim3(fg), dim3(64), 0, st, items, nitems, ipart, rp.P, G, 1);
 }
 
 // ---------------------------------------------------------------- gradients
-// grad_g[off + i] = sum over z in [zoff[g], zoff[g+1]) of part[z * cnt + i]  (fixed order)
-__global__ void k_reduce_splits_grouped(const float *__restrict__ part, const int *__restrict__ zoff, int64_t cnt,
+// grad_g[off + i] = sum over z in [zrange[g].x, zrange[g].y) of part[z * cnt + i]  (fixed order)
+__global__ void k_reduce_splits_grouped(const float *__restrict__ part, const int2 *__restrict__ zrange, int64_t cnt,
                                         const ProbDev *__restrict__ P, int64_t off) {
     const int g = blockIdx.y;
     float *out = P[g].grad + off;
-    const int z0 = zoff[g], z1 = zoff[g + 1];
+    const int z0 = zrange[g].x, z1 = zrange[g].y;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
         float s = 0.0f;
         int z = z0;
@@ -177,11 +221,11 @@ __global__ void k_reduce_splits_grouped(const float *__restrict__ part, const in
     }
 }
 
-void launch_reduce_splits_grouped(hipStream_t st, const float *part, const int *zoff, int64_t cnt, int G,
+void launch_reduce_splits_grouped(hipStream_t st, const float *part, const int2 *zrange, int64_t cnt, int G,
                                   const ProbDev *P, int64_t off) {
     int64_t bx = (cnt + 255) / 256;
     if (bx > 256) bx = 256;
-    hipLaunchKernelGGL(k_reduce_splits_grouped, dim3((unsigned)bx, G), dim3(256), 0, st, part, zoff, cnt, P, off);
+    hipLaunchKernelGGL(k_reduce_splits_grouped, dim3((unsigned)bx, G), dim3(256), 0, st, part, zrange, cnt, P, off);
 }
 
 // grad_g[dst + i] = grad_g[src + i]

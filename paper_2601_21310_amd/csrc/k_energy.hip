@@ -161,6 +161,11 @@ void launch_spmv_energy(hipStream_t st, const int64_t *row_ptr, const int32_t *c
     hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kRedBlock), 0, st, part_pv, part_pp, nb, stats, energy);
 }
 
+void launch_energy_final(hipStream_t st, const double *part_pv, const double *part_pp, int64_t nb, double *stats,
+                         double *energy) {
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kRedBlock), 0, st, part_pv, part_pp, nb, stats, energy);
+}
+
 __global__ void k_set_f64(double *p, double v) { p[0] = v; }
 
 void launch_set_f64(hipStream_t st, double *p, double v) {

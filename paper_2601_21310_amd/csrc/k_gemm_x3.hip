@@ -607,7 +607,8 @@ void launch_gemm_x3(hipStream_t st, const GemmArgs &g0, bool a_kcontig, bool b_n
     if (splits < 1) splits = 1;
     int chunk = (g.K + splits - 1) / splits;
     chunk = (chunk + XBK - 1) / XBK * XBK;
-    g.k_chunk = chunk > 0 ? chunk : XBK;
+    // a chunk given by the caller (a multiple of XBK) fixes the split ranges
+    g.k_chunk = g0.k_chunk > 0 ? g0.k_chunk : (chunk > 0 ? chunk : XBK);
     if (g.bsplit && a_kcontig) {  // weights as B: pre-split planes
 #define DISPATCH_PRE(EPI)                                    \
     if (tm == 64)                                            \

@@ -11,7 +11,8 @@
 // wave-uniform (scalar loads).  Hits are compacted in lane order with ballot/mbcnt,
 // so each row's columns come out in ascending order without a sort:
 //   pass 1 counts hits per (row, column range), an exclusive scan gives offsets,
-//   pass 2 repeats the sweep and writes col/val.
+//   pass 2 repeats the sweep and writes the columns,
+//   pass 3 evaluates the couplings, one wave per row over its entries.
 #include "dnqs_device.h"
 #include "dnqs_kernels.h"
 
@@ -176,11 +177,7 @@ __global__ __launch_bounds__(256) void k_hss_pairs(Ham H, const uint64_t *__rest
             const uint64_t m = ballot(hit);
             if (m) {
                 if (FILL) {
-                    if (hit) {
-                        const int64_t pos = cursor[wave][r] + mbcnt(m);
-                        col[pos] = (int32_t)y;
-                        val[pos] = (float)h_offdiag(H, EriPacked{H.eri_pk}, xa, xb, ya, ybb);
-                    }
+                    if (hit) col[cursor[wave][r] + mbcnt(m)] = (int32_t)y;
                 }
                 if (lane == 0) cursor[wave][r] += __popcll(m);
                 __builtin_amdgcn_wave_barrier();
@@ -211,6 +208,30 @@ void launch_hss_fill(hipStream_t st, const Ham &H, const uint64_t *dets, int64_t
                      int32_t *col, float *val) {
     dim3 grid((unsigned)((n + kRowBlock - 1) / kRowBlock), (unsigned)(nsub / kWavesPerBlock));
     hipLaunchKernelGGL(k_hss_pairs<true>, grid, dim3(256), 0, st, H, dets, n, nsub, nullptr, offs, col, val);
+}
+
+// Values of H_SS after the structure is known: one wave per row, its lanes over the
+// row's entries, so that every lane of a wave evaluates a coupling (in the sweep only the
+// one or two lanes of a hit would be active).  The row's determinant is wave-uniform.
+__global__ __launch_bounds__(256) void k_hss_values(Ham H, const uint64_t *__restrict__ dets, int64_t n,
+                                                    const int64_t *__restrict__ row_ptr,
+                                                    const int32_t *__restrict__ col, float *__restrict__ val) {
+    const int lane = threadIdx.x % kWave;
+    const int64_t x = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    if (x >= n) return;
+    const uint64_t xa = dets[2 * x], xb = dets[2 * x + 1];
+    const int64_t b = row_ptr[x], e = row_ptr[x + 1];
+    const EriPacked eri{H.eri_pk};
+    for (int64_t j = b + lane; j < e; j += kWave) {
+        const int64_t y = col[j];
+        val[j] = (float)h_offdiag(H, eri, xa, xb, dets[2 * y], dets[2 * y + 1]);
+    }
+}
+
+void launch_hss_values(hipStream_t st, const Ham &H, const uint64_t *dets, int64_t n, const int64_t *row_ptr,
+                       const int32_t *col, float *val) {
+    hipLaunchKernelGGL(k_hss_values, dim3((unsigned)((n * kWave + 255) / 256)), dim3(256), 0, st, H, dets, n, row_ptr,
+                       col, val);
 }
 
 // row_ptr[i] = offs[i*nsub], row_ptr[n] = total

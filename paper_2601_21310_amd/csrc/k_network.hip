@@ -422,7 +422,8 @@ void launch_gemm_f32(hipStream_t st, const GemmArgs &g0, bool a_kcontig, bool b_
                      int tm) {
     GemmArgs g = g0;
     if (splits < 1) splits = 1;
-    g.k_chunk = split_chunk(g.K, splits);
+    // a chunk given by the caller (a multiple of BK) fixes the split ranges
+    g.k_chunk = g0.k_chunk > 0 ? g0.k_chunk : split_chunk(g.K, splits);
 #define DISPATCH_TM(AK, BNC, EPI)                                           \
     if (tm == 64)                                                           \
         launch_gemm_t<AK, BNC, EPI, 64>(st, g, splits);                     \
@@ -468,6 +469,27 @@ void launch_reduce_splits(hipStream_t st, const float *part, int splits, int64_t
     int64_t blocks = (count + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)blocks), dim3(256), 0, st, part, splits, count, out);
+}
+
+// out[i] (+)= the splits' partials added in split order onto out[i] (0 for the first
+// fold): folding the splits block by block gives the bits of one k_reduce_splits over
+// all of them, since that sum is also taken left to right starting from 0.
+__global__ void k_fold_splits(const float *__restrict__ part, int splits, int64_t count, float *__restrict__ out,
+                              int accumulate) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < count; i += stride) {
+        float s = accumulate ? out[i] : 0.0f;
+        for (int z = 0; z < splits; ++z) s += part[(int64_t)z * count + i];
+        out[i] = s;
+    }
+}
+
+void launch_fold_splits(hipStream_t st, const float *part, int splits, int64_t count, float *out, bool accumulate) {
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fold_splits, dim3((unsigned)blocks), dim3(256), 0, st, part, splits, count, out,
+                       accumulate ? 1 : 0);
 }
 
 // ------------------------------------------------------------------ orbital rows + LU

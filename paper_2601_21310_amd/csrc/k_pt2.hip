@@ -1,29 +1,66 @@
-// Epstein-Nesbet PT2 (Eq. 13): the internal term over S, fixed-order accumulation of
-// per-workgroup partial sums, and the final combination.  The external sum over P is
-// in k_pt2_part.hip.
+// Epstein-Nesbet PT2 (Eq. 13): the fixed-order sum of the internal terms over S, the
+// fixed-order accumulation of per-sub-bucket partial records, and the final combination.
+// The pair partition is in k_pt2_part.hip, the per-sub-bucket reduce in k_pt2_reduce.hip.
 #include "dnqs_device.h"
 #include "dnqs_kernels.h"
 
 namespace dnqs {
 
 constexpr int kFinBlock = 256;
+constexpr int kRec = 8;  // doubles per partial record (kRedPart)
 
-__device__ inline void block_sum_min(double &s, double &mn, unsigned long long &np, unsigned long long &nt) {
+// One partial record: {sum, min |E - H_aa|, |P|, tiny, fingerprint sum bits, fingerprint
+// XOR bits, 0, 0}.  Counts and the fingerprint are integers (exact in any order); the
+// sums of records are taken in a fixed order.
+struct Rec {
+    double s, mn;
+    unsigned long long np, nt, fs, fx;
+};
+
+__device__ __forceinline__ Rec rec_zero() { return Rec{0.0, INFINITY, 0ull, 0ull, 0ull, 0ull}; }
+
+__device__ __forceinline__ void rec_add(Rec &r, const double *p) {
+    r.s += p[0];
+    r.mn = fmin(r.mn, p[1]);
+    r.np += (unsigned long long)p[2];
+    r.nt += (unsigned long long)p[3];
+    r.fs += (unsigned long long)__double_as_longlong(p[4]);
+    r.fx ^= (unsigned long long)__double_as_longlong(p[5]);
+}
+
+__device__ __forceinline__ void rec_store(const Rec &r, double *p) {
+    p[0] = r.s;
+    p[1] = r.mn;
+    p[2] = (double)r.np;
+    p[3] = (double)r.nt;
+    p[4] = __longlong_as_double((long long)r.fs);
+    p[5] = __longlong_as_double((long long)r.fx);
+    p[6] = 0.0;
+    p[7] = 0.0;
+}
+
+// block reduction of a record (fixed order: lanes by xor butterfly, then waves in order)
+__device__ inline void block_rec(Rec &r) {
     __shared__ double ss[kFinBlock / kWave], sm[kFinBlock / kWave];
-    __shared__ unsigned long long sp[kFinBlock / kWave], st[kFinBlock / kWave];
+    __shared__ unsigned long long sp[kFinBlock / kWave], st[kFinBlock / kWave], sf[kFinBlock / kWave],
+        sx[kFinBlock / kWave];
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
-        s += __shfl_xor(s, o, 64);
-        mn = fmin(mn, __shfl_xor(mn, o, 64));
-        np += __shfl_xor(np, o, 64);
-        nt += __shfl_xor(nt, o, 64);
+        r.s += __shfl_xor(r.s, o, 64);
+        r.mn = fmin(r.mn, __shfl_xor(r.mn, o, 64));
+        r.np += __shfl_xor(r.np, o, 64);
+        r.nt += __shfl_xor(r.nt, o, 64);
+        r.fs += __shfl_xor(r.fs, o, 64);
+        r.fx ^= __shfl_xor(r.fx, o, 64);
     }
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     if (lane == 0) {
-        ss[wave] = s;
-        sm[wave] = mn;
-        sp[wave] = np;
-        st[wave] = nt;
+        ss[wave] = r.s;
+        sm[wave] = r.mn;
+        sp[wave] = r.np;
+        st[wave] = r.nt;
+        sf[wave] = r.fs;
+        sx[wave] = r.fx;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -32,73 +69,72 @@ __device__ inline void block_sum_min(double &s, double &mn, unsigned long long &
             sm[0] = fmin(sm[0], sm[w]);
             sp[0] += sp[w];
             st[0] += st[w];
+            sf[0] += sf[w];
+            sx[0] ^= sx[w];
         }
-        s = ss[0];
-        mn = sm[0];
-        np = sp[0];
-        nt = st[0];
+        r.s = ss[0];
+        r.mn = sm[0];
+        r.np = sp[0];
+        r.nt = st[0];
+        r.fs = sf[0];
+        r.fx = sx[0];
     }
 }
 
-// acc[0] += ext sum, acc[1] = min(acc[1], min den), acc[2] += |P|, acc[3] += tiny; fixed order
+// acc (one record) += the records part[0 .. nb), in a fixed order
 __global__ __launch_bounds__(kFinBlock) void k_pt2_accumulate(const double *__restrict__ part, int64_t nb,
                                                               double *__restrict__ acc) {
-    double s = 0.0, mn = INFINITY;
-    unsigned long long np = 0, nt = 0;
-    for (int64_t i = threadIdx.x; i < nb; i += blockDim.x) {
-        s += part[4 * i];
-        mn = fmin(mn, part[4 * i + 1]);
-        np += (unsigned long long)part[4 * i + 2];
-        nt += (unsigned long long)part[4 * i + 3];
-    }
-    block_sum_min(s, mn, np, nt);
+    Rec r = rec_zero();
+    for (int64_t i = threadIdx.x; i < nb; i += blockDim.x) rec_add(r, part + kRec * i);
+    block_rec(r);
     if (threadIdx.x == 0) {
-        acc[0] += s;
-        acc[1] = fmin(acc[1], mn);
-        acc[2] += (double)np;
-        acc[3] += (double)nt;
+        Rec a = rec_zero();
+        rec_add(a, acc);
+        a.s += r.s;
+        a.mn = fmin(a.mn, r.mn);
+        a.np += r.np;
+        a.nt += r.nt;
+        a.fs += r.fs;
+        a.fx ^= r.fx;
+        rec_store(a, acc);
     }
 }
 
-// internal term over S: sum (v - E psi)^2 / (E - diag), terms with zero numerator skipped
-__global__ __launch_bounds__(kFinBlock) void k_pt2_internal(const double *__restrict__ psi,
-                                                            const double *__restrict__ v,
+// Internal term over S (Eq. 13, first sum): the terms term[i] were formed by the reduce
+// from exact FP64 couplings; here they are summed in a fixed order, with the minimum of
+// |E - H_ii| and the count of |E - H_ii| < 1e-8 over S.
+__global__ __launch_bounds__(kFinBlock) void k_pt2_internal(const double *__restrict__ term,
                                                             const double *__restrict__ diag, int64_t n,
                                                             const double *__restrict__ energy,
                                                             double *__restrict__ part) {
     const double E = energy[0];
-    double s = 0.0, mn = INFINITY;
-    unsigned long long np = 0, nt = 0;
+    Rec r = rec_zero();
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double r = v[i] - E * psi[i];
         const double den = E - diag[i];
-        mn = fmin(mn, fabs(den));
-        if (fabs(den) < 1e-8) ++nt;
-        const double num = r * r;
-        if (num != 0.0) s += num / den;
+        r.mn = fmin(r.mn, fabs(den));
+        if (fabs(den) < 1e-8) ++r.nt;
+        r.s += term[i];
     }
-    block_sum_min(s, mn, np, nt);
+    block_rec(r);
     if (threadIdx.x == 0) {
-        part[4 * blockIdx.x + 0] = s;
-        part[4 * blockIdx.x + 1] = mn;
-        part[4 * blockIdx.x + 2] = 0.0;
-        part[4 * blockIdx.x + 3] = (double)nt;
+        r.np = 0ull;
+        r.fs = 0ull;
+        r.fx = 0ull;
+        rec_store(r, part + kRec * blockIdx.x);
     }
 }
 
 __global__ void k_pt2_init_acc(double *acc) {
-    acc[0] = 0.0;
-    acc[1] = INFINITY;
-    acc[2] = 0.0;
-    acc[3] = 0.0;
+    const Rec r = rec_zero();
+    rec_store(r, acc);
 }
 
-void launch_pt2_internal(hipStream_t st, const double *psi, const double *v, const double *diag, int64_t n,
-                         const double *energy, double *part, double *acc_int) {
+void launch_pt2_internal(hipStream_t st, const double *term, const double *diag, int64_t n, const double *energy,
+                         double *part, double *acc_int) {
     int64_t nb = (n + kFinBlock - 1) / kFinBlock;
     if (nb > 2048) nb = 2048;
     hipLaunchKernelGGL(k_pt2_init_acc, dim3(1), dim3(1), 0, st, acc_int);
-    hipLaunchKernelGGL(k_pt2_internal, dim3((unsigned)nb), dim3(kFinBlock), 0, st, psi, v, diag, n, energy, part);
+    hipLaunchKernelGGL(k_pt2_internal, dim3((unsigned)nb), dim3(kFinBlock), 0, st, term, diag, n, energy, part);
     hipLaunchKernelGGL(k_pt2_accumulate, dim3(1), dim3(kFinBlock), 0, st, part, nb, acc_int);
 }
 
@@ -110,21 +146,10 @@ __global__ __launch_bounds__(kFinBlock) void k_pt2_accumulate_chunks(const doubl
                                                                      double *__restrict__ out) {
     const int64_t chunk = (nb + gridDim.x - 1) / gridDim.x;
     const int64_t lo = (int64_t)blockIdx.x * chunk, hi = lo + chunk < nb ? lo + chunk : nb;
-    double s = 0.0, mn = INFINITY;
-    unsigned long long np = 0, nt = 0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        s += part[4 * i];
-        mn = fmin(mn, part[4 * i + 1]);
-        np += (unsigned long long)part[4 * i + 2];
-        nt += (unsigned long long)part[4 * i + 3];
-    }
-    block_sum_min(s, mn, np, nt);
-    if (threadIdx.x == 0) {
-        out[4 * blockIdx.x + 0] = s;
-        out[4 * blockIdx.x + 1] = mn;
-        out[4 * blockIdx.x + 2] = (double)np;
-        out[4 * blockIdx.x + 3] = (double)nt;
-    }
+    Rec r = rec_zero();
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) rec_add(r, part + kRec * i);
+    block_rec(r);
+    if (threadIdx.x == 0) rec_store(r, out + kRec * blockIdx.x);
 }
 
 void launch_pt2_accumulate(hipStream_t st, const double *part, int64_t nb, double *acc, double *scratch) {
@@ -136,17 +161,17 @@ void launch_pt2_accumulate(hipStream_t st, const double *part, int64_t nb, doubl
     }
 }
 
-int pt2_accumulate_scratch() { return 4 * kAccBlocks; }
+int pt2_accumulate_scratch() { return kRec * kAccBlocks; }
 
 void launch_pt2_init_acc(hipStream_t st, double *acc) {
     hipLaunchKernelGGL(k_pt2_init_acc, dim3(1), dim3(1), 0, st, acc);
 }
 
 __global__ void k_pt2_merge(double *acc, const double *part) {
-    acc[0] += part[0];
-    acc[1] = fmin(acc[1], part[1]);
-    acc[2] += part[2];
-    acc[3] += part[3];
+    Rec a = rec_zero();
+    rec_add(a, acc);
+    rec_add(a, part);
+    rec_store(a, acc);
 }
 
 void launch_pt2_merge(hipStream_t st, double *acc, const double *part) {
@@ -180,7 +205,8 @@ void launch_pt2_records(hipStream_t st, const uint64_t *dets, const double *psi,
                        rec);
 }
 
-// out = {(int + ext)/norm, int, ext, min den}; counts[1] = |P|, counts[2] = tiny
+// out = {(int + ext)/norm, int, ext, min den};
+// counts = {pairs, |P|, tiny, sub-buckets, fingerprint sum, fingerprint XOR}
 __global__ void k_pt2_final(const double *__restrict__ acc_int, const double *__restrict__ acc_ext,
                             const double *__restrict__ stats, double *__restrict__ out, int64_t *__restrict__ counts,
                             int64_t pairs, int64_t passes) {
@@ -193,6 +219,8 @@ __global__ void k_pt2_final(const double *__restrict__ acc_int, const double *__
     counts[1] = (int64_t)acc_ext[2];
     counts[2] = (int64_t)(acc_int[3] + acc_ext[3]);
     counts[3] = passes;
+    counts[4] = (int64_t)__double_as_longlong(acc_ext[4]);
+    counts[5] = (int64_t)__double_as_longlong(acc_ext[5]);
 }
 
 void launch_pt2_final(hipStream_t st, const double *acc_int, const double *acc_ext, const double *stats,

@@ -7,12 +7,16 @@
 //      the same hash bits once per call, k_s_sub_*), so no key is probed in the global
 //      hash set of S;
 //   3. decode every pair descriptor (x XOR flipped positions), recompute H_ax exactly in
-//      FP64 from the packed integrals and accumulate w_a = sum_x H_ax psi_x in a 4096-slot
-//      LDS table (64-bit CAS on the key, FP64 add); the source determinant and psi_x
-//      come from one 32-byte record, and single excitations are queued and done last;
-//   4. compact the keys not in S to the front of the table, then for each add
-//      w_a^2 / (E - H_aa) in FP64 to the workgroup's partial sums, H_aa from the LDS
-//      table by the diagonal rule.
+//      FP64 from the packed integrals and accumulate w_a = sum_x H_ax psi_x in a 3072-slot
+//      LDS table (64-bit CAS on the key; the sum in fixed point, 64 + 32-bit integer
+//      adds, so that it does not depend on the order of the adds); the source
+//      determinant and psi_x come from one 16-byte (M <= 32) or 32-byte record, and
+//      single excitations are queued and done last;
+//   4. for the members a of S: the internal term of Eq. 13 from v_a = w_a + H_aa psi_a;
+//   5. compact the keys not in S to the front of the table, then for each form
+//      w_a^2 / (E - H_aa) in FP64, H_aa from the LDS table by the diagonal rule, and
+//      sum them exactly over the workgroup (integer limbs below the largest term), so
+//      the result of a call is reproducible to the bit.
 // A sub-bucket whose keys do not fit the table raises a flag and the host repeats the L2
 // split and the reduce with twice as many sub-buckets.
 #include "dnqs_device.h"
@@ -23,34 +27,41 @@
 namespace dnqs {
 
 // ------------------------------------------------------------------ reduce
-__device__ inline void red_block(double &s, double &mn, double &np, double &nt) {
-    __shared__ double sh[4][kRedThreads / kWave];
+// Workgroup min / counts / fingerprint (each exact in any order); result to thread 0.
+__device__ inline void red_block(double &mn, double &np, double &nt, unsigned long long &fs,
+                                 unsigned long long &fx) {
+    __shared__ double sh[3][kRedThreads / kWave];
+    __shared__ unsigned long long sf[2][kRedThreads / kWave];
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
-        s += __shfl_xor(s, o, 64);
         mn = fmin(mn, __shfl_xor(mn, o, 64));
         np += __shfl_xor(np, o, 64);
         nt += __shfl_xor(nt, o, 64);
+        fs += __shfl_xor(fs, o, 64);
+        fx ^= __shfl_xor(fx, o, 64);
     }
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     if (lane == 0) {
-        sh[0][wave] = s;
-        sh[1][wave] = mn;
-        sh[2][wave] = np;
-        sh[3][wave] = nt;
+        sh[0][wave] = mn;
+        sh[1][wave] = np;
+        sh[2][wave] = nt;
+        sf[0][wave] = fs;
+        sf[1][wave] = fx;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < (int)(blockDim.x / kWave); ++w) {
-            sh[0][0] += sh[0][w];
-            sh[1][0] = fmin(sh[1][0], sh[1][w]);
+            sh[0][0] = fmin(sh[0][0], sh[0][w]);
+            sh[1][0] += sh[1][w];
             sh[2][0] += sh[2][w];
-            sh[3][0] += sh[3][w];
+            sf[0][0] += sf[0][w];
+            sf[1][0] ^= sf[1][w];
         }
-        s = sh[0][0];
-        mn = sh[1][0];
-        np = sh[2][0];
-        nt = sh[3][0];
+        mn = sh[0][0];
+        np = sh[1][0];
+        nt = sh[2][0];
+        fs = sf[0][0];
+        fx = sf[1][0];
     }
 }
 
@@ -126,7 +137,7 @@ __global__ void k_s_sub_count(const uint64_t *__restrict__ dets, int64_t n, int 
 template <bool PACKED>
 __global__ void k_s_sub_fill(const uint64_t *__restrict__ dets, int64_t n, int sbits, int ss, uint32_t slice,
                              const int64_t *__restrict__ offs, int32_t *__restrict__ cur,
-                             uint64_t *__restrict__ skeys) {
+                             uint64_t *__restrict__ skeys, int32_t *__restrict__ sidx) {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     const uint64_t a = dets[2 * x], b = dets[2 * x + 1];
@@ -135,17 +146,18 @@ __global__ void k_s_sub_fill(const uint64_t *__restrict__ dets, int64_t n, int s
     const int64_t pos = offs[s] + atomicAdd(&cur[s], 1);
     skeys[2 * pos] = a;
     skeys[2 * pos + 1] = b;
+    sidx[pos] = (int32_t)x;
 }
 
 void launch_s_sub(hipStream_t st, const uint64_t *dets, int64_t n, int sbits, bool packed, int32_t *cnt,
-                  const int64_t *offs, uint64_t *skeys, bool fill, int ss, uint32_t slice) {
+                  const int64_t *offs, uint64_t *skeys, int32_t *sidx, bool fill, int ss, uint32_t slice) {
     if (n == 0) return;
     dim3 grid((unsigned)((n + 255) / 256)), blk(256);
     if (fill) {
         if (packed)
-            hipLaunchKernelGGL(k_s_sub_fill<true>, grid, blk, 0, st, dets, n, sbits, ss, slice, offs, cnt, skeys);
+            hipLaunchKernelGGL(k_s_sub_fill<true>, grid, blk, 0, st, dets, n, sbits, ss, slice, offs, cnt, skeys, sidx);
         else
-            hipLaunchKernelGGL(k_s_sub_fill<false>, grid, blk, 0, st, dets, n, sbits, ss, slice, offs, cnt, skeys);
+            hipLaunchKernelGGL(k_s_sub_fill<false>, grid, blk, 0, st, dets, n, sbits, ss, slice, offs, cnt, skeys, sidx);
     } else {
         if (packed)
             hipLaunchKernelGGL(k_s_sub_count<true>, grid, blk, 0, st, dets, n, sbits, ss, slice, cnt);
@@ -155,10 +167,10 @@ void launch_s_sub(hipStream_t st, const uint64_t *dets, int64_t n, int sbits, bo
 }
 
 // ------------------------------------------------------------------ reduce kernel
-// Insert (a, b) into the LDS table; returns the slot or -1 when the table is full.
 // Slot of a key in the LDS table: a 32-bit fold of the key through the lowbias32
-// integer hash (C. Wellons, hash-prospector).  Independent of the partition hash, whose
-// top bits chose the sub-bucket, and about a third of its cost.
+// integer hash (C. Wellons, hash-prospector), mapped onto the kRedTab slots by a
+// multiply-shift.  Independent of the partition hash, whose top bits chose the
+// sub-bucket.
 template <bool PACKED>
 __device__ __forceinline__ uint32_t red_slot(uint64_t a, uint64_t b) {
     uint32_t f = (uint32_t)a ^ ((uint32_t)b * 0x9e3779b1u);
@@ -168,9 +180,13 @@ __device__ __forceinline__ uint32_t red_slot(uint64_t a, uint64_t b) {
     f ^= f >> 15;
     f *= 0x846ca68bu;
     f ^= f >> 16;
-    return f & (kRedTab - 1);
+    return (uint32_t)(((uint64_t)f * (uint64_t)kRedTab) >> 32);
 }
 
+__device__ __forceinline__ uint32_t red_next(uint32_t s) { return s + 1 == (uint32_t)kRedTab ? 0u : s + 1; }
+
+// Insert (a, b) into the LDS table (linear probing); returns the slot or -1 when the
+// table is full.
 template <bool PACKED>
 __device__ __forceinline__ int red_insert(unsigned long long *ka_t, unsigned long long *kb_t, uint64_t a, uint64_t b) {
     uint32_t s = red_slot<PACKED>(a, b);
@@ -187,9 +203,168 @@ __device__ __forceinline__ int red_insert(unsigned long long *ka_t, unsigned lon
                 if (pb == kEmptyKey || pb == b) return (int)s;
             }
         }
-        s = (s + 1) & (kRedTab - 1);
+        s = red_next(s);
     }
     return -1;
+}
+
+// Slot of a key already in the table (after every insertion is done), -1 if absent.
+template <bool PACKED>
+__device__ __forceinline__ int red_find(const unsigned long long *ka_t, const unsigned long long *kb_t, uint64_t a,
+                                        uint64_t b) {
+    uint32_t s = red_slot<PACKED>(a, b);
+    for (int p = 0; p < kRedTab; ++p) {
+        if (PACKED) {
+            const unsigned long long k = ka_t[s];
+            if (k == pack_key(a, b)) return (int)s;
+            if (k == kEmptyKey) return -1;
+        } else {
+            if (ka_t[s] == a && kb_t[s] == b) return (int)s;
+            if (kb_t[s] == kEmptyKey) return -1;
+        }
+        s = red_next(s);
+    }
+    return -1;
+}
+
+// ------------------------------------------------------------------ exact sums
+// w_a is accumulated in fixed point, so that the sum does not depend on the order in
+// which lanes and waves add their terms (integer addition is associative): each term
+// t = H_ax psi_x, |t| <= 2^wexp, is cut at the grid 2^(wexp - 62 + cb) into a 64-bit
+// part and the next 30 - cb bits into a 32-bit part, where 2^cb exceeds the number of
+// pairs of the sub-bucket (so neither sum can overflow).  About 90 - 2 cb bits below
+// 2^wexp are kept: 2^(wexp-64) or finer for sub-buckets of up to 2^13 pairs, far below
+// the FP64 rounding of w_a itself.
+struct FixQ {
+    double up1, up2;    // 2^(62 - cb - wexp), 2^(30 - cb)
+    double dn1, dn2;    // inverses
+};
+
+__device__ __forceinline__ FixQ make_fixq(int wexp, int64_t npairs) {
+    int cb = 0;
+    while (cb < 30 && ((int64_t)1 << cb) <= npairs) ++cb;
+    FixQ q;
+    q.up1 = ldexp(1.0, 62 - cb - wexp);
+    q.up2 = ldexp(1.0, 30 - cb);
+    q.dn1 = ldexp(1.0, wexp + cb - 62);
+    q.dn2 = ldexp(1.0, wexp + cb - 62 - (30 - cb));
+    return q;
+}
+
+__device__ __forceinline__ void fix_split(const FixQ &q, double t, long long &hi, int &lo) {
+    const double y = t * q.up1;
+    hi = __double2ll_rz(y);
+    lo = __double2int_rz((y - (double)hi) * q.up2);
+}
+
+__device__ __forceinline__ double fix_join(const FixQ &q, long long hi, int lo) {
+    return (double)hi * q.dn1 + (double)lo * q.dn2;
+}
+
+// Exact workgroup sum of each thread's values v[0..cnt): the workgroup's largest |v|
+// fixes the scale 2^e, every value is cut into three 40-bit integer limbs below it and
+// the limbs are summed as integers (at most 2^12 values per thread group: no overflow),
+// so the result does not depend on how the values are spread over the threads.  The
+// FP64 result is the exact sum up to the limbs' 2^(e-120) grid, rounded once.  Values
+// that are not finite are summed in FP64 (their sum is inf or NaN in any order).
+// Every thread of the block must call it; the result is returned to thread 0.
+template <int K>
+__device__ inline double block_exact_sum(const double (&v)[K], int cnt) {
+    __shared__ double s_max[kRedThreads / kWave];
+    __shared__ long long s_limb[3][kRedThreads / kWave];
+    __shared__ int s_bad[kRedThreads / kWave];
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    double mx = 0.0;
+    int bad = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        if (j < cnt) {
+            if (isfinite(v[j]))
+                mx = fmax(mx, fabs(v[j]));
+            else
+                bad = 1;
+        }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, o, 64));
+        bad |= __shfl_xor(bad, o, 64);
+    }
+    if (lane == 0) {
+        s_max[wave] = mx;
+        s_bad[wave] = bad;
+    }
+    __syncthreads();
+    mx = 0.0;
+    bad = 0;
+    for (int w = 0; w < nw; ++w) {
+        mx = fmax(mx, s_max[w]);
+        bad |= s_bad[w];
+    }
+    __syncthreads();
+    if (bad) {
+        // inf / NaN present: an FP64 sum (non-finite in any order)
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j < cnt) s += v[j];
+        s = wave_sum(s);
+        if (lane == 0) s_max[wave] = s;
+        __syncthreads();
+        double t = 0.0;
+        if (threadIdx.x == 0)
+            for (int w = 0; w < nw; ++w) t += s_max[w];
+        __syncthreads();
+        return t;
+    }
+    if (mx == 0.0) return 0.0;
+    int e;
+    (void)frexp(mx, &e);  // mx < 2^e
+    const double up = ldexp(1.0, 40 - e), sh = 1099511627776.0;  // 2^40
+    long long l2 = 0, l1 = 0, l0 = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        if (j < cnt) {
+            double y = v[j] * up;  // |y| < 2^40
+            const long long a2 = __double2ll_rz(y);
+            y = (y - (double)a2) * sh;
+            const long long a1 = __double2ll_rz(y);
+            y = (y - (double)a1) * sh;
+            const long long a0 = __double2ll_rz(y);
+            l2 += a2;
+            l1 += a1;
+            l0 += a0;
+        }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        l2 += __shfl_xor(l2, o, 64);
+        l1 += __shfl_xor(l1, o, 64);
+        l0 += __shfl_xor(l0, o, 64);
+    }
+    if (lane == 0) {
+        s_limb[0][wave] = l2;
+        s_limb[1][wave] = l1;
+        s_limb[2][wave] = l0;
+    }
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+        long long L2 = 0, L1 = 0, L0 = 0;
+        for (int w = 0; w < nw; ++w) {
+            L2 += s_limb[0][w];
+            L1 += s_limb[1][w];
+            L0 += s_limb[2][w];
+        }
+        // carry the lower limbs up; the conversion is a fixed formula of the integers
+        const long long c0 = L0 / 1099511627776ll;
+        L0 -= c0 * 1099511627776ll;
+        L1 += c0;
+        const long long c1 = L1 / 1099511627776ll;
+        L1 -= c1 * 1099511627776ll;
+        L2 += c1;
+        t = ldexp((double)L2 + ((double)L1 + (double)L0 / sh) / sh, e - 40);
+    }
+    __syncthreads();
+    return t;
 }
 
 // H_aa by the diagonal rule from the LDS table, with the loops unrolled over at most
@@ -447,39 +622,136 @@ __device__ __forceinline__ PairVal single_part(const Ham &H, const SrcRec &sr, u
 
 __device__ __forceinline__ bool is_single(uint64_t d) { return ((desc_pos(d) >> 14) & 127u) == kNoPos; }
 
+// adds H_ax psi_x to w_a; hb_thr > 0: also marks a when |H_ax psi_x| >= hb_thr (the
+// heat-bath screen of Eq. 14: a key enters the external sum only if some coupling
+// reaches the threshold)
 template <bool PACKED>
 __device__ __forceinline__ bool red_add(const PairVal &pv, unsigned long long *ka_t, unsigned long long *kb_t,
-                                        double *w_t) {
+                                        long long *w_hi, int *w_lo, const FixQ &fq, double hb_thr,
+                                        uint32_t *hb_ok) {
     const int s = red_insert<PACKED>(ka_t, kb_t, pv.a, pv.b);
     if (s < 0) return false;
-    atomicAdd(&w_t[s], (pv.ph * (pv.e1 - pv.e2)) * pv.px);
+    long long hi;
+    int lo;
+    const double t = (pv.ph * (pv.e1 - pv.e2)) * pv.px;
+    fix_split(fq, t, hi, lo);
+    atomicAdd(reinterpret_cast<unsigned long long *>(&w_hi[s]), (unsigned long long)hi);  // two's complement
+    atomicAdd(&w_lo[s], lo);
+    if (hb_thr > 0.0 && fabs(t) >= hb_thr) atomicOr(&hb_ok[s >> 5], 1u << (s & 31));
     return true;
 }
 
+// H_aa of a key from the LDS diagonal table (or the global tables when it is absent).
+template <bool PACKED>
+__device__ __forceinline__ double red_haa(const Ham &H, const double *vt_s, bool lds_vt, int No, uint64_t a,
+                                          uint64_t b) {
+    if (PACKED && H.na <= kHaaOcc && H.nb <= kHaaOcc)
+        return haa_unrolled<uint32_t>(vt_s, No, H.M, H.na, H.nb, (uint32_t)a, (uint32_t)b, H.ecore);
+    if (!PACKED && lds_vt && H.na <= kHaaOcc && H.nb <= kHaaOcc)
+        return haa_unrolled<uint64_t>(vt_s, No, H.M, H.na, H.nb, a, b, H.ecore);
+    if (PACKED) {
+        const uint64_t occ = a | (b << H.M);
+        double haa = H.ecore;
+        uint64_t rest = occ;
+        while (rest) {
+            const int qo = ctz64(rest);
+            rest &= rest - 1;
+            double e = vt_s[qo];
+            const double *row = vt_s + No + qo * (qo - 1) / 2;
+            uint64_t below = occ & ((1ull << qo) - 1ull);
+            while (below) {
+                e += row[ctz64(below)];
+                below &= below - 1;
+            }
+            haa += e;
+        }
+        return haa;
+    }
+    if (lds_vt) {
+        // 128-bit keys: alpha p -> p, beta p -> M + p; every pair (p, q) of occupied
+        // spin-orbitals once, from the row of the larger index
+        double haa = H.ecore;
+        uint64_t ra = a;
+        while (ra) {
+            const int q = ctz64(ra);
+            ra &= ra - 1;
+            double e = vt_s[q];
+            const double *row = vt_s + No + q * (q - 1) / 2;
+            uint64_t below = a & ((1ull << q) - 1ull);
+            while (below) {
+                e += row[ctz64(below)];
+                below &= below - 1;
+            }
+            haa += e;
+        }
+        uint64_t rb = b;
+        while (rb) {
+            const int q = ctz64(rb);
+            rb &= rb - 1;
+            const int qs = H.M + q;
+            double e = vt_s[qs];
+            const double *row = vt_s + No + qs * (qs - 1) / 2;
+            uint64_t al = a;
+            while (al) {
+                e += row[ctz64(al)];
+                al &= al - 1;
+            }
+            uint64_t below = b & ((1ull << q) - 1ull);
+            while (below) {
+                e += row[H.M + ctz64(below)];
+                below &= below - 1;
+            }
+            haa += e;
+        }
+        return haa;
+    }
+    return h_diag(H, a, b);
+}
+
+// Per sub-bucket output part[kRedPart * sub-bucket]:
+//   [0] external sum over its keys of P (exact workgroup sum, see block_exact_sum)
+//   [1] min |E - H_aa| over those keys      [2] their number     [3] those with |E - H_aa| < 1e-8
+//   [4], [5] (bits) sum mod 2^64 and XOR of key_hash(a) over those keys (order-free
+//   fingerprint of P)
+// and, for each member a of S in the sub-bucket, int_term[index of a] =
+// (v_a - E psi_a)^2 / (E - H_aa) with v_a = w_a + H_aa psi_a (w_a: the off-diagonal
+// part of (H_SS psi)_a, summed exactly from FP64 couplings like the external w_a).
 template <bool PACKED>
 __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_t *__restrict__ rec,
                                                             const uint64_t *__restrict__ desc,
                                                             const int64_t *__restrict__ sb,
                                                             const uint64_t *__restrict__ skeys,
+                                                            const int32_t *__restrict__ sidx,
                                                             const int64_t *__restrict__ soffs, int64_t n_s,
                                                             int64_t nsb, const double *__restrict__ vt,
                                                             const double *__restrict__ energy, uint64_t sample_mask,
-                                                            PT2Export ex, double *__restrict__ part,
+                                                            int wexp, double hb_eps,
+                                                            const double *__restrict__ norm2, PT2Export ex,
+                                                            double *__restrict__ part,
+                                                            double *__restrict__ int_term,
                                                             int *__restrict__ overflow) {
     __shared__ unsigned long long ka_t[kRedTab];
     __shared__ unsigned long long kb_t[PACKED ? 1 : kRedTab];
-    __shared__ double w_t[kRedTab];
+    __shared__ long long w_hi[kRedTab];
+    __shared__ int w_lo[kRedTab];
     __shared__ uint32_t in_s[kRedTab / 32];
+    __shared__ uint32_t hb_ok[kRedTab / 32];  // heat-bath screen passed (hb_eps > 0)
     __shared__ uint64_t sq[kRedSingles];  // single excitations, deferred
     __shared__ int nsq;
     extern __shared__ double vt_s[];  // diagonal table, sized at launch (empty: global tables)
     for (int t = threadIdx.x; t < kRedTab; t += blockDim.x) {
         ka_t[t] = kEmptyKey;
         if (!PACKED) kb_t[t] = kEmptyKey;
-        w_t[t] = 0.0;
+        w_hi[t] = 0;
+        w_lo[t] = 0;
     }
-    for (int t = threadIdx.x; t < kRedTab / 32; t += blockDim.x) in_s[t] = 0u;
+    for (int t = threadIdx.x; t < kRedTab / 32; t += blockDim.x) {
+        in_s[t] = 0u;
+        hb_ok[t] = 0u;
+    }
     if (threadIdx.x == 0) nsq = 0;
+    // |H_ax psi_x| >= hb_eps ||psi||_2 (psi in any scale: the threshold is on the normalised psi)
+    const double hb_thr = hb_eps > 0.0 ? hb_eps * sqrt(norm2[0]) : 0.0;
     const int No = 2 * H.M;
     const bool lds_vt = vt != nullptr;  // else (M > 62) H_aa from the global J, K tables
     if (lds_vt)
@@ -496,6 +768,8 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
             atomicOr(&in_s[s >> 5], 1u << (s & 31));
     }
     __syncthreads();
+    const int64_t s0 = sb[blockIdx.x], s1 = sb[blockIdx.x + 1], step = blockDim.x;
+    const FixQ fq = make_fixq(wexp, s1 - s0);
     // Doubles first.  A single excitation's value sums over all occupied orbitals
     // (~3 N_e integral loads against 1-2 for a double); at ~1% of the pairs in random
     // order, handled inline they would stall about half of the waves, so they are queued
@@ -509,7 +783,6 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
     // integral loads, so that every wait is for a count of loads and never for a
     // prefetch.  Singles go to the LDS queue; if it fills up they are all redone by a
     // rescan instead.
-    const int64_t s0 = sb[blockIdx.x], s1 = sb[blockIdx.x + 1], step = blockDim.x;
     if (s1 > s0) {
         const int64_t base = s0 + threadIdx.x;
         auto ld_desc = [&](int64_t k) { return desc[min(base + k * step, s1 - 1)]; };
@@ -526,7 +799,7 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
                 if (is_single(d)) {
                     const int q = atomicAdd(&nsq, 1);
                     if (q < kRedSingles) sq[q] = d;
-                } else if (!red_add<PACKED>(pv, ka_t, kb_t, w_t)) {
+                } else if (!red_add<PACKED>(pv, ka_t, kb_t, w_hi, w_lo, fq, hb_thr, hb_ok)) {
                     lost = true;
                 }
             }
@@ -552,18 +825,34 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
             part_v += __shfl_xor(part_v, 4, 8);
             if (have && l == 0) {
                 pv.e1 += part_v;
-                if (!red_add<PACKED>(pv, ka_t, kb_t, w_t)) lost = true;
+                if (!red_add<PACKED>(pv, ka_t, kb_t, w_hi, w_lo, fq, hb_thr, hb_ok)) lost = true;
             }
         }
     } else {
         for (int64_t i = s0 + threadIdx.x; i < s1; i += step) {
             const uint64_t d = desc[i];
-            if (is_single(d) && !red_add<PACKED>(single_pair<PACKED>(H, load_src<PACKED>(rec, d), d), ka_t, kb_t, w_t))
+            if (is_single(d) &&
+                !red_add<PACKED>(single_pair<PACKED>(H, load_src<PACKED>(rec, d), d), ka_t, kb_t, w_hi, w_lo, fq, hb_thr,
+                                 hb_ok))
                 lost = true;
         }
     }
     if (lost) atomicOr(overflow, 1);
     __syncthreads();
+    const double E = energy[0];
+    // internal term of the members of S in this sub-bucket (few per sub-bucket)
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+        const uint64_t a = skeys[2 * q], b = skeys[2 * q + 1];
+        const int s = red_find<PACKED>(ka_t, kb_t, a, b);
+        if (s < 0) continue;  // lost (overflow raised): this pass is repeated
+        const int32_t xi = sidx[q];
+        const double pa = __longlong_as_double((long long)(PACKED ? rec[2 * (int64_t)xi + 1] : rec[4 * (int64_t)xi + 2]));
+        const double w = fix_join(fq, w_hi[s], w_lo[s]);
+        const double haa = red_haa<PACKED>(H, vt_s, lds_vt, No, a, b);
+        const double r = w + (haa - E) * pa;
+        const double num = r * r;
+        int_term[xi] = num != 0.0 ? num / (E - haa) : 0.0;
+    }
     // compact the keys that enter the sum (not in S, in the sample) to the front of the
     // table, so that every lane of the H_aa loop below has a key
     constexpr int kPer = kRedTab / kRedThreads;
@@ -575,8 +864,9 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
         const int t = threadIdx.x + j * kRedThreads;
         ck[j] = ka_t[t];
         cb[j] = PACKED ? 0ull : kb_t[t];
-        cw[j] = w_t[t];
+        cw[j] = fix_join(fq, w_hi[t], w_lo[t]);
         bool ok = (PACKED ? ck[j] : cb[j]) != kEmptyKey && !((in_s[t >> 5] >> (t & 31)) & 1u);
+        if (hb_thr > 0.0) ok = ok && ((hb_ok[t >> 5] >> (t & 31)) & 1u);
         if (ok && sample_mask) {
             const uint64_t a = PACKED ? (ck[j] & 0xffffffffull) : ck[j], b = PACKED ? (ck[j] >> 32) : cb[j];
             ok = !(key_hash(a, b) & sample_mask);
@@ -586,6 +876,7 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
     uint32_t n_live = 0;
     uint32_t pos = red_scan((uint32_t)__popc(live), n_live);
     __syncthreads();
+    double *w_t = reinterpret_cast<double *>(w_hi);  // the fixed-point table is read out: reuse it
 #pragma unroll
     for (int j = 0; j < kPer; ++j)
         if ((live >> j) & 1u) {
@@ -595,9 +886,15 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
             ++pos;
         }
     __syncthreads();
-    const double E = energy[0];
-    double sum = 0.0, mn = INFINITY, np = 0.0, nt = 0.0;
-    for (int t = threadIdx.x; t < (int)n_live; t += blockDim.x) {
+    double terms[kPer];
+    int nterm = 0;
+    double mn = INFINITY, np = 0.0, nt = 0.0;
+    unsigned long long fsum = 0ull, fxor = 0ull;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        terms[j] = 0.0;
+        const int t = threadIdx.x + j * kRedThreads;
+        if (t >= (int)n_live) continue;
         uint64_t a, b;
         if (PACKED) {
             const unsigned long long k = ka_t[t];
@@ -608,71 +905,16 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
             b = kb_t[t];
         }
         const double w = w_t[t];
-        double haa;
-        if (PACKED && H.na <= kHaaOcc && H.nb <= kHaaOcc) {
-            haa = haa_unrolled<uint32_t>(vt_s, No, H.M, H.na, H.nb, (uint32_t)a, (uint32_t)b, H.ecore);
-        } else if (!PACKED && lds_vt && H.na <= kHaaOcc && H.nb <= kHaaOcc) {
-            haa = haa_unrolled<uint64_t>(vt_s, No, H.M, H.na, H.nb, a, b, H.ecore);
-        } else if (PACKED) {
-            const uint64_t occ = a | (b << H.M);
-            haa = H.ecore;
-            uint64_t rest = occ;
-            while (rest) {
-                const int qo = ctz64(rest);
-                rest &= rest - 1;
-                double e = vt_s[qo];
-                const double *row = vt_s + No + qo * (qo - 1) / 2;
-                uint64_t below = occ & ((1ull << qo) - 1ull);
-                while (below) {
-                    e += row[ctz64(below)];
-                    below &= below - 1;
-                }
-                haa += e;
-            }
-        } else if (lds_vt) {
-            // 128-bit keys: alpha p -> p, beta p -> M + p; every pair (p, q) of occupied
-            // spin-orbitals once, from the row of the larger index
-            haa = H.ecore;
-            uint64_t ra = a;
-            while (ra) {
-                const int q = ctz64(ra);
-                ra &= ra - 1;
-                double e = vt_s[q];
-                const double *row = vt_s + No + q * (q - 1) / 2;
-                uint64_t below = a & ((1ull << q) - 1ull);
-                while (below) {
-                    e += row[ctz64(below)];
-                    below &= below - 1;
-                }
-                haa += e;
-            }
-            uint64_t rb = b;
-            while (rb) {
-                const int q = ctz64(rb);
-                rb &= rb - 1;
-                const int qs = H.M + q;
-                double e = vt_s[qs];
-                const double *row = vt_s + No + qs * (qs - 1) / 2;
-                uint64_t al = a;
-                while (al) {
-                    e += row[ctz64(al)];
-                    al &= al - 1;
-                }
-                uint64_t below = b & ((1ull << q) - 1ull);
-                while (below) {
-                    e += row[H.M + ctz64(below)];
-                    below &= below - 1;
-                }
-                haa += e;
-            }
-        } else {
-            haa = h_diag(H, a, b);
-        }
+        const double haa = red_haa<PACKED>(H, vt_s, lds_vt, No, a, b);
         const double den = E - haa;
         np += 1.0;
         mn = fmin(mn, fabs(den));
         if (fabs(den) < 1e-8) nt += 1.0;
-        if (w != 0.0) sum += w * w / den;
+        if (w != 0.0) terms[j] = w * w / den;
+        nterm = j + 1;
+        const uint64_t kh = key_hash(a, b);
+        fsum += kh;
+        fxor ^= kh;
         if (ex.cap > 0) {
             const unsigned long long k = atomicAdd((unsigned long long *)ex.count, 1ull);
             if ((int64_t)k < ex.cap) {
@@ -683,32 +925,40 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
             }
         }
     }
-    red_block(sum, mn, np, nt);
+    const double sum = block_exact_sum<kPer>(terms, nterm);
+    red_block(mn, np, nt, fsum, fxor);
     if (threadIdx.x == 0) {
-        part[4 * blockIdx.x + 0] = sum;
-        part[4 * blockIdx.x + 1] = mn;
-        part[4 * blockIdx.x + 2] = np;
-        part[4 * blockIdx.x + 3] = nt;
+        double *o = part + (int64_t)kRedPart * blockIdx.x;
+        o[0] = sum;
+        o[1] = mn;
+        o[2] = np;
+        o[3] = nt;
+        o[4] = __longlong_as_double((long long)fsum);
+        o[5] = __longlong_as_double((long long)fxor);
+        o[6] = 0.0;
+        o[7] = 0.0;
     }
 }
 
 void launch_pt2_reduce(hipStream_t st, const Ham &H, const uint64_t *rec, const uint64_t *desc,
-                       const int64_t *sb, int64_t nsb, const uint64_t *skeys, const int64_t *soffs, int64_t n_s,
-                       const double *vt, const double *energy, uint64_t sample_mask, const PT2Export &ex, double *part,
-                       int *overflow, bool packed) {
+                       const int64_t *sb, int64_t nsb, const uint64_t *skeys, const int32_t *sidx,
+                       const int64_t *soffs, int64_t n_s, const double *vt, const double *energy,
+                       uint64_t sample_mask, int wexp, double hb_eps, const double *norm2, const PT2Export &ex,
+                       double *part, double *int_term, int *overflow, bool packed) {
     dim3 grid((unsigned)nsb), blk(kRedThreads);
     const size_t vt_bytes = sizeof(double) * pt2_diag_table_size(H.M);
     if (packed)
-        hipLaunchKernelGGL(k_pt2_reduce<true>, grid, blk, vt_bytes, st, H, rec, desc, sb, skeys, soffs, n_s, nsb, vt,
-                           energy, sample_mask, ex, part, overflow);
+        hipLaunchKernelGGL(k_pt2_reduce<true>, grid, blk, vt_bytes, st, H, rec, desc, sb, skeys, sidx, soffs, n_s,
+                           nsb, vt, energy, sample_mask, wexp, hb_eps, norm2, ex, part, int_term, overflow);
     else if (pt2_diag_table_fits(H.M))
-        hipLaunchKernelGGL(k_pt2_reduce<false>, grid, blk, vt_bytes, st, H, rec, desc, sb, skeys, soffs, n_s,
-                           nsb, vt, energy, sample_mask, ex, part, overflow);
+        hipLaunchKernelGGL(k_pt2_reduce<false>, grid, blk, vt_bytes, st, H, rec, desc, sb, skeys, sidx, soffs, n_s,
+                           nsb, vt, energy, sample_mask, wexp, hb_eps, norm2, ex, part, int_term, overflow);
     else
-        hipLaunchKernelGGL(k_pt2_reduce<false>, grid, blk, 0, st, H, rec, desc, sb, skeys, soffs, n_s, nsb,
-                           (const double *)nullptr, energy, sample_mask, ex, part, overflow);
+        hipLaunchKernelGGL(k_pt2_reduce<false>, grid, blk, 0, st, H, rec, desc, sb, skeys, sidx, soffs, n_s, nsb,
+                           (const double *)nullptr, energy, sample_mask, wexp, hb_eps, norm2, ex, part, int_term, overflow);
 }
 
 int pt2_red_tab() { return kRedTab; }
+int pt2_red_part() { return kRedPart; }
 
 }  // namespace dnqs

@@ -82,7 +82,7 @@ def test_batched_geometry_against_oracle(dnqs, curve, setup):
     H = ham.hss_sparse(WL.M, p.h, p.eri, p.e_core, p.dets)
     o = energy.energy_and_grad(p.theta, WL.widths, p.dets, WL.M, WL.n_elec, H)
     assert abs(out[g]["E"].item() - o["E"]) <= 1e-6
-    assert P.rel_l2(out[g]["grad"].double().cpu().numpy(), o["grad"]) <= 1e-4
+    P.check_grad(out[g]["grad"].double().cpu().numpy(), o["grad"], WL.widths, 1e-4)
 
 
 def _lr(t, lr_max, lr_min, T):

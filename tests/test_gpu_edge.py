@@ -66,7 +66,7 @@ def test_edge_sector(dnqs, ctx, na, nb, nd):
     r = ctx.energy_and_grad(p.wl.widths, theta, conn)
     torch.cuda.synchronize()
     assert abs(r["E"].item() - o["E"]) <= 1e-6
-    assert P.rel_l2(r["grad"].double().cpu().numpy(), o["grad"]) <= 1e-4
+    P.check_grad(r["grad"].double().cpu().numpy(), o["grad"], p.wl.widths, 1e-4)
     E0, psi = fci.lowest_sparse(H) if H.shape[0] > 2 else fci.lowest(H.toarray())
     op = opt2.pt2(p.wl.M, p.h, p.eri, p.e_core, p.dets, psi, H @ psi, o_diag, E0)
     with np.errstate(divide="ignore"):
