@@ -193,6 +193,64 @@ def bench_sweep(args, dnqs, synth, torch):
     print(json.dumps(line))
 
 
+def bench_out_scale(args, dnqs, synth, torch):
+    """Mixed-precision error and speed against the scale of the output layer (the network
+    leaves its near-zero initialisation as it trains): per out_scale, energy+gradient in
+    FP32, MIXED and SPLIT_BF16 on the same S, |E - E_FP32|, the gradient's relative L2
+    error, and the PT2 correction from each form's psi and E (normalised dE of Eq. 13)."""
+    wl = synth.WORKLOADS[args.workload]
+    scales = [float(v) for v in args.out_scale_sweep.split(",")]
+    p0 = synth.make_problem(wl, n_dets=args.n_dets, out_scale=scales[0])
+    ctx = dnqs.Context(0)
+    ctx.autotune(True)
+    ctx.set_integrals(p0.h, p0.eri, p0.e_core, wl.n_alpha, wl.n_beta)
+    dets = dnqs.dets_to_device(p0.dets)
+    conn = ctx.build_connections(dets, validate=False)
+    n = p0.dets.shape[0]
+    rows = []
+    ctx.timing(True)
+    for sc in scales:
+        p = synth.make_problem(wl, n_dets=args.n_dets, out_scale=sc)
+        assert (p.dets == p0.dets).all()
+        theta = torch.from_numpy(p.theta).cuda()
+        row = {"out_scale": sc}
+        ref = None
+        for name, attr in PRECISIONS.items():
+            pr = getattr(dnqs, attr)
+            r = ctx.energy_and_grad(wl.widths, theta, conn, precision=pr)   # tunes new shapes
+            r = ctx.energy_and_grad(wl.widths, theta, conn, precision=pr)
+            torch.cuda.synchronize()
+            ctx.timing_reset()
+            for _ in range(max(args.steps, 3)):
+                r = ctx.energy_and_grad(wl.widths, theta, conn, precision=pr)
+            torch.cuda.synchronize()
+            t = ctx.timing_get("egrad")[0] / max(args.steps, 3)
+            out = ctx.pt2(conn, r["logabs"], r["sign"], r["E"])
+            E, g, dE = r["E"].item(), r["grad"].double(), float(out["out"][0].item())
+            if ref is None:
+                ref = (t, E, g, dE)
+            row[name] = {"ms": t, "speedup_vs_fp32": ref[0] / t, "E": E, "abs_E_minus_E_fp32": abs(E - ref[1]),
+                         "grad_rel_l2_vs_fp32": float(torch.linalg.vector_norm(g - ref[2]) /
+                                                      torch.linalg.vector_norm(ref[2])),
+                         "dE_pt2": dE, "abs_dE_pt2_minus_fp32": abs(dE - ref[3])}
+        rows.append(row)
+        print(f"[bench] out_scale {sc}: {json.dumps(row)}", file=sys.stderr, flush=True)
+    ctx.timing(False)
+    conn.free()
+    line = {
+        "metric": "mixed-precision error and speed against the output-layer scale",
+        "value": rows[0]["mixed"]["speedup_vs_fp32"], "unit": "x vs FP32", "n_gpus": 1,
+        "steps": max(args.steps, 3), "warmup": 2, "ms_per_step": rows[0]["mixed"]["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3+f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "n_dets": n, "widths": list(wl.widths)},
+        "note": "dE_pt2 at a random-init network's psi: E lies inside the H_aa spread, so the "
+                "PT2 values compare the forms, they are not converged corrections",
+        "out_scale_sweep": rows,
+    }
+    print(json.dumps(line))
+
+
 def bench_curve(args, dnqs, synth, torch):
     """One optimisation step over G geometries: G sequential energy_and_grad calls, one
     batched call, and a replayed HIP graph of the batched step + AdamW (same stream)."""
@@ -256,11 +314,11 @@ def bench_curve(args, dnqs, synth, torch):
 
 # HBM bytes per launch of a kernel from two rocprofv3 --pmc passes (FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0, the factors a 1 GiB device copy gives), valid only for the kernel
-# source they were taken on (profiles/pt2_m28_s1e5_hbm_counters.md).
+# source they were taken on (profiles/pt2_hss_m28_s1e5_hbm_counters.md).
 MEASURED_TRAFFIC = {
     ("k_pt2_reduce", "m28_7a7b_s100k"): ("paper_2601_21310_amd/csrc/k_pt2_reduce.hip",
-                                          "866a68f21161680241ac03a3bdb1291370fff1f187f1dffff41916bf2c8d4426",
-                                          24871166043.5),
+                                          "1fa07454529747570c205b9019f564941e780bda4e363d09b75f1529cf34a0d7",
+                                          24992433832.0),
 }
 
 
@@ -300,6 +358,10 @@ def main():
                     help="instead of the headline run: energy+gradient over a synthetic dissociation curve of "
                          "this many geometries (M=20, 6a+6b, |S| log-uniform in [2^10, 2^16]), sequential vs "
                          "batched vs a replayed HIP graph of the batched step with AdamW")
+    ap.add_argument("--out-scale-sweep", default="",
+                    help="instead of the headline run: comma-separated output-layer scales (e.g. "
+                         "1e-3,1e-2,1e-1,1): energy+gradient error and speed of each precision form, and the "
+                         "PT2 correction from each form's psi")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a device copy of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -329,6 +391,8 @@ def main():
         return bench_curve(args, dnqs, synth, torch)
     if args.sweep:
         return bench_sweep(args, dnqs, synth, torch)
+    if args.out_scale_sweep:
+        return bench_out_scale(args, dnqs, synth, torch)
 
     wl = synth.WORKLOADS[args.workload]
     print(f"[bench] building inputs for {wl.name}", file=sys.stderr, flush=True)
