@@ -190,6 +190,21 @@ void dnqs_conn_free(dnqs_conn *conn);
 dnqs_status dnqs_amplitudes(dnqs_ctx *ctx, int slot, const dnqs_net *net, const float *theta, const uint64_t *dets,
                             int64_t n, int precision, double *log_abs, int8_t *sign);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): dnqs_amplitudes with every
+ * workspace (the activations h_1 .. h_{L-1}, the output layer, the BF16 weight planes)
+ * carved from a fixed 64 MiB scratch region that the library holds on each device for
+ * the life of the process, so that the call allocates nothing.  Same arguments, same
+ * kernels and the same results bit for bit as dnqs_amplitudes.  The region bounds n:
+ * about 64 MiB / (4 (d_1 + ... + d_L)) configurations (7,000 for the 56-512-512-512-784
+ * network); a larger n gives DNQS_ECAPACITY before any launch, outputs untouched.
+ * Every context on a device shares that device's region and it keeps the last call's
+ * contents (each workspace is written in full before it is read): calls that overlap
+ * on one device, from any context or stream, race and must be serialised by the
+ * caller.  No autotuning and no timing during the call. */
+dnqs_status dnqs_amplitudes_noalloc(dnqs_ctx *ctx, int slot, const dnqs_net *net, const float *theta,
+                                    const uint64_t *dets, int64_t n, int precision, double *log_abs, int8_t *sign);
+
 /* ------------------------------------------------------------------ energy and gradient
  * One variational step's worth of work on S = conn's determinants (Eqs. 11-12):
  *   psi_x = sign_x exp(log|psi_x| - l_max)                (global scale removed)

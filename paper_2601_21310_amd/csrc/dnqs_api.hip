@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -86,6 +87,32 @@ static void dev_free(const DevAlloc &a, void *p) {
         a.release(p, a.user);
 }
 
+// Scratch region of the allocation-free entry point (dnqs_amplitudes_noalloc): a
+// file-scope device array, one copy per device for the life of the process.  Host code
+// never passes the array's name to a kernel or a copy: its device address on each
+// device is looked up once (hipGetSymbolAddress, at the first dnqs_create on that
+// device, with the device current) and only that address is used.
+constexpr size_t kNoAllocScratch = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+static void *g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+// Device address of the scratch region on `device` (the current device), looked up on
+// first use.
+static hipError_t scratch_address(int device, void **out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
 // Concatenated layout of a batch of problems (built once per set of conns).
 struct BatchPlan {
     bool valid = false;
@@ -120,6 +147,11 @@ struct BatchPlan {
 struct dnqs_ctx {
     int device = 0;
     DevAlloc alloc;
+    // fixed scratch region: while arena is set, workspaces are carved from it in order
+    // (the allocation-free entry point); nothing is allocated
+    void *scratch = nullptr;  // this device's scratch region (its device address)
+    char *arena = nullptr;
+    size_t arena_size = 0, arena_used = 0;
     hipStream_t stream = nullptr;
     std::string err;
     Slot slots[DNQS_MAX_SLOTS];
@@ -202,6 +234,15 @@ dnqs_status fail(dnqs_ctx *ctx, dnqs_status s, const char *fmt, ...) {
 // Workspace buffer `name` of at least `bytes` bytes (grown, never shrunk).
 dnqs_status ws_get(dnqs_ctx *ctx, const std::string &name, size_t bytes, void **out) {
     if (bytes == 0) bytes = 256;
+    if (ctx->arena) {
+        const size_t want = (bytes + 255) & ~(size_t)255;
+        if (ctx->arena_used + want > ctx->arena_size)
+            return fail(ctx, DNQS_ECAPACITY, "workspace '%s' does not fit the %zu-byte scratch region", name.c_str(),
+                        ctx->arena_size);
+        *out = ctx->arena + ctx->arena_used;
+        ctx->arena_used += want;
+        return DNQS_OK;
+    }
     Buf &b = ctx->ws[name];
     if (b.bytes < bytes) {
         if (b.p) {
@@ -257,7 +298,7 @@ struct Timer {
     const char *fam;
     hipEvent_t a = nullptr;
     Timer(dnqs_ctx *c, const char *f) : ctx(c), fam(f) {
-        if (ctx->timing) {
+        if (ctx->timing && !ctx->arena) {
             a = ev_take(ctx);
             if (a) (void)hipEventRecord(a, ctx->stream);
         }
@@ -387,7 +428,7 @@ dnqs_status tuned_launch(dnqs_ctx *ctx, const TuneKey &key, const std::vector<Ge
     if (!ts) ts = ctx->stream;
     auto it = ctx->tuned.find(key);
     if (it != ctx->tuned.end()) return launch(it->second);
-    if (!ctx->autotune || ctx->capturing || cands.size() < 2) return launch(cands[0]);
+    if (!ctx->autotune || ctx->capturing || ctx->arena || cands.size() < 2) return launch(cands[0]);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(ctx, hipEventCreate(&e0));
     HIPCHK(ctx, hipEventCreate(&e1));
@@ -1066,8 +1107,14 @@ dnqs_status dnqs_create(dnqs_ctx **out, int device, void *stream, void *(*alloc)
         g_create_error = std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950";
         return DNQS_EINVAL;
     }
+    void *scr = nullptr;
+    if (scratch_address(device, &scr) != hipSuccess) {
+        g_create_error = "hipGetSymbolAddress of the scratch region failed";
+        return DNQS_EHIP;
+    }
     dnqs_ctx *c = new dnqs_ctx();
     c->device = device;
+    c->scratch = scr;
     c->stream = (hipStream_t)stream;
     c->alloc.alloc = alloc;
     c->alloc.release = release;
@@ -1457,6 +1504,43 @@ dnqs_status dnqs_amplitudes(dnqs_ctx *ctx, int slot, const dnqs_net *net, const 
     TRY(set_device(ctx));
     Timer tm(ctx, "amp");
     return forward(ctx, sl, nv, theta, dets, n, precision, false, log_abs, sign, nullptr);
+}
+
+dnqs_status dnqs_amplitudes_noalloc(dnqs_ctx *ctx, int slot, const dnqs_net *net, const float *theta,
+                                    const uint64_t *dets, int64_t n, int precision, double *log_abs, int8_t *sign) {
+    if (!ctx) return DNQS_EINVAL;
+    TRY(check_slot(ctx, slot));
+    const Slot &sl = ctx->slots[slot];
+    NetView nv;
+    TRY(net_view(ctx, net, sl.M, sl.na, sl.nb, &nv));
+    if (!theta || !dets || !log_abs || !sign) return fail(ctx, DNQS_EINVAL, "NULL pointer argument");
+    if (n < 1 || n >= (int64_t)1 << 31) return fail(ctx, DNQS_EINVAL, "n out of range");
+    if (orb_lu_group(sl.na + sl.nb) == 0) return fail(ctx, DNQS_EINVAL, "N_e > 32 is not supported");
+    if (!precision_ok(precision)) return fail(ctx, DNQS_EINVAL, "precision %d not supported", precision);
+    if (!ctx->scratch) return fail(ctx, DNQS_ESTATE, "no scratch region on this device");
+    // the workspaces forward() takes without a gradient: h_1 .. h_{L-1}, the output layer,
+    // and the BF16 weight planes of each split-BF16 GEMM, each rounded to 256 bytes
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    size_t per_row = 0, fixed = 0;
+    for (int l = 1; l <= nv.L; ++l) per_row += (size_t)nv.w[l] * sizeof(float);
+    for (int l = 2; l <= nv.L; ++l)
+        if (gemm_engine(precision, l == nv.L) == 1) fixed += al((size_t)nv.w[l - 1] * nv.w[l] * 2 * sizeof(uint16_t));
+    size_t need = fixed;
+    for (int l = 1; l <= nv.L; ++l) need += al((size_t)n * nv.w[l] * sizeof(float));
+    if (need > kNoAllocScratch) {
+        const long long maxn = fixed < kNoAllocScratch ? (long long)((kNoAllocScratch - fixed) / per_row) : 0;
+        return fail(ctx, DNQS_ECAPACITY,
+                    "%lld configurations need %zu bytes of scratch; the region holds %zu (at most about %lld "
+                    "configurations of this network per call)",
+                    (long long)n, need, kNoAllocScratch, maxn);
+    }
+    TRY(set_device(ctx));
+    ctx->arena = (char *)ctx->scratch;
+    ctx->arena_size = kNoAllocScratch;
+    ctx->arena_used = 0;
+    const dnqs_status st = forward(ctx, sl, nv, theta, dets, n, precision, false, log_abs, sign, nullptr);
+    ctx->arena = nullptr;
+    return st;
 }
 
 dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, const float *theta,
