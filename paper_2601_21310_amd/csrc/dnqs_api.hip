@@ -2057,160 +2057,226 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
         }
         budget = (int64_t)(fr / 2) + held;
     }
-    int ss = 0;
-    while (ss < 16 && (double)(pairs >> ss) * 16.0 > (double)budget) ++ss;
-    const int64_t slice_pairs = std::max<int64_t>(1, pairs >> ss);
-    // sub-buckets of ~6000 pairs: ~2k unique keys at the measured 3.4 pairs per key,
-    // half of the 4096-slot LDS table
-    const int64_t nsb_target = std::max<int64_t>(1, slice_pairs / 6000);
-    int s1 = 0;
-    // K1 <= 512: an L1 round of 8192 descriptors then holds ~16 per bucket (one 128-byte
-    // line per run), and 2^19 sub-buckets leave K2 <= 1024 for the staged L2 pass
-    while (((int64_t)1 << s1) < nsb_target && (1 << s1) < std::min(512, pt2_max_k1())) ++s1;
-    int s2 = 0;
-    while (((int64_t)1 << (s1 + s2)) < nsb_target && (1 << s2) < pt2_max_k2()) ++s2;
-    const int K1 = 1 << s1;
-    const int64_t nwg = pt2_l1_groups(n);
-    uint32_t *c1 = nullptr;
-    int32_t *c1t = nullptr;
-    int64_t *offs1 = nullptr, *bsum = nullptr, *tot = nullptr, *bstart_d = nullptr, *ex_save = nullptr;
-    TRY(ws_t(ctx, "pt2_c1", (size_t)nwg * K1, &c1));
-    TRY(ws_t(ctx, "pt2_c1t", (size_t)nwg * K1, &c1t));
-    TRY(ws_t(ctx, "pt2_offs1", (size_t)nwg * K1, &offs1));
-    TRY(ws_t(ctx, "pt2_bsum", (size_t)scan_blocks(nwg * K1) + 1, &bsum));
-    TRY(ws_t(ctx, "pt2_tot", 2, &tot));
-    TRY(ws_t(ctx, "pt2_bstart", (size_t)K1 + 1, &bstart_d));
-    TRY(ws_t(ctx, "pt2_exsave", 1, &ex_save));
-    if (o.export_cap > 0) HIPCHK(ctx, hipMemsetAsync(o.export_count, 0, sizeof(int64_t), st));
+    int ss_mem = 0;
+    while (ss_mem < 16 && (double)(pairs >> ss_mem) * 16.0 > (double)budget) ++ss_mem;
     int64_t nsb_used = 0;
-    for (uint32_t slice = 0; slice < (1u << ss); ++slice) {
-        Timer t1(ctx, "pt2_l1");
-        launch_pt2_l1(st, H, conn->dets, n, psi, s1, nwg, c1, nullptr, nullptr, false, packed, ss, slice);
-        CHECK_LAUNCH(ctx);
-        launch_transpose_u32(st, c1, nwg, K1, c1t);
-        launch_exclusive_scan(st, c1t, nwg * K1, offs1, bsum, tot);
-        CHECK_LAUNCH(ctx);
-        int64_t total1 = 0;
-        HIPCHK(ctx, hipMemcpyAsync(&total1, tot, sizeof total1, hipMemcpyDeviceToHost, st));
-        HIPCHK(ctx, hipStreamSynchronize(st));
-        uint64_t *desc1 = nullptr;
-        TRY(ws_t(ctx, "pt2_desc1", (size_t)std::max<int64_t>(total1, 1), &desc1));
-        Timer t1f(ctx, "pt2_l1_fill");
-        launch_pt2_l1(st, H, conn->dets, n, psi, s1, nwg, nullptr, offs1, desc1, true, packed, ss, slice);
-        CHECK_LAUNCH(ctx);
-        t1f.stop();
-        t1.stop();
-        launch_gather_starts(st, offs1, K1, nwg, tot, bstart_d);
-        CHECK_LAUNCH(ctx);
-        std::vector<int64_t> bstart(K1 + 1);
-        HIPCHK(ctx, hipMemcpyAsync(bstart.data(), bstart_d, sizeof(int64_t) * (K1 + 1), hipMemcpyDeviceToHost, st));
-        if (o.export_cap > 0)
-            HIPCHK(ctx, hipMemcpyAsync(ex_save, o.export_count, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
-        HIPCHK(ctx, hipStreamSynchronize(st));
-        for (int attempt = 0;; ++attempt) {
-            const int K2 = 1 << s2;
-            const uint64_t *desc = desc1;
-            const int64_t *sb = bstart_d;
-            int64_t nsb = K1;
+    // The key space is cut into 2^ss slices when the descriptors of all pairs would not fit
+    // the memory budget; a slice whose sub-buckets still overflow at the largest sub-bucket
+    // count (few pairs per key: many keys per sub-bucket) restarts the whole sum with twice
+    // as many slices, each slice then holding half the keys.
+    for (int ss = ss_mem;; ++ss) {
+        bool more_slices = false;
+        launch_pt2_init_acc(st, acc + 8);
+        if (o.export_cap > 0) HIPCHK(ctx, hipMemsetAsync(o.export_count, 0, sizeof(int64_t), st));
+        nsb_used = 0;
+        const int64_t slice_pairs = std::max<int64_t>(1, pairs >> ss);
+        // sub-buckets of ~6000 pairs: ~1.8k unique keys at the 3.4 pairs per key of the
+        // benchmark, 0.55 of the 3072-slot LDS table (fewer pairs per key: the overflow
+        // retries below)
+        const int64_t nsb_target = std::max<int64_t>(1, slice_pairs / 6000);
+        int s1 = 0;
+        // K1 <= 512: an L1 round of 8192 descriptors then holds ~16 per bucket (one 128-byte
+        // line per run), and 2^19 sub-buckets leave K2 <= 1024 for the staged L2 pass
+        while (((int64_t)1 << s1) < nsb_target && (1 << s1) < std::min(512, pt2_max_k1())) ++s1;
+        int s2 = 0;
+        while (((int64_t)1 << (s1 + s2)) < nsb_target && (1 << s2) < pt2_max_k2()) ++s2;
+        const int K1 = 1 << s1;
+        const int64_t nwg = pt2_l1_groups(n);
+        uint32_t *c1 = nullptr;
+        int32_t *c1t = nullptr;
+        int64_t *offs1 = nullptr, *bsum = nullptr, *tot = nullptr, *bstart_d = nullptr, *ex_save = nullptr;
+        TRY(ws_t(ctx, "pt2_c1", (size_t)nwg * K1, &c1));
+        TRY(ws_t(ctx, "pt2_c1t", (size_t)nwg * K1, &c1t));
+        TRY(ws_t(ctx, "pt2_offs1", (size_t)nwg * K1, &offs1));
+        TRY(ws_t(ctx, "pt2_bsum", (size_t)scan_blocks(nwg * K1) + 1, &bsum));
+        TRY(ws_t(ctx, "pt2_tot", 2, &tot));
+        TRY(ws_t(ctx, "pt2_bstart", (size_t)K1 + 1, &bstart_d));
+        TRY(ws_t(ctx, "pt2_exsave", 1, &ex_save));
+        // L1 without a count pass when the L2 pass follows (s2 > 0): every bucket gets a region
+        // of fixed capacity, the expected share of the slice's pairs plus a margin far above
+        // the spread of a hash partition, and the fill appends each round's run at the
+        // region's cursor.  The order of descriptors inside a bucket then depends on timing,
+        // which no result does (every sum of the reduce is exact).  A region that would
+        // overflow sends the slice through the counted pass instead.
+        uint64_t *cur1_d = nullptr;
+        int *ovf1_d = nullptr;
+        TRY(ws_t(ctx, "pt2_cur1", (size_t)K1, &cur1_d));
+        TRY(ws_t(ctx, "pt2_ovf1", 1, &ovf1_d));
+        for (uint32_t slice = 0; slice < (1u << ss); ++slice) {
+            Timer t1(ctx, "pt2_l1");
+            uint64_t *desc1 = nullptr;
+            int64_t total1 = 0, cap1 = 0;
+            std::vector<int64_t> bstart(K1 + 1), bsize(K1);
+            bool fused = false;
             if (s2 > 0) {
-                const int64_t CH = 65536;
-                std::vector<PT2Chunk> chunks;
-                std::vector<int64_t> bcb0(K1), bnc(K1);
-                for (int b = 0; b < K1; ++b) {
-                    const int64_t size = bstart[b + 1] - bstart[b];
-                    const int64_t nc = (size + CH - 1) / CH;
-                    bcb0[b] = (int64_t)chunks.size();
-                    bnc[b] = nc;
-                    for (int64_t c = 0; c < nc; ++c)
-                        chunks.push_back({bstart[b] + c * CH, std::min(CH, size - c * CH), bcb0[b], nc});
-                }
-                const int64_t nchunk = (int64_t)chunks.size();
-                PT2Chunk *chunks_d = nullptr;
-                int64_t *bcb0_d = nullptr, *bnc_d = nullptr, *offs2 = nullptr, *bsum2 = nullptr, *sb_d = nullptr;
-                uint32_t *c2 = nullptr;
-                int32_t *c2t = nullptr;
-                uint64_t *desc2 = nullptr;
-                TRY(ws_t(ctx, "pt2_chunks", (size_t)std::max<int64_t>(nchunk, 1), &chunks_d));
-                TRY(ws_t(ctx, "pt2_bcb0", (size_t)K1, &bcb0_d));
-                TRY(ws_t(ctx, "pt2_bnc", (size_t)K1, &bnc_d));
-                TRY(ws_t(ctx, "pt2_c2", (size_t)std::max<int64_t>(nchunk * K2, 1), &c2));
-                TRY(ws_t(ctx, "pt2_c2t", (size_t)std::max<int64_t>(nchunk * K2, 1), &c2t));
-                TRY(ws_t(ctx, "pt2_offs2", (size_t)std::max<int64_t>(nchunk * K2, 1), &offs2));
-                TRY(ws_t(ctx, "pt2_bsum2", (size_t)scan_blocks(nchunk * K2) + 1, &bsum2));
-                TRY(ws_t(ctx, "pt2_sb", (size_t)K1 * K2 + 1, &sb_d));
-                TRY(ws_t(ctx, "pt2_desc2", (size_t)std::max<int64_t>(total1, 1), &desc2));
-                if (nchunk > 0)
-                    HIPCHK(ctx, hipMemcpyAsync(chunks_d, chunks.data(), sizeof(PT2Chunk) * nchunk,
-                                               hipMemcpyHostToDevice, st));
-                HIPCHK(ctx, hipMemcpyAsync(bcb0_d, bcb0.data(), sizeof(int64_t) * K1, hipMemcpyHostToDevice, st));
-                HIPCHK(ctx, hipMemcpyAsync(bnc_d, bnc.data(), sizeof(int64_t) * K1, hipMemcpyHostToDevice, st));
-                Timer t2(ctx, "pt2_l2");
-                if (nchunk > 0) {
-                    launch_pt2_l2(st, desc1, chunks_d, nchunk, s2, c2, nullptr, nullptr, false);
-                    CHECK_LAUNCH(ctx);
-                    launch_l2_transpose(st, c2, chunks_d, nchunk, K2, c2t);
-                    launch_exclusive_scan(st, c2t, nchunk * K2, offs2, bsum2, tot + 1);
-                    CHECK_LAUNCH(ctx);
-                    launch_pt2_l2(st, desc1, chunks_d, nchunk, s2, nullptr, offs2, desc2, true);
-                    CHECK_LAUNCH(ctx);
-                }
-                launch_sub_starts(st, offs2, bstart_d, bcb0_d, bnc_d, K1, K2, sb_d);
+                cap1 = (int64_t)((double)slice_pairs / K1 * 1.03) + 65536;
+                cap1 = (cap1 + 15) / 16 * 16;
+                TRY(ws_t(ctx, "pt2_desc1", (size_t)K1 * cap1, &desc1));
+                launch_fill_u64(st, cur1_d, (size_t)K1, 0ull);
+                HIPCHK(ctx, hipMemsetAsync(ovf1_d, 0, sizeof(int), st));
+                Timer t1f(ctx, "pt2_l1_fill");
+                launch_pt2_l1(st, H, conn->dets, n, psi, s1, nwg, nullptr, nullptr, desc1, true, packed, ss, slice,
+                              cur1_d, cap1, ovf1_d);
                 CHECK_LAUNCH(ctx);
-                t2.stop();
-                // the host vectors are read by the copies above: wait before they go out of scope
+                t1f.stop();
+                int ovf1 = 0;
+                std::vector<uint64_t> cur1(K1);
+                HIPCHK(ctx, hipMemcpyAsync(cur1.data(), cur1_d, sizeof(uint64_t) * K1, hipMemcpyDeviceToHost, st));
+                HIPCHK(ctx, hipMemcpyAsync(&ovf1, ovf1_d, sizeof(int), hipMemcpyDeviceToHost, st));
                 HIPCHK(ctx, hipStreamSynchronize(st));
-                desc = desc2;
-                sb = sb_d;
-                nsb = (int64_t)K1 * K2;
+                if (!ovf1) {
+                    fused = true;
+                    // bstart: the regions in desc1 (where the L2 chunks read); the device
+                    // copy holds the compact starts instead, the bucket offsets in the L2
+                    // pass's output, where k_sub_starts reads them
+                    std::vector<int64_t> compact(K1 + 1, 0);
+                    for (int b = 0; b < K1; ++b) {
+                        bstart[b] = (int64_t)b * cap1;
+                        bsize[b] = (int64_t)cur1[b];
+                        compact[b + 1] = compact[b] + bsize[b];
+                    }
+                    total1 = compact[K1];
+                    bstart[K1] = (int64_t)K1 * cap1;
+                    HIPCHK(ctx, hipMemcpyAsync(bstart_d, compact.data(), sizeof(int64_t) * (K1 + 1),
+                                               hipMemcpyHostToDevice, st));
+                    HIPCHK(ctx, hipStreamSynchronize(st));
+                }
             }
-            // the members of S in this slice, grouped by sub-bucket (same hash bits as the pairs)
-            int32_t *scnt = nullptr;
-            int64_t *soffs = nullptr, *sbsum = nullptr;
-            uint64_t *skeys = nullptr;
-            int32_t *sidx = nullptr;
-            TRY(ws_t(ctx, "pt2_sidx", (size_t)std::max<int64_t>(n, 1), &sidx));
-            TRY(ws_t(ctx, "pt2_scnt", (size_t)nsb, &scnt));
-            TRY(ws_t(ctx, "pt2_soffs", (size_t)nsb, &soffs));
-            TRY(ws_t(ctx, "pt2_sbsum", (size_t)scan_blocks(nsb) + 1, &sbsum));
-            TRY(ws_t(ctx, "pt2_skeys", (size_t)2 * std::max<int64_t>(n, 1), &skeys));
-            const int sbits = s1 + (s2 > 0 ? s2 : 0);
-            HIPCHK(ctx, hipMemsetAsync(scnt, 0, sizeof(int32_t) * nsb, st));
-            launch_s_sub(st, conn->dets, n, sbits, packed, scnt, nullptr, nullptr, nullptr, false, ss, slice);
-            CHECK_LAUNCH(ctx);
-            launch_exclusive_scan(st, scnt, nsb, soffs, sbsum, tot + 1);
-            CHECK_LAUNCH(ctx);
-            int64_t n_s = 0;  // members of S in this slice
-            HIPCHK(ctx, hipMemcpyAsync(&n_s, tot + 1, sizeof n_s, hipMemcpyDeviceToHost, st));
-            HIPCHK(ctx, hipMemsetAsync(scnt, 0, sizeof(int32_t) * nsb, st));
-            launch_s_sub(st, conn->dets, n, sbits, packed, scnt, soffs, skeys, sidx, true, ss, slice);
-            CHECK_LAUNCH(ctx);
-            HIPCHK(ctx, hipStreamSynchronize(st));
-            double *part_r = nullptr;
-            TRY(ws_t(ctx, "pt2_part_r", (size_t)nsb * pt2_red_part(), &part_r));
-            launch_pt2_init_acc(st, acc + 16);
-            if (o.export_cap > 0)
-                HIPCHK(ctx, hipMemcpyAsync(o.export_count, ex_save, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
-            HIPCHK(ctx, hipMemsetAsync(overflow, 0, sizeof(int), st));
-            Timer tr(ctx, "pt2_reduce");
-            launch_pt2_reduce(st, H, rec, desc, sb, nsb, skeys, sidx, soffs, n_s, vt, energy, o.sample_mask,
-                              sl.wexp, o.eps_hb, stats, ex, part_r, int_term, overflow, packed);
-            CHECK_LAUNCH(ctx);
-            tr.stop();
-            launch_pt2_accumulate(st, part_r, nsb, acc + 16, part);
-            CHECK_LAUNCH(ctx);
-            int ov = 0;
-            HIPCHK(ctx, hipMemcpyAsync(&ov, overflow, sizeof ov, hipMemcpyDeviceToHost, st));
-            HIPCHK(ctx, hipStreamSynchronize(st));
-            if (!ov) {
-                launch_pt2_merge(st, acc + 8, acc + 16);
+            if (!fused) {
+                launch_pt2_l1(st, H, conn->dets, n, psi, s1, nwg, c1, nullptr, nullptr, false, packed, ss, slice);
                 CHECK_LAUNCH(ctx);
-                nsb_used += nsb;
-                break;
+                launch_transpose_u32(st, c1, nwg, K1, c1t);
+                launch_exclusive_scan(st, c1t, nwg * K1, offs1, bsum, tot);
+                CHECK_LAUNCH(ctx);
+                HIPCHK(ctx, hipMemcpyAsync(&total1, tot, sizeof total1, hipMemcpyDeviceToHost, st));
+                HIPCHK(ctx, hipStreamSynchronize(st));
+                TRY(ws_t(ctx, "pt2_desc1", (size_t)std::max<int64_t>(total1, 1), &desc1));
+                Timer t1f(ctx, "pt2_l1_fill");
+                launch_pt2_l1(st, H, conn->dets, n, psi, s1, nwg, nullptr, offs1, desc1, true, packed, ss, slice);
+                CHECK_LAUNCH(ctx);
+                t1f.stop();
+                launch_gather_starts(st, offs1, K1, nwg, tot, bstart_d);
+                CHECK_LAUNCH(ctx);
+                HIPCHK(ctx, hipMemcpyAsync(bstart.data(), bstart_d, sizeof(int64_t) * (K1 + 1), hipMemcpyDeviceToHost,
+                                           st));
+                HIPCHK(ctx, hipStreamSynchronize(st));
+                for (int b = 0; b < K1; ++b) bsize[b] = bstart[b + 1] - bstart[b];
             }
-            if ((1 << s2) >= pt2_max_k2() || attempt > 8)
-                return fail(ctx, DNQS_ECAPACITY, "PT2: a sub-bucket holds more than %d unique keys", pt2_red_tab());
-            ++s2;
+            t1.stop();
+            if (o.export_cap > 0)
+                HIPCHK(ctx, hipMemcpyAsync(ex_save, o.export_count, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+            HIPCHK(ctx, hipStreamSynchronize(st));
+            for (int attempt = 0;; ++attempt) {
+                const int K2 = 1 << s2;
+                const uint64_t *desc = desc1;
+                const int64_t *sb = bstart_d;
+                int64_t nsb = K1;
+                if (s2 > 0) {
+                    const int64_t CH = 65536;
+                    std::vector<PT2Chunk> chunks;
+                    std::vector<int64_t> bcb0(K1), bnc(K1);
+                    for (int b = 0; b < K1; ++b) {
+                        const int64_t size = bsize[b];
+                        const int64_t nc = (size + CH - 1) / CH;
+                        bcb0[b] = (int64_t)chunks.size();
+                        bnc[b] = nc;
+                        for (int64_t c = 0; c < nc; ++c)
+                            chunks.push_back({bstart[b] + c * CH, std::min(CH, size - c * CH), bcb0[b], nc});
+                    }
+                    const int64_t nchunk = (int64_t)chunks.size();
+                    PT2Chunk *chunks_d = nullptr;
+                    int64_t *bcb0_d = nullptr, *bnc_d = nullptr, *offs2 = nullptr, *bsum2 = nullptr, *sb_d = nullptr;
+                    uint32_t *c2 = nullptr;
+                    int32_t *c2t = nullptr;
+                    uint64_t *desc2 = nullptr;
+                    TRY(ws_t(ctx, "pt2_chunks", (size_t)std::max<int64_t>(nchunk, 1), &chunks_d));
+                    TRY(ws_t(ctx, "pt2_bcb0", (size_t)K1, &bcb0_d));
+                    TRY(ws_t(ctx, "pt2_bnc", (size_t)K1, &bnc_d));
+                    TRY(ws_t(ctx, "pt2_c2", (size_t)std::max<int64_t>(nchunk * K2, 1), &c2));
+                    TRY(ws_t(ctx, "pt2_c2t", (size_t)std::max<int64_t>(nchunk * K2, 1), &c2t));
+                    TRY(ws_t(ctx, "pt2_offs2", (size_t)std::max<int64_t>(nchunk * K2, 1), &offs2));
+                    TRY(ws_t(ctx, "pt2_bsum2", (size_t)scan_blocks(nchunk * K2) + 1, &bsum2));
+                    TRY(ws_t(ctx, "pt2_sb", (size_t)K1 * K2 + 1, &sb_d));
+                    TRY(ws_t(ctx, "pt2_desc2", (size_t)std::max<int64_t>(total1, 1), &desc2));
+                    if (nchunk > 0)
+                        HIPCHK(ctx, hipMemcpyAsync(chunks_d, chunks.data(), sizeof(PT2Chunk) * nchunk,
+                                                   hipMemcpyHostToDevice, st));
+                    HIPCHK(ctx, hipMemcpyAsync(bcb0_d, bcb0.data(), sizeof(int64_t) * K1, hipMemcpyHostToDevice, st));
+                    HIPCHK(ctx, hipMemcpyAsync(bnc_d, bnc.data(), sizeof(int64_t) * K1, hipMemcpyHostToDevice, st));
+                    Timer t2(ctx, "pt2_l2");
+                    if (nchunk > 0) {
+                        launch_pt2_l2(st, desc1, chunks_d, nchunk, s2, c2, nullptr, nullptr, false);
+                        CHECK_LAUNCH(ctx);
+                        launch_l2_transpose(st, c2, chunks_d, nchunk, K2, c2t);
+                        launch_exclusive_scan(st, c2t, nchunk * K2, offs2, bsum2, tot + 1);
+                        CHECK_LAUNCH(ctx);
+                        launch_pt2_l2(st, desc1, chunks_d, nchunk, s2, nullptr, offs2, desc2, true);
+                        CHECK_LAUNCH(ctx);
+                    }
+                    launch_sub_starts(st, offs2, bstart_d, bcb0_d, bnc_d, K1, K2, sb_d);
+                    CHECK_LAUNCH(ctx);
+                    t2.stop();
+                    // the host vectors are read by the copies above: wait before they go out of scope
+                    HIPCHK(ctx, hipStreamSynchronize(st));
+                    desc = desc2;
+                    sb = sb_d;
+                    nsb = (int64_t)K1 * K2;
+                }
+                // the members of S in this slice, grouped by sub-bucket (same hash bits as the pairs)
+                int32_t *scnt = nullptr;
+                int64_t *soffs = nullptr, *sbsum = nullptr;
+                uint64_t *skeys = nullptr;
+                int32_t *sidx = nullptr;
+                TRY(ws_t(ctx, "pt2_sidx", (size_t)std::max<int64_t>(n, 1), &sidx));
+                TRY(ws_t(ctx, "pt2_scnt", (size_t)nsb, &scnt));
+                TRY(ws_t(ctx, "pt2_soffs", (size_t)nsb, &soffs));
+                TRY(ws_t(ctx, "pt2_sbsum", (size_t)scan_blocks(nsb) + 1, &sbsum));
+                TRY(ws_t(ctx, "pt2_skeys", (size_t)2 * std::max<int64_t>(n, 1), &skeys));
+                const int sbits = s1 + (s2 > 0 ? s2 : 0);
+                HIPCHK(ctx, hipMemsetAsync(scnt, 0, sizeof(int32_t) * nsb, st));
+                launch_s_sub(st, conn->dets, n, sbits, packed, scnt, nullptr, nullptr, nullptr, false, ss, slice);
+                CHECK_LAUNCH(ctx);
+                launch_exclusive_scan(st, scnt, nsb, soffs, sbsum, tot + 1);
+                CHECK_LAUNCH(ctx);
+                int64_t n_s = 0;  // members of S in this slice
+                HIPCHK(ctx, hipMemcpyAsync(&n_s, tot + 1, sizeof n_s, hipMemcpyDeviceToHost, st));
+                HIPCHK(ctx, hipMemsetAsync(scnt, 0, sizeof(int32_t) * nsb, st));
+                launch_s_sub(st, conn->dets, n, sbits, packed, scnt, soffs, skeys, sidx, true, ss, slice);
+                CHECK_LAUNCH(ctx);
+                HIPCHK(ctx, hipStreamSynchronize(st));
+                double *part_r = nullptr;
+                TRY(ws_t(ctx, "pt2_part_r", (size_t)nsb * pt2_red_part(), &part_r));
+                launch_pt2_init_acc(st, acc + 16);
+                if (o.export_cap > 0)
+                    HIPCHK(ctx, hipMemcpyAsync(o.export_count, ex_save, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+                HIPCHK(ctx, hipMemsetAsync(overflow, 0, sizeof(int), st));
+                Timer tr(ctx, "pt2_reduce");
+                launch_pt2_reduce(st, H, rec, desc, sb, nsb, skeys, sidx, soffs, n_s, vt, energy, o.sample_mask,
+                                  sl.wexp, o.eps_hb, stats, ex, part_r, int_term, overflow, packed);
+                CHECK_LAUNCH(ctx);
+                tr.stop();
+                launch_pt2_accumulate(st, part_r, nsb, acc + 16, part);
+                CHECK_LAUNCH(ctx);
+                int ov = 0;
+                HIPCHK(ctx, hipMemcpyAsync(&ov, overflow, sizeof ov, hipMemcpyDeviceToHost, st));
+                HIPCHK(ctx, hipStreamSynchronize(st));
+                if (!ov) {
+                    launch_pt2_merge(st, acc + 8, acc + 16);
+                    CHECK_LAUNCH(ctx);
+                    nsb_used += nsb;
+                    break;
+                }
+                if ((1 << s2) >= pt2_max_k2() || attempt > 8) {
+                    more_slices = true;
+                    break;
+                }
+                ++s2;
+            }
+            if (more_slices) break;
         }
+        if (!more_slices) break;
+        if (ss >= 20)
+            return fail(ctx, DNQS_ECAPACITY, "PT2: a sub-bucket holds more than %d unique keys", pt2_red_tab());
     }
     launch_pt2_internal(st, int_term, conn->diag, n, energy, part, acc);
     CHECK_LAUNCH(ctx);

@@ -275,10 +275,13 @@ int pt2_red_tab();
 int pt2_red_part();
 int pt2_max_k1();
 int pt2_max_k2();
-// ss > 0: key-space slice `slice` of 2^ss (targets with those top hash bits only)
+// ss > 0: key-space slice `slice` of 2^ss (targets with those top hash bits only).
+// Fill with cur1 != nullptr: no counts needed; bucket b's descriptors go to the region
+// [b cap1, (b + 1) cap1) of desc, appended at the cursor cur1[b] (zeroed by the caller),
+// and a region that would overflow sets *ovf (its excess is not written)
 void launch_pt2_l1(hipStream_t st, const Ham &H, const uint64_t *dets, int64_t n, const double *psi, int s1,
                    int64_t nwg, uint32_t *counts, const int64_t *offs, uint64_t *desc, bool fill, bool packed, int ss,
-                   uint32_t slice);
+                   uint32_t slice, uint64_t *cur1 = nullptr, int64_t cap1 = 0, int *ovf = nullptr);
 void launch_transpose_u32(hipStream_t st, const uint32_t *in, int64_t R, int64_t C, int32_t *out);
 void launch_gather_starts(hipStream_t st, const int64_t *offs, int K, int64_t stride, const int64_t *total,
                           int64_t *starts);

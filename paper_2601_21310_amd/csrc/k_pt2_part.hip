@@ -81,7 +81,9 @@ template <bool FILL, bool PACKED>
 __global__ __launch_bounds__(kL1Threads) void k_pt2_l1(Ham H, const uint64_t *__restrict__ dets, int64_t n,
                                                        const double *__restrict__ psi, int s1, int64_t nwg,
                                                        uint32_t *__restrict__ counts, const int64_t *__restrict__ offs,
-                                                       uint64_t *__restrict__ desc, int ss, uint32_t slice) {
+                                                       uint64_t *__restrict__ desc, int ss, uint32_t slice,
+                                                       unsigned long long *__restrict__ cur1, int64_t cap1,
+                                                       int *__restrict__ ovf) {
     __shared__ uint8_t lists[kL1XPerGroup][4][64];
     __shared__ uint64_t xs[kL1XPerGroup][2];
     __shared__ uint32_t live_s[kL1XPerGroup];
@@ -111,7 +113,7 @@ __global__ __launch_bounds__(kL1Threads) void k_pt2_l1(Ham H, const uint64_t *__
         hist[b] = 0u;
         if (FILL && b < K1) {
             cur[b] = 0u;
-            base[b] = offs[(int64_t)b * nwg + wg];
+            base[b] = cur1 ? 0 : offs[(int64_t)b * nwg + wg];
         }
     }
     __syncthreads();
@@ -163,11 +165,34 @@ __global__ __launch_bounds__(kL1Threads) void k_pt2_l1(Ham H, const uint64_t *__
                 srt[sp] = d[j];
                 sbk[sp] = (uint16_t)bk[j];
             }
+        if (cur1) {
+            // fixed-capacity bucket regions: this round's run of bucket b is reserved at
+            // the region's cursor (one 64-bit atomic per non-empty bucket and round), so no
+            // count pass is needed; a region that would overflow raises *ovf and the
+            // caller repeats the pass with counted offsets
+            for (int b = threadIdx.x; b < K1; b += blockDim.x) {
+                const uint32_t c = hist[b];
+                int64_t r = -1;
+                if (c) {
+                    r = (int64_t)atomicAdd(&cur1[b], (unsigned long long)c);
+                    if (r + (int64_t)c > cap1) {
+                        atomicOr(ovf, 1);
+                        r = -1;
+                    } else {
+                        r += (int64_t)b * cap1;
+                    }
+                }
+                base[b] = r;
+            }
+        }
         __syncthreads();
         const uint32_t nvalid = bst[K1];
         for (uint32_t sp = threadIdx.x; sp < nvalid; sp += blockDim.x) {
             const uint32_t b = sbk[sp];
-            desc[base[b] + cur[b] + (sp - bst[b])] = srt[sp];
+            if (!cur1)
+                desc[base[b] + cur[b] + (sp - bst[b])] = srt[sp];
+            else if (base[b] >= 0)
+                desc[base[b] + (sp - bst[b])] = srt[sp];
         }
         __syncthreads();
         for (int b = threadIdx.x; b <= K1; b += blockDim.x) {
@@ -184,22 +209,23 @@ __global__ __launch_bounds__(kL1Threads) void k_pt2_l1(Ham H, const uint64_t *__
 
 void launch_pt2_l1(hipStream_t st, const Ham &H, const uint64_t *dets, int64_t n, const double *psi, int s1,
                    int64_t nwg, uint32_t *counts, const int64_t *offs, uint64_t *desc, bool fill, bool packed, int ss,
-                   uint32_t slice) {
+                   uint32_t slice, uint64_t *cur1, int64_t cap1, int *ovf) {
     dim3 grid((unsigned)nwg), blk(kL1Threads);
+    unsigned long long *c1 = reinterpret_cast<unsigned long long *>(cur1);
     if (fill) {
         if (packed)
             hipLaunchKernelGGL((k_pt2_l1<true, true>), grid, blk, 0, st, H, dets, n, psi, s1, nwg, counts, offs, desc,
-                               ss, slice);
+                               ss, slice, c1, cap1, ovf);
         else
             hipLaunchKernelGGL((k_pt2_l1<true, false>), grid, blk, 0, st, H, dets, n, psi, s1, nwg, counts, offs, desc,
-                               ss, slice);
+                               ss, slice, c1, cap1, ovf);
     } else {
         if (packed)
             hipLaunchKernelGGL((k_pt2_l1<false, true>), grid, blk, 0, st, H, dets, n, psi, s1, nwg, counts, offs,
-                               desc, ss, slice);
+                               desc, ss, slice, c1, cap1, ovf);
         else
             hipLaunchKernelGGL((k_pt2_l1<false, false>), grid, blk, 0, st, H, dets, n, psi, s1, nwg, counts, offs,
-                               desc, ss, slice);
+                               desc, ss, slice, c1, cap1, ovf);
     }
 }
 

@@ -185,18 +185,33 @@ __device__ __forceinline__ uint32_t red_slot(uint64_t a, uint64_t b) {
 
 __device__ __forceinline__ uint32_t red_next(uint32_t s) { return s + 1 == (uint32_t)kRedTab ? 0u : s + 1; }
 
-// Insert (a, b) into the LDS table (linear probing); returns the slot or -1 when the
-// table is full.
+// A pass is redone with more sub-buckets when a table fills up.  "Full" is decided by a
+// count of the occupied slots: past 7/8 of the slots the pass is marked lost, so no lane
+// keeps probing an (almost) full table; at the table's working load (about 0.55) the
+// longest probe sequence over millions of tables stays far below kRedProbe, the hard
+// bound on a probe sequence.  In the pair loop each wave adds its newly claimed slots
+// with one atomic (a ballot), and the loop checks the count once per iteration.
+constexpr int kRedFillMax = kRedTab / 8 * 7;
+constexpr int kRedProbe = 1024;
+
+// Insert (a, b) into the LDS table (linear probing); returns the slot, or -1 when no free
+// slot or matching key is found within kRedProbe probes.  claimed: this call took an
+// empty slot.
 template <bool PACKED>
-__device__ __forceinline__ int red_insert(unsigned long long *ka_t, unsigned long long *kb_t, uint64_t a, uint64_t b) {
+__device__ __forceinline__ int red_insert(unsigned long long *ka_t, unsigned long long *kb_t, uint64_t a, uint64_t b,
+                                          bool &claimed) {
     uint32_t s = red_slot<PACKED>(a, b);
-    for (int p = 0; p < kRedTab; ++p) {
+    for (int p = 0; p < kRedProbe; ++p) {
         if (PACKED) {
             const unsigned long long k = pack_key(a, b);
             const unsigned long long prev = atomicCAS(&ka_t[s], (unsigned long long)kEmptyKey, k);
-            if (prev == kEmptyKey || prev == k) return (int)s;
+            if (prev == kEmptyKey || prev == k) {
+                claimed = prev == kEmptyKey;
+                return (int)s;
+            }
         } else {
             const unsigned long long pa = atomicCAS(&ka_t[s], (unsigned long long)kEmptyKey, (unsigned long long)a);
+            if (pa == kEmptyKey) claimed = true;
             if (pa == kEmptyKey || pa == a) {
                 const unsigned long long pb =
                     atomicCAS(&kb_t[s], (unsigned long long)kEmptyKey, (unsigned long long)b);
@@ -213,7 +228,7 @@ template <bool PACKED>
 __device__ __forceinline__ int red_find(const unsigned long long *ka_t, const unsigned long long *kb_t, uint64_t a,
                                         uint64_t b) {
     uint32_t s = red_slot<PACKED>(a, b);
-    for (int p = 0; p < kRedTab; ++p) {
+    for (int p = 0; p < kRedProbe; ++p) {
         if (PACKED) {
             const unsigned long long k = ka_t[s];
             if (k == pack_key(a, b)) return (int)s;
@@ -230,18 +245,32 @@ __device__ __forceinline__ int red_find(const unsigned long long *ka_t, const un
 // ------------------------------------------------------------------ exact sums
 // w_a is accumulated in fixed point, so that the sum does not depend on the order in
 // which lanes and waves add their terms (integer addition is associative): each term
-// t = H_ax psi_x, |t| <= 2^wexp, is cut at the grid 2^(wexp - 62 + cb) into a 64-bit
-// part and the next 30 - cb bits into a 32-bit part, where 2^cb exceeds the number of
-// pairs of the sub-bucket (so neither sum can overflow).  About 90 - 2 cb bits below
-// 2^wexp are kept: 2^(wexp-64) or finer for sub-buckets of up to 2^13 pairs, far below
-// the FP64 rounding of w_a itself.
+// t = H_ax psi_x, |t| <= 2^wexp, is scaled to y = t 2^(62 - cb - wexp), where 2^cb exceeds
+// the number of pairs of the sub-bucket and cb >= 11 (so |y| <= 2^51 and neither sum can
+// overflow), rounded to the nearest integer (the 64-bit part), and the remainder
+// (|r| <= 1/2) is scaled by 2^(30 - cb) and truncated into a 32-bit part.  About
+// 90 - 2 cb bits below 2^wexp are kept: 2^(wexp-64) or finer for sub-buckets of up to 2^13
+// pairs, far below the FP64 rounding of w_a itself.
+//
+// Rounding to an integer uses the FP64 adder: for |y| < 2^51, y + 1.5 2^52 lies in
+// [2^52, 2^53), where the spacing is 1, so the sum is 1.5 2^52 + round(y) exactly and
+// round(y) is the difference of the two bit patterns as 64-bit integers; y - round(y) is
+// exact.  Two instructions where a double-to-int64 conversion takes about a dozen.
+constexpr double kRoundMagic = 6755399441055744.0;  // 1.5 * 2^52
+
+__device__ __forceinline__ long long round_split(double y, double &rem) {
+    const double m = y + kRoundMagic;
+    rem = y - (m - kRoundMagic);
+    return __double_as_longlong(m) - __double_as_longlong(kRoundMagic);
+}
+
 struct FixQ {
     double up1, up2;    // 2^(62 - cb - wexp), 2^(30 - cb)
     double dn1, dn2;    // inverses
 };
 
 __device__ __forceinline__ FixQ make_fixq(int wexp, int64_t npairs) {
-    int cb = 0;
+    int cb = 11;
     while (cb < 30 && ((int64_t)1 << cb) <= npairs) ++cb;
     FixQ q;
     q.up1 = ldexp(1.0, 62 - cb - wexp);
@@ -252,9 +281,9 @@ __device__ __forceinline__ FixQ make_fixq(int wexp, int64_t npairs) {
 }
 
 __device__ __forceinline__ void fix_split(const FixQ &q, double t, long long &hi, int &lo) {
-    const double y = t * q.up1;
-    hi = __double2ll_rz(y);
-    lo = __double2int_rz((y - (double)hi) * q.up2);
+    double r;
+    hi = round_split(t * q.up1, r);
+    lo = __double2int_rz(r * q.up2);
 }
 
 __device__ __forceinline__ double fix_join(const FixQ &q, long long hi, int lo) {
@@ -262,8 +291,9 @@ __device__ __forceinline__ double fix_join(const FixQ &q, long long hi, int lo) 
 }
 
 // Exact workgroup sum of each thread's values v[0..cnt): the workgroup's largest |v|
-// fixes the scale 2^e, every value is cut into three 40-bit integer limbs below it and
-// the limbs are summed as integers (at most 2^12 values per thread group: no overflow),
+// fixes the scale 2^e, every value is cut into three 40-bit integer limbs below it
+// (nearest-integer limbs, so a limb may be negative) and the limbs are summed as
+// integers (at most 2^12 values per thread group: no overflow),
 // so the result does not depend on how the values are spread over the threads.  The
 // FP64 result is the exact sum up to the limbs' 2^(e-120) grid, rounded once.  Values
 // that are not finite are summed in FP64 (their sum is inf or NaN in any order).
@@ -324,12 +354,11 @@ __device__ inline double block_exact_sum(const double (&v)[K], int cnt) {
 #pragma unroll
     for (int j = 0; j < K; ++j)
         if (j < cnt) {
-            double y = v[j] * up;  // |y| < 2^40
-            const long long a2 = __double2ll_rz(y);
-            y = (y - (double)a2) * sh;
-            const long long a1 = __double2ll_rz(y);
-            y = (y - (double)a1) * sh;
-            const long long a0 = __double2ll_rz(y);
+            // nearest-integer limbs: |a2| <= 2^40, |a1|, |a0| <= 2^39 (remainders are exact)
+            double r;
+            const long long a2 = round_split(v[j] * up, r);
+            const long long a1 = round_split(r * sh, r);
+            const long long a0 = round_split(r * sh, r);
             l2 += a2;
             l1 += a1;
             l0 += a0;
@@ -418,6 +447,61 @@ __device__ __forceinline__ double haa_unrolled(const double *vt, int No, int M, 
             for (int p = 0; p < q; ++p) e1 += row[ob[p]];
         }
     return e0 + (e1 + e2);
+}
+
+// H_aa by the diagonal rule with the alpha count NA fixed at compile time, row by row of
+// the table (a row: the pairs (p, q) of one occupied spin-orbital q with the occupied p
+// below it): the alpha rows and the alpha part of every beta row are straight-line code,
+// so their reads are issued together and waited for together, where the loops bounded by
+// the runtime counts wait once per read.  The beta rows are a loop that is not unrolled,
+// which keeps the registers in flight to one row.  Each row is summed before it is added,
+// a fixed order, so the result is reproducible to the bit.
+template <int NA, typename W>
+__device__ __forceinline__ double haa_rows(const double *vt, int No, int M, int nb, W a, W b, double ecore) {
+    int oa[NA];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+        oa[k] = low_bit(a);
+        a &= a - 1;
+    }
+    double e = ecore;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+        const double *row = vt + No + oa[q] * (oa[q] - 1) / 2;
+        double r = vt[oa[q]];
+#pragma unroll
+        for (int p = 0; p < q; ++p) r += row[oa[p]];
+        e += r;
+    }
+    W prev = 0;
+#pragma unroll 1
+    for (int q = 0; q < nb; ++q) {
+        const int sq = M + low_bit(b);
+        b &= b - 1;
+        const double *row = vt + No + sq * (sq - 1) / 2;
+        double r = vt[sq];
+#pragma unroll
+        for (int p = 0; p < NA; ++p) r += row[oa[p]];
+        for (W pb = prev; pb; pb &= pb - 1) r += row[M + low_bit(pb)];
+        prev |= (W)1 << (sq - M);
+        e += r;
+    }
+    return e;
+}
+
+// the alpha counts of the workloads measured here get the row form; others the generic
+// unrolled loops (a wave-uniform branch: na and nb are kernel arguments)
+template <typename W>
+__device__ __forceinline__ double haa_lds(const double *vt, int No, int M, int na, int nb, W a, W b, double ecore) {
+    if (sizeof(W) == 4) {  // M <= 32
+        if (na == 7) return haa_rows<7, W>(vt, No, M, nb, a, b, ecore);
+        if (na == 6) return haa_rows<6, W>(vt, No, M, nb, a, b, ecore);
+        if (na == 5) return haa_rows<5, W>(vt, No, M, nb, a, b, ecore);
+        if (na == 4) return haa_rows<4, W>(vt, No, M, nb, a, b, ecore);
+    } else if (na == 12) {
+        return haa_rows<12, W>(vt, No, M, nb, a, b, ecore);
+    }
+    return haa_unrolled<W>(vt, No, M, na, nb, a, b, ecore);
 }
 
 // exclusive scan of one count per thread across the workgroup; total to every thread
@@ -628,8 +712,8 @@ __device__ __forceinline__ bool is_single(uint64_t d) { return ((desc_pos(d) >> 
 template <bool PACKED>
 __device__ __forceinline__ bool red_add(const PairVal &pv, unsigned long long *ka_t, unsigned long long *kb_t,
                                         long long *w_hi, int *w_lo, const FixQ &fq, double hb_thr,
-                                        uint32_t *hb_ok) {
-    const int s = red_insert<PACKED>(ka_t, kb_t, pv.a, pv.b);
+                                        uint32_t *hb_ok, bool &claimed) {
+    const int s = red_insert<PACKED>(ka_t, kb_t, pv.a, pv.b, claimed);
     if (s < 0) return false;
     long long hi;
     int lo;
@@ -646,9 +730,9 @@ template <bool PACKED>
 __device__ __forceinline__ double red_haa(const Ham &H, const double *vt_s, bool lds_vt, int No, uint64_t a,
                                           uint64_t b) {
     if (PACKED && H.na <= kHaaOcc && H.nb <= kHaaOcc)
-        return haa_unrolled<uint32_t>(vt_s, No, H.M, H.na, H.nb, (uint32_t)a, (uint32_t)b, H.ecore);
+        return haa_lds<uint32_t>(vt_s, No, H.M, H.na, H.nb, (uint32_t)a, (uint32_t)b, H.ecore);
     if (!PACKED && lds_vt && H.na <= kHaaOcc && H.nb <= kHaaOcc)
-        return haa_unrolled<uint64_t>(vt_s, No, H.M, H.na, H.nb, a, b, H.ecore);
+        return haa_lds<uint64_t>(vt_s, No, H.M, H.na, H.nb, a, b, H.ecore);
     if (PACKED) {
         const uint64_t occ = a | (b << H.M);
         double haa = H.ecore;
@@ -738,6 +822,8 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
     __shared__ uint32_t hb_ok[kRedTab / 32];  // heat-bath screen passed (hb_eps > 0)
     __shared__ uint64_t sq[kRedSingles];  // single excitations, deferred
     __shared__ int nsq;
+    __shared__ int s_lost;  // a key did not fit: this pass is redone, so stop early
+    __shared__ int s_fill;  // occupied slots
     extern __shared__ double vt_s[];  // diagonal table, sized at launch (empty: global tables)
     for (int t = threadIdx.x; t < kRedTab; t += blockDim.x) {
         ka_t[t] = kEmptyKey;
@@ -749,7 +835,11 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
         in_s[t] = 0u;
         hb_ok[t] = 0u;
     }
-    if (threadIdx.x == 0) nsq = 0;
+    if (threadIdx.x == 0) {
+        nsq = 0;
+        s_lost = 0;
+        s_fill = 0;
+    }
     // |H_ax psi_x| >= hb_eps ||psi||_2 (psi in any scale: the threshold is on the normalised psi)
     const double hb_thr = hb_eps > 0.0 ? hb_eps * sqrt(norm2[0]) : 0.0;
     const int No = 2 * H.M;
@@ -757,13 +847,15 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
     if (lds_vt)
         for (int t = threadIdx.x; t < No + No * (No - 1) / 2; t += blockDim.x) vt_s[t] = vt[t];
     __syncthreads();
-    bool lost = false;
+    volatile int *lost = &s_lost;
     // members of S that hash into this sub-bucket: in the table, marked
     const int64_t q0 = soffs[blockIdx.x], q1 = blockIdx.x + 1 < nsb ? soffs[blockIdx.x + 1] : n_s;
     for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
-        const int s = red_insert<PACKED>(ka_t, kb_t, skeys[2 * q], skeys[2 * q + 1]);
+        bool claimed = false;
+        const int s = red_insert<PACKED>(ka_t, kb_t, skeys[2 * q], skeys[2 * q + 1], claimed);
+        if (claimed) atomicAdd(&s_fill, 1);
         if (s < 0)
-            lost = true;
+            *lost = 1;
         else
             atomicOr(&in_s[s >> 5], 1u << (s & 31));
     }
@@ -795,16 +887,22 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
             const PairVal pv = double_value<PACKED>(H, Rk, d);
             Rn = load_src<PACKED>(rec, Dn);
             Dk = ld_desc(k + 4);
+            bool claimed = false;
             if (base + k * step < s1) {
                 if (is_single(d)) {
                     const int q = atomicAdd(&nsq, 1);
                     if (q < kRedSingles) sq[q] = d;
-                } else if (!red_add<PACKED>(pv, ka_t, kb_t, w_hi, w_lo, fq, hb_thr, hb_ok)) {
-                    lost = true;
+                } else if (!red_add<PACKED>(pv, ka_t, kb_t, w_hi, w_lo, fq, hb_thr, hb_ok, claimed)) {
+                    *lost = 1;
                 }
             }
+            // the wave's newly claimed slots, one atomic (no return value)
+            const uint64_t m = __ballot(claimed);
+            if (m && (int)(threadIdx.x % kWave) == __ffsll((unsigned long long)m) - 1) atomicAdd(&s_fill, __popcll(m));
         };
+        volatile int *fillp = &s_fill;
         for (int64_t k = 0; base + k * step < s1; k += 4) {
+            if (*lost | (*fillp > kRedFillMax)) break;  // per wave; the workgroup leaves together below
             stage(k, D0, R0, D1, R1);
             stage(k + 1, D1, R1, D2, R0);
             stage(k + 2, D2, R0, D3, R1);
@@ -812,6 +910,11 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
         }
     }
     __syncthreads();
+    // the same values on every thread after the barrier
+    if (__builtin_amdgcn_readfirstlane(s_lost) | (__builtin_amdgcn_readfirstlane(s_fill) > kRedFillMax)) {
+        if (threadIdx.x == 0) atomicOr(overflow, 1);
+        return;
+    }
     if (nsq <= kRedSingles) {
         // eight lanes per queued single, each summing every eighth occupied orbital
         for (int k0 = 0; k0 < nsq; k0 += kRedThreads / 8) {
@@ -825,26 +928,33 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
             part_v += __shfl_xor(part_v, 4, 8);
             if (have && l == 0) {
                 pv.e1 += part_v;
-                if (!red_add<PACKED>(pv, ka_t, kb_t, w_hi, w_lo, fq, hb_thr, hb_ok)) lost = true;
+                bool claimed = false;
+                if (!red_add<PACKED>(pv, ka_t, kb_t, w_hi, w_lo, fq, hb_thr, hb_ok, claimed)) *lost = 1;
+                if (claimed) atomicAdd(&s_fill, 1);
             }
         }
     } else {
         for (int64_t i = s0 + threadIdx.x; i < s1; i += step) {
             const uint64_t d = desc[i];
+            bool claimed = false;
             if (is_single(d) &&
                 !red_add<PACKED>(single_pair<PACKED>(H, load_src<PACKED>(rec, d), d), ka_t, kb_t, w_hi, w_lo, fq, hb_thr,
-                                 hb_ok))
-                lost = true;
+                                 hb_ok, claimed))
+                *lost = 1;
+            if (claimed) atomicAdd(&s_fill, 1);
         }
     }
-    if (lost) atomicOr(overflow, 1);
     __syncthreads();
+    if (__builtin_amdgcn_readfirstlane(s_lost) | (__builtin_amdgcn_readfirstlane(s_fill) > kRedFillMax)) {
+        if (threadIdx.x == 0) atomicOr(overflow, 1);
+        return;
+    }
     const double E = energy[0];
     // internal term of the members of S in this sub-bucket (few per sub-bucket)
     for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
         const uint64_t a = skeys[2 * q], b = skeys[2 * q + 1];
         const int s = red_find<PACKED>(ka_t, kb_t, a, b);
-        if (s < 0) continue;  // lost (overflow raised): this pass is repeated
+        if (s < 0) continue;  // not reached: every member was inserted
         const int32_t xi = sidx[q];
         const double pa = __longlong_as_double((long long)(PACKED ? rec[2 * (int64_t)xi + 1] : rec[4 * (int64_t)xi + 2]));
         const double w = fix_join(fq, w_hi[s], w_lo[s]);
@@ -886,15 +996,11 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
             ++pos;
         }
     __syncthreads();
-    double terms[kPer];
-    int nterm = 0;
+    // one pass over the live keys (a plain loop, so H_aa's code appears once): the term
+    // w_a^2 / (E - H_aa) replaces w_a in its slot
     double mn = INFINITY, np = 0.0, nt = 0.0;
     unsigned long long fsum = 0ull, fxor = 0ull;
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-        terms[j] = 0.0;
-        const int t = threadIdx.x + j * kRedThreads;
-        if (t >= (int)n_live) continue;
+    for (int t = threadIdx.x; t < (int)n_live; t += kRedThreads) {
         uint64_t a, b;
         if (PACKED) {
             const unsigned long long k = ka_t[t];
@@ -910,8 +1016,7 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
         np += 1.0;
         mn = fmin(mn, fabs(den));
         if (fabs(den) < 1e-8) nt += 1.0;
-        if (w != 0.0) terms[j] = w * w / den;
-        nterm = j + 1;
+        w_t[t] = w != 0.0 ? w * w / den : 0.0;
         const uint64_t kh = key_hash(a, b);
         fsum += kh;
         fxor ^= kh;
@@ -924,6 +1029,15 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
                 ex.haa[k] = haa;
             }
         }
+    }
+    // this thread's terms (its own slots, written above) into registers for the exact sum
+    double terms[kPer];
+    int nterm = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int t = threadIdx.x + j * kRedThreads;
+        terms[j] = t < (int)n_live ? w_t[t] : 0.0;
+        if (t < (int)n_live) nterm = j + 1;
     }
     const double sum = block_exact_sum<kPer>(terms, nterm);
     red_block(mn, np, nt, fsum, fxor);
