@@ -317,8 +317,8 @@ def bench_curve(args, dnqs, synth, torch):
 # source they were taken on (profiles/pt2_hss_m28_s1e5_hbm_counters.md).
 MEASURED_TRAFFIC = {
     ("k_pt2_reduce", "m28_7a7b_s100k"): ("paper_2601_21310_amd/csrc/k_pt2_reduce.hip",
-                                          "1fa07454529747570c205b9019f564941e780bda4e363d09b75f1529cf34a0d7",
-                                          24992433832.0),
+                                          "d6e1d2bf2facbdf4186fc89bdf7a2cd451d9ba6ed5dad9f6d078e54260c1527c",
+                                          24924268254.0),
 }
 
 
