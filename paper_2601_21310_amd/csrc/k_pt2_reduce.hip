@@ -167,12 +167,22 @@ void launch_s_sub(hipStream_t st, const uint64_t *dets, int64_t n, int sbits, bo
 }
 
 // ------------------------------------------------------------------ reduce kernel
-// Slot of a key in the LDS table: a 32-bit fold of the key through the lowbias32
-// integer hash (C. Wellons, hash-prospector), mapped onto the kRedTab slots by a
-// multiply-shift.  Independent of the partition hash, whose top bits chose the
-// sub-bucket.
+// Probe sequence of a key in the LDS table (double hashing): the start slot and the step
+// come from a 32-bit fold of the key through the lowbias32 integer hash (C. Wellons,
+// hash-prospector), the start mapped onto the kRedTab slots by a multiply-shift and the
+// step an odd number below 2^11 that is not a multiple of 3, so coprime with
+// kRedTab = 3 * 2^10 and the sequence visits every slot.  Independent of the partition
+// hash, whose top bits chose the sub-bucket.  Double hashing rather than linear
+// probing: its probe counts have a shorter tail at the same load (no clustering), and a
+// wave waits for its longest probe sequence.
+static_assert(kRedTab == 3072, "the probe step is coprime with 3 * 2^10");
+
+struct Probe {
+    uint32_t s, step;
+};
+
 template <bool PACKED>
-__device__ __forceinline__ uint32_t red_slot(uint64_t a, uint64_t b) {
+__device__ __forceinline__ Probe red_probe(uint64_t a, uint64_t b) {
     uint32_t f = (uint32_t)a ^ ((uint32_t)b * 0x9e3779b1u);
     if (!PACKED) f ^= ((uint32_t)(a >> 32) * 0x85ebca6bu) ^ ((uint32_t)(b >> 32) * 0xc2b2ae35u);
     f ^= f >> 16;
@@ -180,10 +190,18 @@ __device__ __forceinline__ uint32_t red_slot(uint64_t a, uint64_t b) {
     f ^= f >> 15;
     f *= 0x846ca68bu;
     f ^= f >> 16;
-    return (uint32_t)(((uint64_t)f * (uint64_t)kRedTab) >> 32);
+    Probe p;
+    p.s = (uint32_t)(((uint64_t)f * (uint64_t)kRedTab) >> 32);
+    uint32_t st = (((f * 0x9e3779b1u) >> 22) << 1) | 1u;  // odd, < 2^11
+    if (st % 3u == 0u) st += 2u;
+    p.step = st;
+    return p;
 }
 
-__device__ __forceinline__ uint32_t red_next(uint32_t s) { return s + 1 == (uint32_t)kRedTab ? 0u : s + 1; }
+__device__ __forceinline__ void red_step(Probe &p) {
+    p.s += p.step;
+    if (p.s >= (uint32_t)kRedTab) p.s -= (uint32_t)kRedTab;
+}
 
 // A pass is redone with more sub-buckets when a table fills up.  "Full" is decided by a
 // count of the occupied slots: past 7/8 of the slots the pass is marked lost, so no lane
@@ -200,8 +218,9 @@ constexpr int kRedProbe = 1024;
 template <bool PACKED>
 __device__ __forceinline__ int red_insert(unsigned long long *ka_t, unsigned long long *kb_t, uint64_t a, uint64_t b,
                                           bool &claimed) {
-    uint32_t s = red_slot<PACKED>(a, b);
+    Probe pr = red_probe<PACKED>(a, b);
     for (int p = 0; p < kRedProbe; ++p) {
+        const uint32_t s = pr.s;
         if (PACKED) {
             const unsigned long long k = pack_key(a, b);
             const unsigned long long prev = atomicCAS(&ka_t[s], (unsigned long long)kEmptyKey, k);
@@ -218,7 +237,7 @@ __device__ __forceinline__ int red_insert(unsigned long long *ka_t, unsigned lon
                 if (pb == kEmptyKey || pb == b) return (int)s;
             }
         }
-        s = red_next(s);
+        red_step(pr);
     }
     return -1;
 }
@@ -227,8 +246,9 @@ __device__ __forceinline__ int red_insert(unsigned long long *ka_t, unsigned lon
 template <bool PACKED>
 __device__ __forceinline__ int red_find(const unsigned long long *ka_t, const unsigned long long *kb_t, uint64_t a,
                                         uint64_t b) {
-    uint32_t s = red_slot<PACKED>(a, b);
+    Probe pr = red_probe<PACKED>(a, b);
     for (int p = 0; p < kRedProbe; ++p) {
+        const uint32_t s = pr.s;
         if (PACKED) {
             const unsigned long long k = ka_t[s];
             if (k == pack_key(a, b)) return (int)s;
@@ -237,7 +257,7 @@ __device__ __forceinline__ int red_find(const unsigned long long *ka_t, const un
             if (ka_t[s] == a && kb_t[s] == b) return (int)s;
             if (kb_t[s] == kEmptyKey) return -1;
         }
-        s = red_next(s);
+        red_step(pr);
     }
     return -1;
 }
@@ -576,10 +596,9 @@ __device__ __forceinline__ uint64_t src_beta(const SrcRec &sr) { return ((uint64
 // (holes of x, then particles; ascending within a spin), so the class, the orbitals and
 // the target are read off it; values and phases are those of the Slater-Condon rules with
 // ascending hole/particle pairing (h_offdiag).  One code path for both classes (a wave
-// nearly always holds both), straight-line so that the loads can be waited for by count:
+// nearly always holds both); the exchange integral is loaded for same-spin pairs only:
 //   alpha-beta: i -> r (alpha), j -> t (beta), value (ri|tj)
 //   same-spin:  holes i < j, particles r < t, value (ri|tj) - (rj|ti)
-// For alpha-beta pairs the second load re-reads the first integral and is not used.
 // Called on every descriptor of the sub-bucket, singles included.
 template <bool PACKED>
 __device__ __forceinline__ PairVal double_value(const Ham &H, const SrcRec &sr, uint64_t d) {
@@ -603,8 +622,8 @@ __device__ __forceinline__ PairVal double_value(const Ham &H, const SrcRec &sr, 
     pv.a = xa ^ (ab ? f_ir : (beta ? 0ull : (f_ir | f_jt)));
     pv.b = xb ^ (ab ? f_jt : (beta ? (f_ir | f_jt) : 0ull));
     pv.e1 = e[tri_index(ri, tj)];
-    pv.e2 = e[ab ? tri_index(ri, tj) : tri_index(rj, ti)];
-    if (ab) pv.e2 = 0.0;
+    pv.e2 = 0.0;
+    if (!ab) pv.e2 = e[tri_index(rj, ti)];  // same-spin doubles only: fewer L1/L2 requests
     pv.px = __longlong_as_double((long long)sr.p);
     pv.ph = red_phase<PACKED>(s1, i, r) * red_phase<PACKED>(s2, j, t);
     return pv;
