@@ -27,42 +27,47 @@
 namespace dnqs {
 
 // ------------------------------------------------------------------ reduce
-// Workgroup min / counts / fingerprint (each exact in any order); result to thread 0.
-__device__ inline void red_block(double &mn, double &np, double &nt, unsigned long long &fs,
-                                 unsigned long long &fx) {
-    __shared__ double sh[3][kRedThreads / kWave];
-    __shared__ unsigned long long sf[2][kRedThreads / kWave];
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        mn = fmin(mn, __shfl_xor(mn, o, 64));
-        np += __shfl_xor(np, o, 64);
-        nt += __shfl_xor(nt, o, 64);
-        fs += __shfl_xor(fs, o, 64);
-        fx ^= __shfl_xor(fx, o, 64);
-    }
-    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    if (lane == 0) {
-        sh[0][wave] = mn;
-        sh[1][wave] = np;
-        sh[2][wave] = nt;
-        sf[0][wave] = fs;
-        sf[1][wave] = fx;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < (int)(blockDim.x / kWave); ++w) {
-            sh[0][0] = fmin(sh[0][0], sh[0][w]);
-            sh[1][0] += sh[1][w];
-            sh[2][0] += sh[2][w];
-            sf[0][0] += sf[0][w];
-            sf[1][0] ^= sf[1][w];
-        }
-        mn = sh[0][0];
-        np = sh[1][0];
-        nt = sh[2][0];
-        fs = sf[0][0];
-        fx = sf[1][0];
-    }
+// Wave reductions: two quad permutations and two rotations within each row of 16 lanes
+// by DPP leave every lane with its row's result, and the four rows' results are read out
+// (readlane) and combined in a fixed order, (r0 op r1) op (r2 op r3).  Every lane of the
+// wave must be active.  (Cross-lane moves on the VALU: the generic shuffle goes through
+// the LDS crossbar, one round trip per step.)
+// a 64-bit value of lane l, as two 32-bit reads (the readlane builtin is 32-bit: a wider
+// argument is narrowed to its low half)
+__device__ __forceinline__ long long readlane64(long long v, int l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+    return (long long)(((uint64_t)hi << 32) | lo);
+}
+
+template <int CTRL, int ROW>
+__device__ __forceinline__ long long dpp_ll(long long id, long long v) {
+    return __builtin_amdgcn_update_dpp(id, v, CTRL, ROW, 0xf, false);
+}
+
+template <typename T>
+__device__ __forceinline__ long long to_ll(T v) {
+    if constexpr (sizeof(T) == 8 && __is_same(T, double)) return __double_as_longlong(v);
+    else return (long long)v;
+}
+
+template <typename T>
+__device__ __forceinline__ T from_ll(long long v) {
+    if constexpr (__is_same(T, double)) return __longlong_as_double(v);
+    else return (T)v;
+}
+
+template <typename T, typename Op>
+__device__ __forceinline__ T wave_reduce(T v, T id, Op op) {
+    const long long i = to_ll(id);
+    v = op(v, from_ll<T>(dpp_ll<0xB1, 0xf>(i, to_ll(v))));   // quad_perm [1,0,3,2]
+    v = op(v, from_ll<T>(dpp_ll<0x4E, 0xf>(i, to_ll(v))));   // quad_perm [2,3,0,1]
+    v = op(v, from_ll<T>(dpp_ll<0x124, 0xf>(i, to_ll(v))));  // row_ror:4
+    v = op(v, from_ll<T>(dpp_ll<0x128, 0xf>(i, to_ll(v))));  // row_ror:8
+    const long long b = to_ll(v);
+    const T r0 = from_ll<T>(readlane64(b, 0)), r1 = from_ll<T>(readlane64(b, 16));
+    const T r2 = from_ll<T>(readlane64(b, 32)), r3 = from_ll<T>(readlane64(b, 48));
+    return op(op(r0, r1), op(r2, r3));
 }
 
 // Coulomb minus same-spin exchange between spin-orbitals s, t (alpha s < M, beta M + p)
@@ -167,12 +172,14 @@ void launch_s_sub(hipStream_t st, const uint64_t *dets, int64_t n, int sbits, bo
 }
 
 // ------------------------------------------------------------------ reduce kernel
-// Probe sequence of a key in the LDS table (double hashing): the start slot and the step
-// come from a 32-bit fold of the key through the lowbias32 integer hash (C. Wellons,
-// hash-prospector), the start mapped onto the kRedTab slots by a multiply-shift and the
-// step an odd number below 2^11 that is not a multiple of 3, so coprime with
-// kRedTab = 3 * 2^10 and the sequence visits every slot.  Independent of the partition
-// hash, whose top bits chose the sub-bucket.  Double hashing rather than linear
+// Probe sequence of a key in the LDS table (double hashing).  The key is folded to 32
+// bits (f = a XOR b * odd constant) and multiplied by a second odd constant; the top 22
+// bits of the product map onto the kRedTab slots (start = floor(top22 * 3 / 2^12), near
+// uniform), and seven low bits give the step 6k + 1, which is odd and not a multiple of 3,
+// so coprime with kRedTab = 3 * 2^10: the sequence visits every slot.  Two 32-bit
+// multiplies and a 24-bit one: the hash is computed for every pair, and a full
+// integer-hash finaliser cost more than the probes it saved.  Independent of the
+// partition hash, whose top bits chose the sub-bucket.  Double hashing rather than linear
 // probing: its probe counts have a shorter tail at the same load (no clustering), and a
 // wave waits for its longest probe sequence.
 static_assert(kRedTab == 3072, "the probe step is coprime with 3 * 2^10");
@@ -185,16 +192,10 @@ template <bool PACKED>
 __device__ __forceinline__ Probe red_probe(uint64_t a, uint64_t b) {
     uint32_t f = (uint32_t)a ^ ((uint32_t)b * 0x9e3779b1u);
     if (!PACKED) f ^= ((uint32_t)(a >> 32) * 0x85ebca6bu) ^ ((uint32_t)(b >> 32) * 0xc2b2ae35u);
-    f ^= f >> 16;
-    f *= 0x7feb352du;
-    f ^= f >> 15;
-    f *= 0x846ca68bu;
-    f ^= f >> 16;
+    const uint32_t h = (f ^ (f >> 16)) * 0x7feb352du;
     Probe p;
-    p.s = (uint32_t)(((uint64_t)f * (uint64_t)kRedTab) >> 32);
-    uint32_t st = (((f * 0x9e3779b1u) >> 22) << 1) | 1u;  // odd, < 2^11
-    if (st % 3u == 0u) st += 2u;
-    p.step = st;
+    p.s = __umul24(h >> 10, 3u) >> 12;           // [0, 3072)
+    p.step = __umul24((h >> 3) & 127u, 6u) + 1u;  // 6k + 1 <= 763
     return p;
 }
 
@@ -310,110 +311,141 @@ __device__ __forceinline__ double fix_join(const FixQ &q, long long hi, int lo) 
     return (double)hi * q.dn1 + (double)lo * q.dn2;
 }
 
-// Exact workgroup sum of each thread's values v[0..cnt): the workgroup's largest |v|
-// fixes the scale 2^e, every value is cut into three 40-bit integer limbs below it
-// (nearest-integer limbs, so a limb may be negative) and the limbs are summed as
-// integers (at most 2^12 values per thread group: no overflow),
-// so the result does not depend on how the values are spread over the threads.  The
-// FP64 result is the exact sum up to the limbs' 2^(e-120) grid, rounded once.  Values
-// that are not finite are summed in FP64 (their sum is inf or NaN in any order).
-// Every thread of the block must call it; the result is returned to thread 0.
+// The workgroup's outputs, to part[0..8) by thread 0:
+//   [0] the exact sum of every thread's values v[0..cnt): the workgroup's largest |v|
+//       fixes the scale 2^e, every value is cut into three 40-bit integer limbs below it
+//       (nearest-integer limbs, so a limb may be negative) and the limbs are summed as
+//       integers (at most 2^12 values per thread group: no overflow), so the result does
+//       not depend on how the values are spread over the threads; the FP64 result is the
+//       exact sum up to the limbs' 2^(e-120) grid, rounded once.  Values that are not
+//       finite are summed in FP64 (their sum is inf or NaN in any order).
+//   [1] min of mn, [2] sum of np, [3] sum of nt, [4], [5] (bits) sum mod 2^64 and XOR of
+//       fs, fx; [6], [7] zero.  Each is exact in any order.
+// Two barriers: the maximum and the other reductions together, then the limbs.  Every
+// thread of the block must call it.
 template <int K>
-__device__ inline double block_exact_sum(const double (&v)[K], int cnt) {
-    __shared__ double s_max[kRedThreads / kWave];
-    __shared__ long long s_limb[3][kRedThreads / kWave];
-    __shared__ int s_bad[kRedThreads / kWave];
-    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+__device__ inline void red_final(const double (&v)[K], int cnt, double mn, double np, double nt,
+                                 unsigned long long fs, unsigned long long fx, double *__restrict__ out) {
+    constexpr int NW = kRedThreads / kWave;
+    __shared__ double s_d[4][NW];              // max |v|, min, np, nt
+    __shared__ unsigned long long s_u[3][NW];  // fs, fx, non-finite flag
+    __shared__ long long s_l[3][NW];           // limb sums (or the FP64 sum's bits)
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     double mx = 0.0;
-    int bad = 0;
+    unsigned long long bad = 0ull;
 #pragma unroll
     for (int j = 0; j < K; ++j)
         if (j < cnt) {
             if (isfinite(v[j]))
                 mx = fmax(mx, fabs(v[j]));
             else
-                bad = 1;
+                bad = 1ull;
         }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        mx = fmax(mx, __shfl_xor(mx, o, 64));
-        bad |= __shfl_xor(bad, o, 64);
-    }
+    const auto dmax = [](double a, double b) { return fmax(a, b); };
+    const auto dmin = [](double a, double b) { return fmin(a, b); };
+    const auto dadd = [](double a, double b) { return a + b; };
+    const auto uadd = [](unsigned long long a, unsigned long long b) { return a + b; };
+    const auto uxor = [](unsigned long long a, unsigned long long b) { return a ^ b; };
+    const auto uor = [](unsigned long long a, unsigned long long b) { return a | b; };
+    const auto ladd = [](long long a, long long b) { return a + b; };
+    mx = wave_reduce(mx, 0.0, dmax);
+    mn = wave_reduce(mn, (double)INFINITY, dmin);
+    np = wave_reduce(np, 0.0, dadd);
+    nt = wave_reduce(nt, 0.0, dadd);
+    fs = wave_reduce(fs, 0ull, uadd);
+    fx = wave_reduce(fx, 0ull, uxor);
+    bad = wave_reduce(bad, 0ull, uor);
     if (lane == 0) {
-        s_max[wave] = mx;
-        s_bad[wave] = bad;
+        s_d[0][wave] = mx;
+        s_d[1][wave] = mn;
+        s_d[2][wave] = np;
+        s_d[3][wave] = nt;
+        s_u[0][wave] = fs;
+        s_u[1][wave] = fx;
+        s_u[2][wave] = bad;
     }
     __syncthreads();
     mx = 0.0;
-    bad = 0;
-    for (int w = 0; w < nw; ++w) {
-        mx = fmax(mx, s_max[w]);
-        bad |= s_bad[w];
+    bad = 0ull;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        mx = fmax(mx, s_d[0][w]);
+        bad |= s_u[2][w];
     }
-    __syncthreads();
+    double sum = 0.0;
     if (bad) {
         // inf / NaN present: an FP64 sum (non-finite in any order)
-        double s = 0.0;
+        double t = 0.0;
 #pragma unroll
         for (int j = 0; j < K; ++j)
-            if (j < cnt) s += v[j];
-        s = wave_sum(s);
-        if (lane == 0) s_max[wave] = s;
+            if (j < cnt) t += v[j];
+        t = wave_reduce(t, 0.0, dadd);
+        if (lane == 0) s_l[0][wave] = __double_as_longlong(t);
         __syncthreads();
-        double t = 0.0;
         if (threadIdx.x == 0)
-            for (int w = 0; w < nw; ++w) t += s_max[w];
+            for (int w = 0; w < NW; ++w) sum += __longlong_as_double(s_l[0][w]);
+    } else if (mx != 0.0) {
+        int e;
+        (void)frexp(mx, &e);  // mx < 2^e
+        const double up = ldexp(1.0, 40 - e), sh = 1099511627776.0;  // 2^40
+        long long l2 = 0, l1 = 0, l0 = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j < cnt) {
+                // nearest-integer limbs: |a2| <= 2^40, |a1|, |a0| <= 2^39 (remainders are exact)
+                double r;
+                const long long a2 = round_split(v[j] * up, r);
+                const long long a1 = round_split(r * sh, r);
+                const long long a0 = round_split(r * sh, r);
+                l2 += a2;
+                l1 += a1;
+                l0 += a0;
+            }
+        l2 = wave_reduce(l2, 0ll, ladd);
+        l1 = wave_reduce(l1, 0ll, ladd);
+        l0 = wave_reduce(l0, 0ll, ladd);
+        if (lane == 0) {
+            s_l[0][wave] = l2;
+            s_l[1][wave] = l1;
+            s_l[2][wave] = l0;
+        }
         __syncthreads();
-        return t;
-    }
-    if (mx == 0.0) return 0.0;
-    int e;
-    (void)frexp(mx, &e);  // mx < 2^e
-    const double up = ldexp(1.0, 40 - e), sh = 1099511627776.0;  // 2^40
-    long long l2 = 0, l1 = 0, l0 = 0;
-#pragma unroll
-    for (int j = 0; j < K; ++j)
-        if (j < cnt) {
-            // nearest-integer limbs: |a2| <= 2^40, |a1|, |a0| <= 2^39 (remainders are exact)
-            double r;
-            const long long a2 = round_split(v[j] * up, r);
-            const long long a1 = round_split(r * sh, r);
-            const long long a0 = round_split(r * sh, r);
-            l2 += a2;
-            l1 += a1;
-            l0 += a0;
+        if (threadIdx.x == 0) {
+            long long L2 = 0, L1 = 0, L0 = 0;
+            for (int w = 0; w < NW; ++w) {
+                L2 += s_l[0][w];
+                L1 += s_l[1][w];
+                L0 += s_l[2][w];
+            }
+            // carry the lower limbs up; the conversion is a fixed formula of the integers
+            const long long c0 = L0 / 1099511627776ll;
+            L0 -= c0 * 1099511627776ll;
+            L1 += c0;
+            const long long c1 = L1 / 1099511627776ll;
+            L1 -= c1 * 1099511627776ll;
+            L2 += c1;
+            sum = ldexp((double)L2 + ((double)L1 + (double)L0 / sh) / sh, e - 40);
         }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        l2 += __shfl_xor(l2, o, 64);
-        l1 += __shfl_xor(l1, o, 64);
-        l0 += __shfl_xor(l0, o, 64);
     }
-    if (lane == 0) {
-        s_limb[0][wave] = l2;
-        s_limb[1][wave] = l1;
-        s_limb[2][wave] = l0;
-    }
-    __syncthreads();
-    double t = 0.0;
     if (threadIdx.x == 0) {
-        long long L2 = 0, L1 = 0, L0 = 0;
-        for (int w = 0; w < nw; ++w) {
-            L2 += s_limb[0][w];
-            L1 += s_limb[1][w];
-            L0 += s_limb[2][w];
+        double m = s_d[1][0], p = s_d[2][0], q = s_d[3][0];
+        unsigned long long a = s_u[0][0], x = s_u[1][0];
+        for (int w = 1; w < NW; ++w) {
+            m = fmin(m, s_d[1][w]);
+            p += s_d[2][w];
+            q += s_d[3][w];
+            a += s_u[0][w];
+            x ^= s_u[1][w];
         }
-        // carry the lower limbs up; the conversion is a fixed formula of the integers
-        const long long c0 = L0 / 1099511627776ll;
-        L0 -= c0 * 1099511627776ll;
-        L1 += c0;
-        const long long c1 = L1 / 1099511627776ll;
-        L1 -= c1 * 1099511627776ll;
-        L2 += c1;
-        t = ldexp((double)L2 + ((double)L1 + (double)L0 / sh) / sh, e - 40);
+        out[0] = sum;
+        out[1] = m;
+        out[2] = p;
+        out[3] = q;
+        out[4] = __longlong_as_double((long long)a);
+        out[5] = __longlong_as_double((long long)x);
+        out[6] = 0.0;
+        out[7] = 0.0;
     }
-    __syncthreads();
-    return t;
 }
 
 // H_aa by the diagonal rule from the LDS table, with the loops unrolled over at most
@@ -524,26 +556,33 @@ __device__ __forceinline__ double haa_lds(const double *vt, int No, int M, int n
     return haa_unrolled<W>(vt, No, M, na, nb, a, b, ecore);
 }
 
-// exclusive scan of one count per thread across the workgroup; total to every thread
+// exclusive scan of one count per thread across the workgroup; total to every thread.
+// The wave's inclusive scan by DPP: row shifts by 1, 2 and 3 of the original values give
+// sums of four, row shifts by 4 and 8 (on the upper banks) complete each row of 16, and
+// the totals of the rows below (read out of lanes 15, 31, 47) are added.
 __device__ inline uint32_t red_scan(uint32_t v, uint32_t &total) {
     __shared__ uint32_t wsum[kRedThreads / kWave];
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    uint32_t inc = v;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t u = __shfl_up(inc, o, kWave);
-        if (lane >= o) inc += u;
-    }
-    if (lane == kWave - 1) wsum[wave] = inc;
+    const int x = (int)v;
+    int inc = x + __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    inc += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);         // row_shr:2
+    inc += __builtin_amdgcn_update_dpp(0, x, 0x113, 0xf, 0xf, false);         // row_shr:3
+    inc += __builtin_amdgcn_update_dpp(0, inc, 0x114, 0xf, 0xe, false);       // row_shr:4, banks 1-3
+    inc += __builtin_amdgcn_update_dpp(0, inc, 0x118, 0xf, 0xc, false);       // row_shr:8, banks 2-3
+    const int t0 = __builtin_amdgcn_readlane(inc, 15), t1 = __builtin_amdgcn_readlane(inc, 31);
+    const int t2 = __builtin_amdgcn_readlane(inc, 47);
+    const int row = lane >> 4;
+    inc += (row >= 1 ? t0 : 0) + (row >= 2 ? t1 : 0) + (row >= 3 ? t2 : 0);
+    if (lane == kWave - 1) wsum[wave] = (uint32_t)inc;
     __syncthreads();
     uint32_t before = 0;
     total = 0;
     for (int w = 0; w < kRedThreads / kWave; ++w) {
-        const uint32_t x = wsum[w];
-        if (w < wave) before += x;
-        total += x;
+        const uint32_t y = wsum[w];
+        if (w < wave) before += y;
+        total += y;
     }
-    return before + inc - v;
+    return before + (uint32_t)inc - v;
 }
 
 // (-1)^(occupied orbitals of s strictly between p and q); 32-bit strings when M <= 32
@@ -555,6 +594,17 @@ __device__ __forceinline__ int red_phase(uint64_t s, int p, int q) {
         return (__popc((uint32_t)s & m) & 1) ? -1 : 1;
     }
     return phase_between(s, p, q);
+}
+
+// Pair index (p|q) -> p(p+1)/2 + q for p >= q, with a 24-bit product: p, q < 2^11 (orbital
+// pairs of M <= 64), so p(p+1) < 2^24.
+// (v_mul_u32_u24 written out: left to itself the compiler fuses the product and the index's
+// widening into a 64-bit multiply-add, which issues at a quarter of the rate)
+__device__ __forceinline__ int tri24(int p, int q) {
+    const uint32_t hi = (uint32_t)max(p, q), lo = (uint32_t)min(p, q);
+    uint32_t pr;
+    asm("v_mul_u32_u24 %0, %1, %2" : "=v"(pr) : "v"(hi), "v"(hi + 1u));
+    return (int)((pr >> 1) + lo);
 }
 
 // H_ax psi_x for one pair descriptor.  The descriptor's flipped positions give the
@@ -580,14 +630,21 @@ __device__ __forceinline__ SrcRec load_src(const uint64_t *__restrict__ rec, uin
     return SrcRec{*reinterpret_cast<const uint4 *>(rec + 4 * x), rec[4 * x + 2]};
 }
 
-// A pair's target (a, b) and the factors of H_ax psi_x = ph * (e1 - e2) * psi_x.  The
-// integrals are kept as loaded and combined in red_add, after the loop has issued its
-// prefetches, so that the wait for them does not cover the prefetches.
+// A pair's target (a, b) and the factors of H_ax psi_x = (-1)^phase (e1 - e2) psi_x; the
+// phase is kept as the FP64 sign bit (sgn = 0 or 2^63) and applied with an XOR, which is
+// exact.  The integrals are kept as loaded and combined in red_add, after the loop has
+// issued its prefetches, so that the wait for them does not cover the prefetches.
 struct PairVal {
     uint64_t a, b;
     double e1, e2, px;
-    int ph;
+    uint64_t sgn;
 };
+
+__device__ __forceinline__ uint64_t sign_bit(int ph) { return ph < 0 ? 0x8000000000000000ull : 0ull; }
+
+__device__ __forceinline__ double pair_term(const PairVal &pv) {
+    return __longlong_as_double((long long)((uint64_t)__double_as_longlong((pv.e1 - pv.e2) * pv.px) ^ pv.sgn));
+}
 
 __device__ __forceinline__ uint64_t src_alpha(const SrcRec &sr) { return ((uint64_t)sr.s.y << 32) | sr.s.x; }
 __device__ __forceinline__ uint64_t src_beta(const SrcRec &sr) { return ((uint64_t)sr.s.w << 32) | sr.s.z; }
@@ -602,7 +659,6 @@ __device__ __forceinline__ uint64_t src_beta(const SrcRec &sr) { return ((uint64
 // Called on every descriptor of the sub-bucket, singles included.
 template <bool PACKED>
 __device__ __forceinline__ PairVal double_value(const Ham &H, const SrcRec &sr, uint64_t d) {
-    const uint64_t xa = src_alpha(sr), xb = src_beta(sr);
     const uint32_t pos = desc_pos(d);
     const int p0 = (int)(pos & 127u), p1 = (int)((pos >> 7) & 127u);
     // A single's last two positions are kNoPos: it is called on singles too (their result
@@ -612,20 +668,37 @@ __device__ __forceinline__ PairVal double_value(const Ham &H, const SrcRec &sr, 
     const bool ab = p0 < 64 && p2 >= 64, beta = p0 >= 64;
     const int i = p0 & 63, t = p3 & 63;
     const int r = ab ? p1 : (p2 & 63), j = ab ? (p2 - 64) : (p1 & 63);
-    const uint64_t f_ir = (1ull << i) | (1ull << r), f_jt = (1ull << j) | (1ull << t);
-    const uint64_t s1 = beta ? xb : xa;                                    // holds i and r
-    const uint64_t s2 = ab ? xb : ((s1 & ~(1ull << i)) | (1ull << r));  // holds j and t
-    const int ri = tri_index(r, i), tj = tri_index(t, j);
-    const int rj = tri_index(r, j), ti = tri_index(t, i);
+    const int ri = tri24(r, i), tj = tri24(t, j);
+    const int rj = tri24(r, j), ti = tri24(t, i);
     const double *e = H.eri_pk;
     PairVal pv;
-    pv.a = xa ^ (ab ? f_ir : (beta ? 0ull : (f_ir | f_jt)));
-    pv.b = xb ^ (ab ? f_jt : (beta ? (f_ir | f_jt) : 0ull));
-    pv.e1 = e[tri_index(ri, tj)];
+    pv.e1 = e[tri24(ri, tj)];
     pv.e2 = 0.0;
-    if (!ab) pv.e2 = e[tri_index(rj, ti)];  // same-spin doubles only: fewer L1/L2 requests
+    if (!ab) pv.e2 = e[tri24(rj, ti)];  // same-spin doubles only: fewer L1/L2 requests
     pv.px = __longlong_as_double((long long)sr.p);
-    pv.ph = red_phase<PACKED>(s1, i, r) * red_phase<PACKED>(s2, j, t);
+    int par;
+    if (PACKED) {
+        // M <= 32: 32-bit strings, masks and phases
+        const uint32_t xa = sr.s.x, xb = sr.s.z;
+        const uint32_t f_ir = (1u << i) | (1u << r), f_jt = (1u << j) | (1u << t);
+        const uint32_t s1 = beta ? xb : xa;                                  // holds i and r
+        const uint32_t s2 = ab ? xb : ((s1 & ~(1u << i)) | (1u << r));  // holds j and t
+        pv.a = xa ^ (ab ? f_ir : (beta ? 0u : (f_ir | f_jt)));
+        pv.b = xb ^ (ab ? f_jt : (beta ? (f_ir | f_jt) : 0u));
+        // occupied orbitals strictly between the hole and the particle, for both moves
+        const uint32_t m1 = ((1u << max(i, r)) - 1u) & ~((2u << min(i, r)) - 1u);
+        const uint32_t m2 = ((1u << max(j, t)) - 1u) & ~((2u << min(j, t)) - 1u);
+        par = (__popc(s1 & m1) + __popc(s2 & m2)) & 1;
+    } else {
+        const uint64_t xa = src_alpha(sr), xb = src_beta(sr);
+        const uint64_t f_ir = (1ull << i) | (1ull << r), f_jt = (1ull << j) | (1ull << t);
+        const uint64_t s1 = beta ? xb : xa;
+        const uint64_t s2 = ab ? xb : ((s1 & ~(1ull << i)) | (1ull << r));
+        pv.a = xa ^ (ab ? f_ir : (beta ? 0ull : (f_ir | f_jt)));
+        pv.b = xb ^ (ab ? f_jt : (beta ? (f_ir | f_jt) : 0ull));
+        par = (phase_between(s1, i, r) * phase_between(s2, j, t)) < 0 ? 1 : 0;
+    }
+    pv.sgn = (uint64_t)par << 63;
     return pv;
 }
 
@@ -677,13 +750,19 @@ __device__ __forceinline__ PairVal single_pair(const Ham &H, const SrcRec &sr, u
     pv.e1 = single_value_grouped(H, p, q, same, other);
     pv.e2 = 0.0;
     pv.px = __longlong_as_double((long long)sr.p);
-    pv.ph = red_phase<PACKED>(same, p, q);
+    pv.sgn = sign_bit(red_phase<PACKED>(same, p, q));
     return pv;
 }
 
-// One lane's share of a single (hole p0, particle p1) spread over eight lanes: lane l
-// sums the terms of the occupied orbitals r != q numbered l, l + 8, ... (same spin first,
-// ascending) into part; the returned e1 holds h_pq, and the caller adds the eight parts.
+// One lane's share of a single (hole p0, particle p1) spread over eight lanes; the
+// returned e1 holds h_pq, and the caller adds the eight parts.
+//   M <= 32: lane l takes the orbitals r = l, l + 8, l + 16, l + 24 and adds, for each,
+//   (pq|rr) once per electron occupying r (q excluded on the same spin) minus (pr|rq) when
+//   r is occupied on the same spin (the weights 0, 1, 2 and the products are exact).  Its
+//   loads go out together, so a single costs one integral latency; the order of the adds
+//   is fixed.
+//   Otherwise: lane l sums the terms of the occupied orbitals r != q numbered l, l + 8, ...
+//   (same spin first, ascending).
 template <bool PACKED>
 __device__ __forceinline__ PairVal single_part(const Ham &H, const SrcRec &sr, uint64_t d, int l, double &part) {
     const uint64_t xa = src_alpha(sr), xb = src_beta(sr);
@@ -694,23 +773,43 @@ __device__ __forceinline__ PairVal single_part(const Ham &H, const SrcRec &sr, u
     const uint64_t same = beta ? xb : xa, other = beta ? xa : xb;
     const uint64_t flip = (1ull << q) | (1ull << p);
     const double *e = H.eri_pk;
-    const int pq = tri_index(p, q);
-    uint64_t sm = same & ~(1ull << q), om = other;
-    const int ns = popc64(sm);
-    // this lane's orbitals: entries l, l + 8, ... of (same-spin list, other-spin list)
-    for (int idx = 0; ; idx += 8) {
-        const int n = idx + l;
-        if (n >= ns + popc64(om)) break;
-        if (n < ns) {
-            uint64_t m = sm;
-            for (int c = 0; c < n; ++c) m &= m - 1;
-            const int r = ctz64(m);
-            part += e[tri_index(pq, tri_index(r, r))] - e[tri_index(tri_index(p, r), tri_index(r, q))];
-        } else {
-            uint64_t m = om;
-            for (int c = 0; c < n - ns; ++c) m &= m - 1;
-            const int r = ctz64(m);
-            part += e[tri_index(pq, tri_index(r, r))];
+    if (PACKED) {
+        const int pq = tri24(p, q);
+        const uint32_t sm = (uint32_t)same & ~(1u << q), om = (uint32_t)other;
+        double c[4], x[4], nc[4], nx[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            // every load is issued (index clamped into the table), then weighted by the
+            // occupation: no branches, so the eight loads go out back to back
+            const int r = l + 8 * k;  // < 32; strings hold no bits at or above M
+            const int rl = min(r, H.M - 1);
+            const uint32_t bit = 1u << r;
+            nc[k] = (double)(((sm & bit) ? 1 : 0) + ((om & bit) ? 1 : 0));
+            nx[k] = (sm & bit) ? 1.0 : 0.0;
+            c[k] = e[tri24(pq, tri24(rl, rl))];
+            x[k] = e[tri24(tri24(p, rl), tri24(rl, q))];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) part += nc[k] * c[k] - nx[k] * x[k];
+    } else {
+        const int pq = tri_index(p, q);
+        uint64_t sm = same & ~(1ull << q), om = other;
+        const int ns = popc64(sm);
+        // this lane's orbitals: entries l, l + 8, ... of (same-spin list, other-spin list)
+        for (int idx = 0;; idx += 8) {
+            const int n = idx + l;
+            if (n >= ns + popc64(om)) break;
+            if (n < ns) {
+                uint64_t m = sm;
+                for (int c = 0; c < n; ++c) m &= m - 1;
+                const int r = ctz64(m);
+                part += e[tri_index(pq, tri_index(r, r))] - e[tri_index(tri_index(p, r), tri_index(r, q))];
+            } else {
+                uint64_t m = om;
+                for (int c = 0; c < n - ns; ++c) m &= m - 1;
+                const int r = ctz64(m);
+                part += e[tri_index(pq, tri_index(r, r))];
+            }
         }
     }
     PairVal pv;
@@ -719,7 +818,7 @@ __device__ __forceinline__ PairVal single_part(const Ham &H, const SrcRec &sr, u
     pv.e1 = H.h64[p * H.M + q];
     pv.e2 = 0.0;
     pv.px = __longlong_as_double((long long)sr.p);
-    pv.ph = red_phase<PACKED>(same, p, q);
+    pv.sgn = sign_bit(red_phase<PACKED>(same, p, q));
     return pv;
 }
 
@@ -736,7 +835,7 @@ __device__ __forceinline__ bool red_add(const PairVal &pv, unsigned long long *k
     if (s < 0) return false;
     long long hi;
     int lo;
-    const double t = (pv.ph * (pv.e1 - pv.e2)) * pv.px;
+    const double t = pair_term(pv);
     fix_split(fq, t, hi, lo);
     atomicAdd(reinterpret_cast<unsigned long long *>(&w_hi[s]), (unsigned long long)hi);  // two's complement
     atomicAdd(&w_lo[s], lo);
@@ -812,7 +911,7 @@ __device__ __forceinline__ double red_haa(const Ham &H, const double *vt_s, bool
 }
 
 // Per sub-bucket output part[kRedPart * sub-bucket]:
-//   [0] external sum over its keys of P (exact workgroup sum, see block_exact_sum)
+//   [0] external sum over its keys of P (exact workgroup sum, see red_final)
 //   [1] min |E - H_aa| over those keys      [2] their number     [3] those with |E - H_aa| < 1e-8
 //   [4], [5] (bits) sum mod 2^64 and XOR of key_hash(a) over those keys (order-free
 //   fingerprint of P)
@@ -866,7 +965,9 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
     if (lds_vt)
         for (int t = threadIdx.x; t < No + No * (No - 1) / 2; t += blockDim.x) vt_s[t] = vt[t];
     __syncthreads();
-    volatile int *lost = &s_lost;
+    // s_lost and s_fill are read while other waves update them: relaxed LDS atomics (a
+    // volatile pointer would become a generic one, whose loads wait for every load in flight)
+    auto set_lost = [&]() { __hip_atomic_store(&s_lost, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
     // members of S that hash into this sub-bucket: in the table, marked
     const int64_t q0 = soffs[blockIdx.x], q1 = blockIdx.x + 1 < nsb ? soffs[blockIdx.x + 1] : n_s;
     for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
@@ -874,7 +975,7 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
         const int s = red_insert<PACKED>(ka_t, kb_t, skeys[2 * q], skeys[2 * q + 1], claimed);
         if (claimed) atomicAdd(&s_fill, 1);
         if (s < 0)
-            *lost = 1;
+            set_lost();
         else
             atomicOr(&in_s[s >> 5], 1u << (s & 31));
     }
@@ -895,33 +996,36 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
     // prefetch.  Singles go to the LDS queue; if it fills up they are all redone by a
     // rescan instead.
     if (s1 > s0) {
-        const int64_t base = s0 + threadIdx.x;
-        auto ld_desc = [&](int64_t k) { return desc[min(base + k * step, s1 - 1)]; };
+        // in-bucket offsets in 32 bits (a sub-bucket holds far fewer than 2^31 pairs)
+        const uint64_t *dsb = desc + s0;
+        const int nsub = (int)(s1 - s0), base = (int)threadIdx.x, stp = (int)step;
+        auto ld_desc = [&](int k) { return dsb[min(base + k * stp, nsub - 1)]; };
         uint64_t D0 = ld_desc(0), D1 = ld_desc(1), D2 = ld_desc(2), D3 = ld_desc(3);
         SrcRec R0 = load_src<PACKED>(rec, D0), R1{};
         // pair k: descriptor Dk, record Rk; loads the record of pair k + 1 (from Dn) into
         // Rn and the descriptor of pair k + 4 into Dk
-        auto stage = [&](int64_t k, uint64_t &Dk, const SrcRec &Rk, const uint64_t &Dn, SrcRec &Rn) {
+        auto stage = [&](int k, uint64_t &Dk, const SrcRec &Rk, const uint64_t &Dn, SrcRec &Rn) {
             const uint64_t d = Dk;
             const PairVal pv = double_value<PACKED>(H, Rk, d);
             Rn = load_src<PACKED>(rec, Dn);
             Dk = ld_desc(k + 4);
             bool claimed = false;
-            if (base + k * step < s1) {
+            if (base + k * stp < nsub) {
                 if (is_single(d)) {
                     const int q = atomicAdd(&nsq, 1);
                     if (q < kRedSingles) sq[q] = d;
                 } else if (!red_add<PACKED>(pv, ka_t, kb_t, w_hi, w_lo, fq, hb_thr, hb_ok, claimed)) {
-                    *lost = 1;
+                    set_lost();
                 }
             }
             // the wave's newly claimed slots, one atomic (no return value)
             const uint64_t m = __ballot(claimed);
             if (m && (int)(threadIdx.x % kWave) == __ffsll((unsigned long long)m) - 1) atomicAdd(&s_fill, __popcll(m));
         };
-        volatile int *fillp = &s_fill;
-        for (int64_t k = 0; base + k * step < s1; k += 4) {
-            if (*lost | (*fillp > kRedFillMax)) break;  // per wave; the workgroup leaves together below
+        for (int k = 0; base + k * stp < nsub; k += 4) {
+            const int lost_now = __hip_atomic_load(&s_lost, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const int fill_now = __hip_atomic_load(&s_fill, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (lost_now | (fill_now > kRedFillMax)) break;  // per wave; the workgroup leaves together below
             stage(k, D0, R0, D1, R1);
             stage(k + 1, D1, R1, D2, R0);
             stage(k + 2, D2, R0, D3, R1);
@@ -948,7 +1052,7 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
             if (have && l == 0) {
                 pv.e1 += part_v;
                 bool claimed = false;
-                if (!red_add<PACKED>(pv, ka_t, kb_t, w_hi, w_lo, fq, hb_thr, hb_ok, claimed)) *lost = 1;
+                if (!red_add<PACKED>(pv, ka_t, kb_t, w_hi, w_lo, fq, hb_thr, hb_ok, claimed)) set_lost();
                 if (claimed) atomicAdd(&s_fill, 1);
             }
         }
@@ -959,7 +1063,7 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
             if (is_single(d) &&
                 !red_add<PACKED>(single_pair<PACKED>(H, load_src<PACKED>(rec, d), d), ka_t, kb_t, w_hi, w_lo, fq, hb_thr,
                                  hb_ok, claimed))
-                *lost = 1;
+                set_lost();
             if (claimed) atomicAdd(&s_fill, 1);
         }
     }
@@ -1058,19 +1162,7 @@ __global__ __launch_bounds__(kRedThreads) void k_pt2_reduce(Ham H, const uint64_
         terms[j] = t < (int)n_live ? w_t[t] : 0.0;
         if (t < (int)n_live) nterm = j + 1;
     }
-    const double sum = block_exact_sum<kPer>(terms, nterm);
-    red_block(mn, np, nt, fsum, fxor);
-    if (threadIdx.x == 0) {
-        double *o = part + (int64_t)kRedPart * blockIdx.x;
-        o[0] = sum;
-        o[1] = mn;
-        o[2] = np;
-        o[3] = nt;
-        o[4] = __longlong_as_double((long long)fsum);
-        o[5] = __longlong_as_double((long long)fxor);
-        o[6] = 0.0;
-        o[7] = 0.0;
-    }
+    red_final<kPer>(terms, nterm, mn, np, nt, fsum, fxor, part + (int64_t)kRedPart * blockIdx.x);
 }
 
 void launch_pt2_reduce(hipStream_t st, const Ham &H, const uint64_t *rec, const uint64_t *desc,
