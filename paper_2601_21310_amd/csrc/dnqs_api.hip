@@ -2244,6 +2244,24 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
                 launch_s_sub(st, conn->dets, n, sbits, packed, scnt, soffs, skeys, sidx, true, ss, slice);
                 CHECK_LAUNCH(ctx);
                 HIPCHK(ctx, hipStreamSynchronize(st));
+                // Few pairs per key leave many keys per sub-bucket: count the keys of 1024
+                // sampled sub-buckets first, and cut the key space finer before the reduce
+                // if the fullest sample comes near the tables' fill limit (the reduce's own
+                // overflow retry still covers an unsampled sub-bucket).
+                if (s2 > 0 && (1 << s2) < pt2_max_k2()) {
+                    int *maxk = nullptr;
+                    TRY(ws_t(ctx, "pt2_maxk", 1, &maxk));
+                    HIPCHK(ctx, hipMemsetAsync(maxk, 0, sizeof(int), st));
+                    launch_pt2_keycount(st, rec, desc, sb, nsb, 1024, skeys, soffs, n_s, maxk, packed);
+                    CHECK_LAUNCH(ctx);
+                    int mk = 0;
+                    HIPCHK(ctx, hipMemcpyAsync(&mk, maxk, sizeof(int), hipMemcpyDeviceToHost, st));
+                    HIPCHK(ctx, hipStreamSynchronize(st));
+                    if (mk > pt2_red_fill_max() / 10 * 9) {
+                        ++s2;
+                        continue;
+                    }
+                }
                 double *part_r = nullptr;
                 TRY(ws_t(ctx, "pt2_part_r", (size_t)nsb * pt2_red_part(), &part_r));
                 launch_pt2_init_acc(st, acc + 16);

@@ -272,6 +272,12 @@ struct PT2Chunk {
 
 int64_t pt2_l1_groups(int64_t n);
 int pt2_red_tab();
+// the largest key count (members of S included) of the sub-buckets 0, stride, 2 stride, ...
+// (stride = nsb / nsample), counted up to just past the reduce's fill limit
+void launch_pt2_keycount(hipStream_t st, const uint64_t *rec, const uint64_t *desc, const int64_t *sb, int64_t nsb,
+                         int64_t nsample, const uint64_t *skeys, const int64_t *soffs, int64_t n_s, int *maxkeys,
+                         bool packed);
+int pt2_red_fill_max();
 int pt2_red_part();
 int pt2_max_k1();
 int pt2_max_k2();

@@ -910,6 +910,86 @@ __device__ __forceinline__ double red_haa(const Ham &H, const double *vt_s, bool
     return h_diag(H, a, b);
 }
 
+// Key count of sampled sub-buckets, before the reduce: workgroup i inserts the keys of
+// sub-bucket i * stride (its members of S, then every pair's target) into an LDS table
+// like the reduce's and stops once the table passes the reduce's fill limit.  *maxkeys
+// receives the largest count.  The host uses it to cut the key space finer before the
+// reduce runs, instead of after a reduce pass whose tables overflowed (few pairs per
+// key: many keys per sub-bucket).
+template <bool PACKED>
+__global__ __launch_bounds__(kRedThreads) void k_pt2_keycount(const uint64_t *__restrict__ rec,
+                                                              const uint64_t *__restrict__ desc,
+                                                              const int64_t *__restrict__ sb, int64_t nsb,
+                                                              int64_t stride, const uint64_t *__restrict__ skeys,
+                                                              const int64_t *__restrict__ soffs, int64_t n_s,
+                                                              int *__restrict__ maxkeys) {
+    __shared__ unsigned long long ka_t[kRedTab];
+    __shared__ unsigned long long kb_t[PACKED ? 1 : kRedTab];
+    __shared__ int s_fill;
+    const int64_t i = (int64_t)blockIdx.x * stride;
+    if (i >= nsb) return;
+    for (int t = threadIdx.x; t < kRedTab; t += blockDim.x) {
+        ka_t[t] = kEmptyKey;
+        if (!PACKED) kb_t[t] = kEmptyKey;
+    }
+    if (threadIdx.x == 0) s_fill = 0;
+    __syncthreads();
+    const int lane = (int)(threadIdx.x % kWave);
+    auto count = [&](bool claimed) {
+        const uint64_t m = __ballot(claimed);
+        if (m && lane == __ffsll((unsigned long long)m) - 1) atomicAdd(&s_fill, __popcll(m));
+    };
+    const int64_t q0 = soffs[i], q1 = i + 1 < nsb ? soffs[i + 1] : n_s;
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+        bool claimed = false;
+        (void)red_insert<PACKED>(ka_t, kb_t, skeys[2 * q], skeys[2 * q + 1], claimed);
+        count(claimed);
+    }
+    __syncthreads();
+    const int64_t s0 = sb[i], s1 = sb[i + 1];
+    for (int64_t k0 = s0; k0 < s1; k0 += blockDim.x) {
+        if (__hip_atomic_load(&s_fill, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) > kRedFillMax) break;
+        const int64_t k = k0 + threadIdx.x;
+        bool claimed = false;
+        if (k < s1) {
+            // the target: x with the descriptor's positions flipped (alpha p, beta 64 + p)
+            const uint64_t d = desc[k];
+            const SrcRec sr = load_src<PACKED>(rec, d);
+            uint64_t a = src_alpha(sr), b = src_beta(sr);
+            const uint32_t pos = desc_pos(d);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t p = (pos >> (7 * u)) & 127u;
+                if (p == kNoPos) continue;
+                if (p < 64)
+                    a ^= 1ull << p;
+                else
+                    b ^= 1ull << (p - 64);
+            }
+            (void)red_insert<PACKED>(ka_t, kb_t, a, b, claimed);
+        }
+        count(claimed);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(maxkeys, s_fill);
+}
+
+void launch_pt2_keycount(hipStream_t st, const uint64_t *rec, const uint64_t *desc, const int64_t *sb, int64_t nsb,
+                         int64_t nsample, const uint64_t *skeys, const int64_t *soffs, int64_t n_s, int *maxkeys,
+                         bool packed) {
+    if (nsb <= 0 || nsample <= 0) return;
+    const int64_t stride = std::max<int64_t>(1, nsb / nsample);
+    const int64_t nwg = (nsb + stride - 1) / stride;
+    if (packed)
+        hipLaunchKernelGGL(k_pt2_keycount<true>, dim3((unsigned)nwg), dim3(kRedThreads), 0, st, rec, desc, sb, nsb,
+                           stride, skeys, soffs, n_s, maxkeys);
+    else
+        hipLaunchKernelGGL(k_pt2_keycount<false>, dim3((unsigned)nwg), dim3(kRedThreads), 0, st, rec, desc, sb, nsb,
+                           stride, skeys, soffs, n_s, maxkeys);
+}
+
+int pt2_red_fill_max() { return kRedFillMax; }
+
 // Per sub-bucket output part[kRedPart * sub-bucket]:
 //   [0] external sum over its keys of P (exact workgroup sum, see red_final)
 //   [1] min |E - H_aa| over those keys      [2] their number     [3] those with |E - H_aa| < 1e-8
