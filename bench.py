@@ -317,8 +317,8 @@ def bench_curve(args, dnqs, synth, torch):
 # source they were taken on (profiles/pt2_hss_m28_s1e5_hbm_counters.md).
 MEASURED_TRAFFIC = {
     ("k_pt2_reduce", "m28_7a7b_s100k"): ("paper_2601_21310_amd/csrc/k_pt2_reduce.hip",
-                                          "4aa6d4a90f927bf11696c053b51e103667da6452703bf1a2e472704254a7f565",
-                                          24921647936.0),
+                                          "d6c838336acef5560292a95e7a7a5fc4e809190c38a5409cfa1df87c5a8aa6bc",
+                                          24907113760.0),
 }
 
 

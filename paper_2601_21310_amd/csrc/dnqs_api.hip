@@ -2246,9 +2246,10 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
                 HIPCHK(ctx, hipStreamSynchronize(st));
                 // Few pairs per key leave many keys per sub-bucket: count the keys of 1024
                 // sampled sub-buckets first, and cut the key space finer before the reduce
-                // if the fullest sample comes near the tables' fill limit (the reduce's own
-                // overflow retry still covers an unsampled sub-bucket).
-                if (s2 > 0 && (1 << s2) < pt2_max_k2()) {
+                // if the fullest sample comes near the tables' fill limit: more sub-buckets,
+                // or, at the largest sub-bucket count, more key-space slices (the reduce's
+                // own overflow retry still covers an unsampled sub-bucket).
+                if (s2 > 0) {
                     int *maxk = nullptr;
                     TRY(ws_t(ctx, "pt2_maxk", 1, &maxk));
                     HIPCHK(ctx, hipMemsetAsync(maxk, 0, sizeof(int), st));
@@ -2258,8 +2259,12 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
                     HIPCHK(ctx, hipMemcpyAsync(&mk, maxk, sizeof(int), hipMemcpyDeviceToHost, st));
                     HIPCHK(ctx, hipStreamSynchronize(st));
                     if (mk > pt2_red_fill_max() / 10 * 9) {
-                        ++s2;
-                        continue;
+                        if ((1 << s2) < pt2_max_k2()) {
+                            ++s2;
+                            continue;
+                        }
+                        more_slices = true;
+                        break;
                     }
                 }
                 double *part_r = nullptr;
