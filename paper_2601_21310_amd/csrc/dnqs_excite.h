@@ -12,6 +12,15 @@ namespace dnqs {
 
 constexpr uint32_t kNoPos = 127u;
 
+// a * b for a, b < 2^24 with a product below 2^32, as v_mul_u32_u24 (full rate; a 32-bit
+// integer multiply issues at a quarter of the rate), written out so that the compiler
+// keeps it
+__device__ __forceinline__ int mul24(int a, int b) {
+    int p;
+    asm("v_mul_u32_u24 %0, %1, %2" : "=v"(p) : "v"(a), "v"(b));
+    return p;
+}
+
 // n / d and n % d for 0 <= n, d < 2^24: a float-reciprocal estimate (off by at most a
 // few) corrected to the exact quotient with integer arithmetic.
 struct FastDiv {
@@ -23,7 +32,7 @@ __device__ __forceinline__ FastDiv make_fastdiv(int d) { return FastDiv{d, 1.0f 
 
 __device__ __forceinline__ int fdiv(int n, const FastDiv &f, int &rem) {
     int q = (int)((float)n * f.r);
-    int r = n - q * f.d;
+    int r = n - mul24(q, f.d);  // q d <= n + a few d < 2^25
     while (r < 0) {
         --q;
         r += f.d;
@@ -46,10 +55,10 @@ struct ExcLists {
 // pair index t over n items (i < j), ordered by j then i: t = j(j-1)/2 + i
 __device__ __forceinline__ void unrank_pair(int t, int &i, int &j) {
     int jj = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)t)) * 0.5f);
-    while (jj * (jj - 1) / 2 > t) --jj;
-    while ((jj + 1) * jj / 2 <= t) ++jj;
+    while (mul24(jj, jj - 1) / 2 > t) --jj;  // jj < 2^13
+    while (mul24(jj + 1, jj) / 2 <= t) ++jj;
     j = jj;
-    i = t - jj * (jj - 1) / 2;
+    i = t - mul24(jj, jj - 1) / 2;
 }
 
 // Fill lists[4][64] for det (xa, xb) with one wavefront (lanes 0..M-1 take part).
