@@ -128,3 +128,25 @@ def test_large_pt2_sampled_keys(dnqs, ctx):
     for a, b in keys[:50]:
         assert not np.any((p.dets[:, 0] == a) & (p.dets[:, 1] == b)), "exported key lies in S"
     print(f"  {k} sampled keys, max |dw| {np.max(np.abs(w_g - w_o)):.2e}; pairs {out['counts'][0].item()}")
+
+
+def test_large_pt2_slicing_and_reproducibility(dnqs, ctx):
+    """128-bit keys (6e8 pairs, 2.4e8 keys of P, 1.3e5 sub-buckets): two calls give the
+    same bits, and a run cut into key-space slices (16 MiB descriptor budget) has the
+    same pair count, |P| and fingerprint, and the same sums up to FP64 summation order."""
+    print("[m56] pt2 slicing / reproducibility", flush=True)
+    p = prob(1.0)
+    dets, theta = _gpu(dnqs, ctx, p)
+    conn = ctx.build_connections(dets)
+    r = ctx.energy_and_grad(p.wl.widths, theta, conn, want_grad=False)
+    a = ctx.pt2(conn, r["logabs"], r["sign"], r["E"])
+    b = ctx.pt2(conn, r["logabs"], r["sign"], r["E"])
+    assert torch.equal(a["out"].view(torch.int64), b["out"].view(torch.int64))
+    assert torch.equal(a["counts"], b["counts"])
+    s = ctx.pt2(conn, r["logabs"], r["sign"], r["E"], max_pair_bytes=1 << 24)
+    ca, cs = a["counts"].cpu().numpy(), s["counts"].cpu().numpy()
+    assert ca[0] == cs[0] and ca[1] == cs[1] and ca[4] == cs[4] and ca[5] == cs[5]
+    oa, os_ = a["out"].cpu().numpy(), s["out"].cpu().numpy()
+    assert abs(oa[1] - os_[1]) <= 1e-12 * max(1.0, abs(oa[1]))
+    assert abs(oa[2] - os_[2]) <= 1e-12 * max(1.0, abs(oa[2]))
+    print(f"  |P| {ca[1]}, sub-buckets {ca[3]} (sliced run {cs[3]}), external {oa[2]:.12e} / {os_[2]:.12e}")
