@@ -37,7 +37,8 @@
  * Errors
  *   Every call returns a dnqs_status.  Arguments are validated on the host before
  *   any launch; on a non-zero status nothing was enqueued by that call unless the
- *   status is DNQS_EHIP.  dnqs_last_error() gives a message for the last failure on
+ *   status is DNQS_EHIP or DNQS_EDOMAIN (the latter found from device results by the
+ *   synchronising calls dnqs_lanczos and dnqs_pt2).  dnqs_last_error() gives a message for the last failure on
  *   a context.  No C++ exception crosses this boundary.
  */
 #ifndef DNQS_H
@@ -60,7 +61,7 @@ typedef enum {
     DNQS_EHIP = -3,      /* a HIP runtime call failed */
     DNQS_ECAPACITY = -4, /* a fixed-capacity structure would overflow */
     DNQS_ESTATE = -5,    /* call out of order (e.g. no integrals in the slot) */
-    DNQS_EDOMAIN = -6    /* numerical domain error (psi^T psi == 0) */
+    DNQS_EDOMAIN = -6    /* numerical domain error: psi^T psi or a start vector's norm is 0 or not finite */
 } dnqs_status;
 
 /* Arithmetic of the network GEMMs.  Activations, weights and gradients are FP32 in
@@ -259,7 +260,9 @@ dnqs_status dnqs_energy_and_grad(dnqs_ctx *ctx, int slot, const dnqs_net *net, c
  * spread).  Stops when the Ritz residual |H y - lambda y| <= tol max(1, |lambda|), at
  * max_iter (1..4096) vectors or on an invariant subspace.  energy: dev FP64[1]; vec:
  * dev FP64[n] unit Ritz vector (NULL: not formed); iters, residual: host (NULL: not
- * returned).  Holds (max_iter + 1) n FP64 values of workspace.  Synchronises the stream. */
+ * returned).  Holds (max_iter + 1) n FP64 values of workspace.  DNQS_EDOMAIN if the
+ * start vector's norm is 0 or not finite (energy and vec untouched).  Synchronises the
+ * stream. */
 dnqs_status dnqs_lanczos(dnqs_ctx *ctx, const dnqs_conn *conn, int max_iter, double tol, const double *start,
                          double *energy, double *vec, int *iters, double *residual);
 
@@ -299,7 +302,9 @@ dnqs_status dnqs_lanczos(dnqs_ctx *ctx, const dnqs_conn *conn, int max_iter, dou
  * at the call), the key space is cut into 2^k slices by the top k bits of the key hash
  * and processed one slice after the other (S re-enumerated for each), so that any |S|
  * fits; the result does not depend on the slicing beyond FP64 summation order.
- * counts[3] then sums the sub-buckets over slices.  Synchronises the stream. */
+ * counts[3] then sums the sub-buckets over slices.  DNQS_EDOMAIN, before the sums and
+ * with out and counts untouched, if log_abs has no finite maximum (psi^T psi after
+ * scaling is 0 or not finite).  Synchronises the stream. */
 typedef struct {
     uint64_t sample_mask;
     int64_t export_cap;

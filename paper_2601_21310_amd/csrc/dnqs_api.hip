@@ -1864,6 +1864,14 @@ dnqs_status dnqs_lanczos(dnqs_ctx *ctx, const dnqs_conn *conn, int max_iter, dou
     else
         launch_lz_start(st, conn->diag, n, sc, w);
     launch_lz_norm(st, w, n, part, sc);
+    CHECK_LAUNCH(ctx);
+    {
+        double nrm = 0.0;
+        HIPCHK(ctx, hipMemcpyAsync(&nrm, sc, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));
+        if (!(nrm > 0.0) || !std::isfinite(nrm))
+            return fail(ctx, DNQS_EDOMAIN, "lanczos: the start vector has norm %g", nrm);
+    }
     launch_lz_scale(st, w, n, sc, V);
     CHECK_LAUNCH(ctx);
     std::vector<double> a, b, y;
@@ -2016,6 +2024,15 @@ dnqs_status dnqs_pt2(dnqs_ctx *ctx, int slot, const dnqs_conn *conn, const doubl
     launch_scale_psi(st, log_abs, sign, n, part, stats + 1, psi);
     launch_spmv_energy(st, conn->row_ptr, conn->col, conn->val, conn->diag, psi, n, v, part, part2, stats, e_tmp);
     CHECK_LAUNCH(ctx);
+    {
+        // the sums are divided by psi^T psi: no finite log_abs (every amplitude zero), or a
+        // +inf or NaN one, leaves nothing to normalise
+        double pp = 0.0;
+        HIPCHK(ctx, hipMemcpyAsync(&pp, stats, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));
+        if (!(pp > 0.0) || !std::isfinite(pp))
+            return fail(ctx, DNQS_EDOMAIN, "pt2: psi^T psi = %g after scaling (log_abs has no finite maximum)", pp);
+    }
     double *acc = nullptr;  // 8-double records: [internal | external total | current slice attempt]
     TRY(ws_t(ctx, "pt2_acc", 24, &acc));
     launch_pt2_init_acc(st, acc + 8);

@@ -150,3 +150,19 @@ def test_large_pt2_slicing_and_reproducibility(dnqs, ctx):
     assert abs(oa[1] - os_[1]) <= 1e-12 * max(1.0, abs(oa[1]))
     assert abs(oa[2] - os_[2]) <= 1e-12 * max(1.0, abs(oa[2]))
     print(f"  |P| {ca[1]}, sub-buckets {ca[3]} (sliced run {cs[3]}), external {oa[2]:.12e} / {os_[2]:.12e}")
+
+
+def test_large_candidates_capacity(dnqs, ctx):
+    """Every (x, a) candidate of the screened set is held once, so |S| n_exc >= 2^31 is
+    refused before any launch (n_exc = 404712 at M = 56, 12 + 12 electrons: 6000
+    determinants are past the limit)."""
+    print("[m56] candidate capacity", flush=True)
+    p = synth.make_problem(synth.WORKLOADS[NAME], n_dets=6000)
+    dets, theta = _gpu(dnqs, ctx, p)
+    conn = ctx.build_connections(dets)
+    r = ctx.energy_and_grad(p.wl.widths, theta, conn, want_grad=False)
+    with pytest.raises(dnqs.DnqsError, match="ECAPACITY"):
+        ctx.heatbath_candidates(conn, r["logabs"], r["sign"], 1e-3)
+    # the context stays usable: PT2 on the same set (which streams its pairs) still runs
+    out = ctx.pt2(conn, r["logabs"], r["sign"], r["E"])
+    assert out["counts"][0].item() == 6000 * 404712

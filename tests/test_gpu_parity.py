@@ -235,6 +235,37 @@ def test_invalid_inputs_rejected(dnqs, ctx):
         ctx.build_connections(dnqs.dets_to_device(p.dets), slot=5)
 
 
+def test_domain_errors_rejected(dnqs, ctx):
+    """psi = 0 (no finite log|psi|) has no normalised PT2, a zero start vector no Krylov
+    space: both are refused, outputs untouched, and the context stays usable."""
+    p, dets, theta = _setup(dnqs, ctx, "m8_4a4b_full")
+    conn = ctx.build_connections(dets)
+    res = ctx.energy_and_grad(p.wl.widths, theta, conn, want_grad=False)
+    zero = torch.full((conn.n,), float("-inf"), dtype=torch.float64, device="cuda")
+    with pytest.raises(dnqs.DnqsError, match="EDOMAIN"):
+        ctx.pt2(conn, zero, res["sign"], res["E"])
+    with pytest.raises(dnqs.DnqsError, match="EDOMAIN"):
+        ctx.lanczos(conn, start=torch.zeros(conn.n, dtype=torch.float64, device="cuda"))
+    nan = torch.full((conn.n,), float("nan"), dtype=torch.float64, device="cuda")
+    with pytest.raises(dnqs.DnqsError, match="EDOMAIN"):
+        ctx.lanczos(conn, start=nan)
+    # the context stays usable: the same calls with valid inputs give the oracle's numbers
+    rp, col, val, diag = P.oracle_hss("m8_4a4b_full")
+    E0 = np.linalg.eigvalsh(np.diag(diag) + _dense(rp, col, val, len(diag)))[0]
+    lz = ctx.lanczos(conn, max_iter=400, tol=1e-10, want_vec=False)
+    assert abs(lz["E"].item() - E0) <= 2.0 ** -24 * np.linalg.norm(val) + 1e-9 * max(1.0, abs(E0))
+    o = P.oracle_pt2("m8_4a4b_full")
+    out = ctx.pt2(conn, res["logabs"], res["sign"], res["E"])
+    assert out["counts"][1].item() == o["stats"]["n_p"]
+
+
+def _dense(rp, col, val, m):
+    a = np.zeros((m, m))
+    for r in range(m):
+        a[r, col[rp[r]:rp[r + 1]]] = val[rp[r]:rp[r + 1]]
+    return a
+
+
 # ------------------------------------------------------------------ mixed precision
 # Split-BF16 GEMMs carry a relative error near 2^-16 per product (operands split into
 # two BF16 parts, the lo*lo term dropped) against 2^-24 for FP32; the bars below are the
