@@ -6,8 +6,10 @@ the library is not built, or no gfx950 GPU is present, calls raise.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 import torch
@@ -69,6 +71,27 @@ ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
+# connection sets, graphs and contexts still open when the interpreter exits are freed
+# (in that order) while torch, whose caching allocator takes back their device memory,
+# is still alive
+_open_objects = weakref.WeakSet()
+_open_contexts = weakref.WeakSet()
+
+
+@atexit.register
+def _close_open_contexts():
+    for o in list(_open_objects):
+        try:
+            o.free()
+        except Exception:
+            pass
+    for c in list(_open_contexts):
+        try:
+            c.close()
+        except Exception:
+            pass
+
+
 class TorchAllocator:
     """Device memory for the library from torch's caching allocator, on the context's
     stream (torch stays the only owner of device memory).  Counts calls and live bytes."""
@@ -76,6 +99,7 @@ class TorchAllocator:
     def __init__(self, device: int, stream: int):
         self.device = device
         self.stream = stream
+        self._delete = torch.cuda.caching_allocator_delete
         self.n_alloc = 0
         self.n_release = 0
         self.live = {}
@@ -92,7 +116,7 @@ class TorchAllocator:
     def release(self, p: int):
         self.n_release += 1
         self.live.pop(p, None)
-        torch.cuda.caching_allocator_delete(p)
+        self._delete(p)
 
     @property
     def live_bytes(self):
@@ -182,6 +206,7 @@ class Connections:
     def __init__(self, ctx, handle, slot, dets):
         self._ctx = ctx
         self.handle = handle
+        _open_objects.add(self)
         self.slot = slot
         self.dets = dets
         n, nnz = C.c_int64(), C.c_int64()
@@ -279,6 +304,7 @@ class Context:
         self.handle = h
         self.stream = stream
         self._slots = {}
+        _open_contexts.add(self)
 
     def _check(self, st):
         if st != 0:
@@ -523,6 +549,7 @@ class Graph:
     def __init__(self, ctx, handle):
         self._ctx = ctx
         self.handle = handle
+        _open_objects.add(self)
 
     def launch(self):
         self._ctx._check(lib().dnqs_graph_launch(self._ctx.handle, self.handle))

@@ -65,12 +65,14 @@ __global__ __launch_bounds__(kLzBlock) void k_lz_orth(const double *__restrict__
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// out[0] = sqrt(sum of nb partials) (fixed order)
-__global__ void k_lz_norm(const double *__restrict__ part, int nb, double *__restrict__ out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// out[0] = sqrt(sum of nb partials): each thread sums a fixed strided share, then the
+// block sum in a fixed order (one workgroup; the same bits on every call)
+__global__ __launch_bounds__(kLzBlock) void k_lz_norm(const double *__restrict__ part, int nb,
+                                                      double *__restrict__ out) {
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[b];
-    out[0] = sqrt(s);
+    for (int b = threadIdx.x; b < nb; b += kLzBlock) s += part[b];
+    s = lz_block_sum(s);
+    if (threadIdx.x == 0) out[0] = sqrt(s);
 }
 
 // dst[i] = src[i] / nrm[0]
@@ -134,7 +136,7 @@ void launch_lz_orth(hipStream_t st, const double *V, int64_t ldv, int m, const d
                     double *part, double *nrm) {
     const unsigned g = lz_grid(n);
     hipLaunchKernelGGL(k_lz_orth, dim3(g), dim3(kLzBlock), 0, st, V, ldv, m, c, w, n, part);
-    hipLaunchKernelGGL(k_lz_norm, dim3(1), dim3(64), 0, st, part, (int)g, nrm);
+    hipLaunchKernelGGL(k_lz_norm, dim3(1), dim3(kLzBlock), 0, st, part, (int)g, nrm);
 }
 
 void launch_lz_norm(hipStream_t st, const double *w, int64_t n, double *part, double *nrm) {
@@ -142,7 +144,7 @@ void launch_lz_norm(hipStream_t st, const double *w, int64_t n, double *part, do
     const unsigned g = lz_grid(n);
     hipLaunchKernelGGL(k_lz_orth, dim3(g), dim3(kLzBlock), 0, st, w, n, 0, (const double *)nullptr,
                        const_cast<double *>(w), n, part);
-    hipLaunchKernelGGL(k_lz_norm, dim3(1), dim3(64), 0, st, part, (int)g, nrm);
+    hipLaunchKernelGGL(k_lz_norm, dim3(1), dim3(kLzBlock), 0, st, part, (int)g, nrm);
 }
 
 void launch_lz_scale(hipStream_t st, const double *src, int64_t n, const double *nrm, double *dst) {
