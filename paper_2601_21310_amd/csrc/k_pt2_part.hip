@@ -35,7 +35,24 @@
 
 namespace dnqs {
 
-int64_t pt2_l1_groups(int64_t n) { return (n + kL1XPerGroup - 1) / kL1XPerGroup; }
+// Determinants per L1 workgroup (at most kL1XPerGroup).  A workgroup's LDS fills a CU, so
+// the groups run in waves of one per CU; the group size is chosen so that the last wave
+// is (nearly) full rather than a few groups running alone on an idle chip.
+int pt2_l1_xper(int64_t n) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    const int64_t per_wave = (int64_t)kL1XPerGroup * cus;
+    const int64_t waves = std::max<int64_t>(1, (n + per_wave - 1) / per_wave);
+    const int64_t xper = (n + waves * cus - 1) / (waves * cus);
+    return (int)std::min<int64_t>(std::max<int64_t>(xper, 1), kL1XPerGroup);
+}
+
+int64_t pt2_l1_groups(int64_t n) {
+    const int xper = pt2_l1_xper(n);
+    return (n + xper - 1) / xper;
+}
 int pt2_max_dets() { return 1 << kDescXBits; }
 
 // ------------------------------------------------------------------ block scan
@@ -68,7 +85,7 @@ __device__ inline void block_exclusive_scan(const uint32_t *cnt, uint32_t *out, 
 }
 
 // ------------------------------------------------------------------ L1
-// One 1024-thread workgroup per kL1XPerGroup determinants.  The workgroup's pairs are
+// One 1024-thread workgroup per xper (<= kL1XPerGroup) determinants.  The workgroup's pairs are
 // numbered q = (determinant in the group) * n_exc + excitation and produced in rounds of
 // kL1Round (8 per thread).  Count pass (FILL = false): per-bucket totals of the group.
 // Fill pass: each round is sorted by bucket in LDS (histogram with ranks, scan, place)
@@ -79,7 +96,7 @@ __device__ inline void block_exclusive_scan(const uint32_t *cnt, uint32_t *out, 
 // and the bucket bits are taken from the hash shifted past the slice bits.
 template <bool FILL, bool PACKED>
 __global__ __launch_bounds__(kL1Threads) void k_pt2_l1(Ham H, const uint64_t *__restrict__ dets, int64_t n,
-                                                       const double *__restrict__ psi, int s1, int64_t nwg,
+                                                       const double *__restrict__ psi, int s1, int xper, int64_t nwg,
                                                        uint32_t *__restrict__ counts, const int64_t *__restrict__ offs,
                                                        uint64_t *__restrict__ desc, int ss, uint32_t slice,
                                                        unsigned long long *__restrict__ cur1, int64_t cap1,
@@ -98,8 +115,8 @@ __global__ __launch_bounds__(kL1Threads) void k_pt2_l1(Ham H, const uint64_t *__
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const int64_t wg = blockIdx.x;
     constexpr int kWavesL1 = kL1Threads / kWave;
-    for (int xl = wave; xl < kL1XPerGroup; xl += kWavesL1) {
-        const int64_t x = wg * kL1XPerGroup + xl;
+    for (int xl = wave; xl < xper; xl += kWavesL1) {
+        const int64_t x = wg * xper + xl;
         const bool live = x < n && psi[x] != 0.0;
         const uint64_t xa = live ? dets[2 * x] : 0ull, xb = live ? dets[2 * x + 1] : 0ull;
         wave_build_lists(lists[xl], H.M, xa, xb);
@@ -119,7 +136,7 @@ __global__ __launch_bounds__(kL1Threads) void k_pt2_l1(Ham H, const uint64_t *__
     __syncthreads();
     const ExcLists proto = make_exc_lists(lists[0], H.M, H.na, H.nb);  // class sizes: the same for every det
     const int T = proto.total;
-    const int64_t total = (int64_t)kL1XPerGroup * T;
+    const int64_t total = (int64_t)xper * T;
     for (int64_t r0 = 0; r0 < total; r0 += kL1Round) {
         uint64_t d[kL1Round / kL1Threads];
         uint32_t bk[kL1Round / kL1Threads], rk[kL1Round / kL1Threads];
@@ -144,7 +161,7 @@ __global__ __launch_bounds__(kL1Threads) void k_pt2_l1(Ham H, const uint64_t *__
                 if (ss) h <<= ss;
                 if (in_slice) {
                     bk[j] = l1_bucket(h, s1);
-                    d[j] = make_desc(wg * kL1XPerGroup + xl, pos, h, s1);
+                    d[j] = make_desc(wg * xper + xl, pos, h, s1);
                 }
             }
             rk[j] = atomicAdd(&hist[bk[j]], 1u);
@@ -211,20 +228,21 @@ void launch_pt2_l1(hipStream_t st, const Ham &H, const uint64_t *dets, int64_t n
                    int64_t nwg, uint32_t *counts, const int64_t *offs, uint64_t *desc, bool fill, bool packed, int ss,
                    uint32_t slice, uint64_t *cur1, int64_t cap1, int *ovf) {
     dim3 grid((unsigned)nwg), blk(kL1Threads);
+    const int xper = pt2_l1_xper(n);  // nwg = pt2_l1_groups(n) comes from the same choice
     unsigned long long *c1 = reinterpret_cast<unsigned long long *>(cur1);
     if (fill) {
         if (packed)
-            hipLaunchKernelGGL((k_pt2_l1<true, true>), grid, blk, 0, st, H, dets, n, psi, s1, nwg, counts, offs, desc,
+            hipLaunchKernelGGL((k_pt2_l1<true, true>), grid, blk, 0, st, H, dets, n, psi, s1, xper, nwg, counts, offs, desc,
                                ss, slice, c1, cap1, ovf);
         else
-            hipLaunchKernelGGL((k_pt2_l1<true, false>), grid, blk, 0, st, H, dets, n, psi, s1, nwg, counts, offs, desc,
+            hipLaunchKernelGGL((k_pt2_l1<true, false>), grid, blk, 0, st, H, dets, n, psi, s1, xper, nwg, counts, offs, desc,
                                ss, slice, c1, cap1, ovf);
     } else {
         if (packed)
-            hipLaunchKernelGGL((k_pt2_l1<false, true>), grid, blk, 0, st, H, dets, n, psi, s1, nwg, counts, offs,
+            hipLaunchKernelGGL((k_pt2_l1<false, true>), grid, blk, 0, st, H, dets, n, psi, s1, xper, nwg, counts, offs,
                                desc, ss, slice, c1, cap1, ovf);
         else
-            hipLaunchKernelGGL((k_pt2_l1<false, false>), grid, blk, 0, st, H, dets, n, psi, s1, nwg, counts, offs,
+            hipLaunchKernelGGL((k_pt2_l1<false, false>), grid, blk, 0, st, H, dets, n, psi, s1, xper, nwg, counts, offs,
                                desc, ss, slice, c1, cap1, ovf);
     }
 }
